@@ -1,0 +1,184 @@
+"""ctypes wrapper of the FP64 CPU oracle (``libblink_ref.so``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the package smoke check and the
+benchmark's CPU-baseline leg. The product path never imports this module.
+Arguments are NumPy arrays on the host; see ``blink_ref.h`` for definitions.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libblink_ref.so")
+SRC = os.path.join(HERE, "blink_ref.c")
+
+_lib = None
+
+
+def compile_library(src: str, out: str) -> str:
+    """gcc -O2 -fopenmp -ffp-contract=off (no fast-math) of one oracle source into a shared object."""
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-D_GNU_SOURCE", "-fPIC", "-shared", "-Wall", "-Wextra", "-I", HERE, "-o", tmp, src,
+           "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = True) -> str:
+    """Compile libblink_ref.so next to its source."""
+    if force or not os.path.exists(LIB_PATH):
+        compile_library(SRC, LIB_PATH)
+    return LIB_PATH
+
+
+def load(path: str):
+    """Load an oracle shared object and declare its signatures."""
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, f64 = ctypes.c_int, ctypes.c_double
+    L.blink_ref_cells_per_metre.restype = f64
+    L.blink_ref_cells_per_metre.argtypes = [f64, i32, f64]
+    L.blink_ref_grid.restype = i32
+    L.blink_ref_grid.argtypes = [P, P, P, i32, i32, f64, i32, f64, i32, P, P, P, P, P]
+    L.blink_ref_ifft1d.restype = i32
+    L.blink_ref_ifft1d.argtypes = [P, i32]
+    L.blink_ref_ifft2d.restype = i32
+    L.blink_ref_ifft2d.argtypes = [P, i32, f64, i32, P, P]
+    L.blink_ref_image_batch.restype = i32
+    L.blink_ref_image_batch.argtypes = [P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32,
+                                        P, P, P, P, P, i32]
+    L.blink_ref_max_threads.restype = i32
+    L.blink_ref_max_threads.argtypes = []
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build(force=False)
+        _lib = load(LIB_PATH)
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Oracle:
+    """The oracle's entry points bound to one loaded copy of the library."""
+
+    def __init__(self, L):
+        self.L = L
+
+    def cells_per_metre(self, freq_hz: float, grid_n: int, pixel_scale: float) -> float:
+        return self.L.blink_ref_cells_per_metre(float(freq_hz), int(grid_n), float(pixel_scale))
+
+    def grid(self, vis, flags, uvw, freq_hz, grid_n, pixel_scale, weighting=0):
+        """Grid one (t,c): vis complex [P][B] (or [B]), flags [B] or None, uvw [B][3].
+
+        Returns dict(grid complex128 [P][N][N], counts int32 [N][N], cell_idx int32 [B],
+        weight_sum float, n_out int)."""
+        vis = np.asarray(vis)
+        if vis.ndim == 1:
+            vis = vis[None]
+        P, B = vis.shape
+        v = _c(vis, np.complex64)
+        f = None if flags is None else _c(flags, np.uint8)
+        u = _c(uvw, np.float64)
+        N = int(grid_n)
+        g = np.empty((P, N, N), dtype=np.complex128)
+        counts = np.empty((N, N), dtype=np.int32)
+        cell = np.empty(B, dtype=np.int32)
+        W = ctypes.c_double()
+        nout = ctypes.c_int32()
+        rc = self.L.blink_ref_grid(_ptr(v), _ptr(f), _ptr(u), P, B, float(freq_hz), N, float(pixel_scale),
+                                  int(weighting), _ptr(g), _ptr(counts), _ptr(cell), ctypes.byref(W),
+                                  ctypes.byref(nout))
+        if rc != 0:
+            raise ValueError(f"blink_ref_grid failed with code {rc}")
+        return {"grid": g, "counts": counts, "cell_idx": cell, "weight_sum": W.value,
+                "n_out": nout.value}
+
+    def ifft1d(self, x):
+        a = _c(x, np.complex128).copy()
+        rc = self.L.blink_ref_ifft1d(_ptr(a), a.shape[0])
+        if rc != 0:
+            raise ValueError(f"blink_ref_ifft1d failed with code {rc}")
+        return a
+
+    def ifft2d(self, grid_, weight_sum=1.0, shift=True):
+        """Dirty image of one complex grid [N][N]. Returns (image float64 [N][N], imag_max)."""
+        g = _c(grid_, np.complex128)
+        N = g.shape[0]
+        img = np.empty((N, N), dtype=np.float64)
+        im = ctypes.c_double()
+        rc = self.L.blink_ref_ifft2d(_ptr(g), N, float(weight_sum), int(bool(shift)), _ptr(img),
+                                    ctypes.byref(im))
+        if rc != 0:
+            raise ValueError(f"blink_ref_ifft2d failed with code {rc}")
+        return img, im.value
+
+    def image_batch(self, vis, flags, uvw, freq_hz, grid_n, pixel_scale, weighting=0, shift=True,
+                    n_threads=0, want_counts=False):
+        """Whole path over vis [T][C][P][B]. Returns dict(images [T][C][P][N][N] float64,
+        weight_sum [T][C][P], n_out [T][C], cell_idx [T][C][B], counts [T][C][N][N] or None)."""
+        v = _c(vis, np.complex64)
+        T, C, P, B = v.shape
+        f = None if flags is None else _c(flags, np.uint8)
+        u = _c(uvw, np.float64)
+        fr = _c(freq_hz, np.float64)
+        N = int(grid_n)
+        images = np.empty((T, C, P, N, N), dtype=np.float64)
+        W = np.empty((T, C, P), dtype=np.float64)
+        nout = np.empty((T, C), dtype=np.int32)
+        cell = np.empty((T, C, B), dtype=np.int32)
+        counts = np.empty((T, C, N, N), dtype=np.int32) if want_counts else None
+        rc = self.L.blink_ref_image_batch(_ptr(v), _ptr(f), _ptr(u), _ptr(fr), T, C, P, B, N,
+                                         float(pixel_scale), int(weighting), int(bool(shift)),
+                                         _ptr(images), _ptr(W), _ptr(nout), _ptr(cell), _ptr(counts),
+                                         int(n_threads))
+        if rc != 0:
+            raise ValueError(f"blink_ref_image_batch failed with code {rc}")
+        return {"images": images, "weight_sum": W, "n_out": nout, "cell_idx": cell, "counts": counts}
+
+    def max_threads(self) -> int:
+        return int(self.L.blink_ref_max_threads())
+
+
+def default() -> Oracle:
+    return Oracle(lib())
+
+
+def cells_per_metre(*a, **k):
+    return default().cells_per_metre(*a, **k)
+
+
+def grid(*a, **k):
+    return default().grid(*a, **k)
+
+
+def ifft1d(*a, **k):
+    return default().ifft1d(*a, **k)
+
+
+def ifft2d(*a, **k):
+    return default().ifft2d(*a, **k)
+
+
+def image_batch(*a, **k):
+    return default().image_batch(*a, **k)
+
+
+def max_threads() -> int:
+    return default().max_threads()

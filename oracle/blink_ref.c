@@ -1,0 +1,240 @@
+/*
+ * blink_ref.c — FP64 CPU oracle for batched dirty imaging (test infrastructure only).
+ *
+ * The definitions and the readings of the paper it follows are stated in blink_ref.h.
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math).
+ */
+#include "blink_ref.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define SPEED_OF_LIGHT 299792458.0
+
+static int is_pow2(int n) { return n >= 2 && n <= 16384 && (n & (n - 1)) == 0; }
+
+static int mod_n(int a, int n) { int r = a % n; return r < 0 ? r + n : r; }
+
+/* Section 4, Eq. 5: the grid has N cells per side; with pixel scale dl the image spans N*dl in
+ * direction cosine, so a cell is 1/(N dl) wavelengths wide and u metres are u f / c wavelengths.
+ * The product is evaluated as (f / c) * (N * dl). */
+double blink_ref_cells_per_metre(double freq_hz, int grid_n, double pixel_scale)
+{
+    double cycles_per_metre = freq_hz / SPEED_OF_LIGHT;
+    double cells_per_wavelength = (double)grid_n * pixel_scale;
+    return cycles_per_metre * cells_per_wavelength;
+}
+
+/* Section 6.2.4: nearest-cell placement with no convolution kernel; natural weighting by default.
+ * Hermitian completion: the visibility of baseline (i,j) at (u,v) implies conj(V) at (-u,-v). */
+int blink_ref_grid(const float *vis, const uint8_t *flags, const double *uvw, int P, int B,
+                   double freq_hz, int grid_n, double pixel_scale, int weighting,
+                   double *grid, int32_t *counts, int32_t *cell_idx,
+                   double *weight_sum, int32_t *n_out)
+{
+    if (!is_pow2(grid_n) || P < 1 || B < 0 || !vis || !uvw || !grid || !weight_sum || !n_out)
+        return 1;
+    if (weighting != 0 && weighting != 1)
+        return 1;
+    const int N = grid_n;
+    const size_t NN = (size_t)N * N;
+    int32_t *cnt = (int32_t *)calloc(NN, sizeof(int32_t));
+    if (!cnt)
+        return 2;
+    memset(grid, 0, sizeof(double) * 2 * NN * (size_t)P);
+
+    const double k = blink_ref_cells_per_metre(freq_hz, N, pixel_scale);
+    const double half = (double)(N / 2);
+    int32_t outside = 0;
+    int64_t kept = 0;
+    for (int b = 0; b < B; ++b) {
+        if (flags && flags[b]) {
+            if (cell_idx) cell_idx[b] = -1;
+            continue;
+        }
+        double xu = uvw[3 * (size_t)b + 0] * k;   /* one IEEE double product each */
+        double xv = uvw[3 * (size_t)b + 1] * k;
+        double ru = nearbyint(xu);                /* round half to even */
+        double rv = nearbyint(xv);
+        if (!(fabs(ru) < half && fabs(rv) < half)) {
+            if (cell_idx) cell_idx[b] = -2;
+            ++outside;
+            continue;
+        }
+        int iu = (int)ru, iv = (int)rv;
+        size_t c1 = (size_t)mod_n(iv, N) * N + mod_n(iu, N);
+        size_t c2 = (size_t)mod_n(-iv, N) * N + mod_n(-iu, N);
+        if (cell_idx) cell_idx[b] = (int32_t)c1;
+        cnt[c1] += 1;
+        cnt[c2] += 1;
+        ++kept;
+        for (int p = 0; p < P; ++p) {
+            const float *v = vis + 2 * ((size_t)p * B + b);
+            double re = (double)v[0], im = (double)v[1];
+            double *g = grid + 2 * NN * (size_t)p;
+            g[2 * c1] += re;
+            g[2 * c1 + 1] += im;
+            g[2 * c2] += re;
+            g[2 * c2 + 1] -= im;
+        }
+    }
+
+    double W;
+    if (weighting == 0) {
+        W = 2.0 * (double)kept;
+    } else {
+        int64_t occupied = 0;
+        for (size_t c = 0; c < NN; ++c) {
+            if (cnt[c] == 0) continue;
+            ++occupied;
+            for (int p = 0; p < P; ++p) {
+                double *g = grid + 2 * NN * (size_t)p;
+                g[2 * c] /= (double)cnt[c];
+                g[2 * c + 1] /= (double)cnt[c];
+            }
+        }
+        W = (double)occupied;
+    }
+    if (counts) memcpy(counts, cnt, sizeof(int32_t) * NN);
+    *weight_sum = W;
+    *n_out = outside;
+    free(cnt);
+    return 0;
+}
+
+/* Textbook iterative radix-2 decimation-in-time FFT with the + sign of the inverse transform
+ * (the image side of Eq. 4's exp(-i2pi(ul+vm))). Twiddles cos/sin(2 pi j / n) from libm. */
+int blink_ref_ifft1d(double *a, int n)
+{
+    if (!is_pow2(n) && n != 1) return 1;
+    if (!a) return 1;
+    if (n == 1) return 0;
+    /* bit-reversal permutation */
+    for (int i = 1, j = 0; i < n; ++i) {
+        int bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) {
+            double tr = a[2 * i], ti = a[2 * i + 1];
+            a[2 * i] = a[2 * j]; a[2 * i + 1] = a[2 * j + 1];
+            a[2 * j] = tr; a[2 * j + 1] = ti;
+        }
+    }
+    for (int len = 2; len <= n; len <<= 1) {
+        int h = len / 2;
+        for (int k = 0; k < h; ++k) {
+            double ang = 2.0 * M_PI * (double)k / (double)len;
+            double wr = cos(ang), wi = sin(ang);
+            for (int i = 0; i < n; i += len) {
+                double *x = a + 2 * (i + k), *y = a + 2 * (i + k + h);
+                double tr = wr * y[0] - wi * y[1];
+                double ti = wr * y[1] + wi * y[0];
+                y[0] = x[0] - tr; y[1] = x[1] - ti;
+                x[0] = x[0] + tr; x[1] = x[1] + ti;
+            }
+        }
+    }
+    return 0;
+}
+
+/* Eq. 5 and Section 6.2.4: dirty image = inverse 2D FFT of the grid (rows, then columns),
+ * then the shift that moves the phase centre from the corner to the middle, then the real
+ * part, normalised by the weight sum so a 1 Jy source at the phase centre peaks at 1. */
+int blink_ref_ifft2d(const double *grid, int grid_n, double weight_sum, int shift,
+                     double *image, double *imag_max)
+{
+    if (!is_pow2(grid_n) || !grid || !image) return 1;
+    const int N = grid_n;
+    const size_t NN = (size_t)N * N;
+    if (!(weight_sum > 0.0) || !isfinite(weight_sum)) {
+        memset(image, 0, sizeof(double) * NN);
+        if (imag_max) *imag_max = 0.0;
+        return 0;
+    }
+    double *work = (double *)malloc(sizeof(double) * 2 * NN);
+    double *col = (double *)malloc(sizeof(double) * 2 * (size_t)N);
+    if (!work || !col) { free(work); free(col); return 2; }
+    memcpy(work, grid, sizeof(double) * 2 * NN);
+    for (int r = 0; r < N; ++r)                 /* along u (x) */
+        blink_ref_ifft1d(work + 2 * (size_t)r * N, N);
+    for (int c = 0; c < N; ++c) {               /* along v (y) */
+        for (int r = 0; r < N; ++r) {
+            col[2 * r] = work[2 * ((size_t)r * N + c)];
+            col[2 * r + 1] = work[2 * ((size_t)r * N + c) + 1];
+        }
+        blink_ref_ifft1d(col, N);
+        for (int r = 0; r < N; ++r) {
+            work[2 * ((size_t)r * N + c)] = col[2 * r];
+            work[2 * ((size_t)r * N + c) + 1] = col[2 * r + 1];
+        }
+    }
+    const double inv = 1.0 / weight_sum;
+    double im_max = 0.0;
+    const int s = shift ? N / 2 : 0;
+    for (int y = 0; y < N; ++y) {
+        int ry = (y + s) % N;                   /* fftshift: output y holds raw (y - N/2) mod N */
+        for (int x = 0; x < N; ++x) {
+            int rx = (x + s) % N;
+            const double *w = work + 2 * ((size_t)ry * N + rx);
+            image[(size_t)y * N + x] = w[0] * inv;
+            double ai = fabs(w[1] * inv);
+            if (ai > im_max) im_max = ai;
+        }
+    }
+    if (imag_max) *imag_max = im_max;
+    free(work);
+    free(col);
+    return 0;
+}
+
+int blink_ref_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+int blink_ref_image_batch(const float *vis, const uint8_t *flags, const double *uvw,
+                          const double *freq_hz, int T, int C, int P, int B, int grid_n,
+                          double pixel_scale, int weighting, int shift, double *images,
+                          double *weight_sum, int32_t *n_out, int32_t *cell_idx,
+                          int32_t *counts, int n_threads)
+{
+    if (!is_pow2(grid_n) || T < 0 || C < 0 || P < 1 || B < 0) return 1;
+    if (!vis || !uvw || !freq_hz || !images) return 1;
+    if (weighting != 0 && weighting != 1) return 1;
+    const int N = grid_n;
+    const size_t NN = (size_t)N * N;
+    const long n_tc = (long)T * C;
+    int err = 0;
+#ifdef _OPENMP
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads) reduction(max : err)
+#endif
+    for (long tc = 0; tc < n_tc; ++tc) {
+        const long t = tc / C, c = tc % C;
+        double *grid = (double *)malloc(sizeof(double) * 2 * NN * (size_t)P);
+        if (!grid) { err = 2; continue; }
+        double W = 0.0;
+        int32_t nout = 0;
+        int rc = blink_ref_grid(vis + 2 * (size_t)tc * P * B, flags ? flags + (size_t)tc * B : NULL,
+                                uvw + 3 * (size_t)t * B, P, B, freq_hz[c], N, pixel_scale,
+                                weighting, grid, counts ? counts + (size_t)tc * NN : NULL,
+                                cell_idx ? cell_idx + (size_t)tc * B : NULL, &W, &nout);
+        for (int p = 0; rc == 0 && p < P; ++p) {
+            rc = blink_ref_ifft2d(grid + 2 * NN * (size_t)p, N, W, shift,
+                                  images + ((size_t)tc * P + p) * NN, NULL);
+            if (weight_sum) weight_sum[(size_t)tc * P + p] = W;
+        }
+        if (n_out) n_out[tc] = nout;
+        if (rc > err) err = rc;
+        free(grid);
+    }
+    return err;
+}

@@ -1,0 +1,84 @@
+/*
+ * blink_ref — plain, slow, obviously correct FP64 CPU oracle for batched dirty imaging.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may link, load or call this
+ * library: only the tests, the package's smoke check and the benchmark's CPU-baseline
+ * leg use it. It shares no code, header, table or constant with the HIP library.
+ *
+ * What it computes (BLINK, arXiv 2505.15204):
+ *   - Section 4, Eq. 4: visibilities sample S(u,v) = FT of the sky with kernel exp(-i2pi(ul+vm)).
+ *   - Section 4, Eq. 5 and Section 6.2.4: each visibility is placed, with no convolution
+ *     kernel, on the regular N x N grid cell of its (u,v) ("gridding"); natural weighting
+ *     gives every baseline the same weight; the dirty image is the inverse 2D FFT of the
+ *     grid, shifted so the phase centre is in the middle.
+ *   - Section 6.1: visibilities and images are 32-bit floats; this oracle widens them to
+ *     double exactly and computes everything in IEEE double (no FMA contraction).
+ *
+ * Readings where the paper is silent (each one is listed with its reason in the design notes):
+ *   cell size      1/(N*dl) wavelengths, so k = (f/c)*(N*dl) cells per metre, in that order;
+ *   rounding       iu = nearbyint(u*k), ties to even, on that single double product;
+ *   out of grid    kept only if |iu| < N/2 and |iv| < N/2 (strict; NaN counts as outside);
+ *   Hermitian      every kept visibility V at (iu,iv) also contributes conj(V) at (-iu,-iv);
+ *   linear cell    (iv mod N)*N + (iu mod N), corner origin;
+ *   weighting      natural: G = sum of placements, W = number of placements;
+ *                  uniform: G = mean of the placements in the cell, W = number of occupied cells;
+ *   image          I[y][x] = Re( sum_{kv,ku} G[kv][ku] exp(+2 pi i (ku X + kv Y)/N) ) / W,
+ *                  X = x - N/2, Y = y - N/2 when shifted (X = x, Y = y otherwise); W = 0 gives 0;
+ *   flags          a flagged (t,c,b) is dropped before weighting, for every polarisation.
+ *
+ * Layouts: complex values are interleaved (re, im) pairs. vis is complex64 [T][C][P][B];
+ * uvw is double [T][B][3] metres; freq is double [C]; flags are uint8 [T][C][B] (1 = flagged,
+ * NULL = none); grids are complex double [N][N] row-major (row = v index); images are double
+ * [N][N] (row = y = m direction, column = x = l direction).
+ *
+ * Return codes: 0 success, 1 invalid argument (N not a power of two in [2, 16384], negative
+ * sizes, NULL required pointer), 2 out of memory. Nothing is written on an argument error.
+ */
+#ifndef BLINK_REF_H
+#define BLINK_REF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Cells per metre for one channel: k = (f / c) * (N * dl), c = 299792458 m/s. */
+double blink_ref_cells_per_metre(double freq_hz, int grid_n, double pixel_scale);
+
+/* Nearest-cell gridding of one (time, channel) for P polarisations.
+ * vis: complex64 [P][B]; flags: uint8 [B] or NULL; uvw: double [B][3].
+ * grid: out complex double [P][N][N]; counts: out int32 [N][N] (placements per cell) or NULL;
+ * cell_idx: out int32 [B] (linear cell of the (iu,iv) placement, -1 flagged, -2 out of grid) or NULL;
+ * weight_sum: out W (same for every polarisation); n_out: out number of out-of-grid visibilities. */
+int blink_ref_grid(const float *vis, const uint8_t *flags, const double *uvw, int P, int B,
+                   double freq_hz, int grid_n, double pixel_scale, int weighting,
+                   double *grid, int32_t *counts, int32_t *cell_idx,
+                   double *weight_sum, int32_t *n_out);
+
+/* In-place unnormalised inverse DFT of length n (power of two): X[j] <- sum_k X[k] exp(+2 pi i jk/n).
+ * Iterative radix-2 decimation-in-time with bit-reversed input order. */
+int blink_ref_ifft1d(double *data, int n);
+
+/* Dirty image of one complex grid [N][N]: I = Re(IDFT2(G)) / W, optionally shifted.
+ * weight_sum <= 0 or not finite gives an all-zero image. imag_max (may be NULL) receives
+ * max |Im| / W over the image, for the realness check. */
+int blink_ref_ifft2d(const double *grid, int grid_n, double weight_sum, int shift,
+                     double *image, double *imag_max);
+
+/* Whole path over a batch: images [T][C][P][N][N] double, weight_sum [T][C][P] (or NULL),
+ * n_out [T][C] (or NULL), cell_idx [T][C][B] (or NULL), counts [T][C][N][N] (or NULL).
+ * OpenMP over (t,c) with n_threads threads (<= 0: the OpenMP default). */
+int blink_ref_image_batch(const float *vis, const uint8_t *flags, const double *uvw,
+                          const double *freq_hz, int T, int C, int P, int B, int grid_n,
+                          double pixel_scale, int weighting, int shift, double *images,
+                          double *weight_sum, int32_t *n_out, int32_t *cell_idx,
+                          int32_t *counts, int n_threads);
+
+/* Number of threads blink_ref_image_batch would use for n_threads <= 0. */
+int blink_ref_max_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

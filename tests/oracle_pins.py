@@ -1,0 +1,357 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by the mathematics.
+
+Every pin takes an ``oracle.Oracle`` (so the same checks can be run against a copy of
+the oracle built with a planted mistake) and raises AssertionError on failure.
+None of them re-types the oracle's arithmetic: they compare it with hand-worked golden
+values, brute-force definitions evaluated a different way (direct sums instead of FFTs,
+sums over baselines instead of over cells), an independent library FFT, closed forms
+and invariants.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+C_LIGHT = 299792458.0
+
+
+# ----------------------------------------------------------------------------- fixtures
+
+def read_cell_fixture():
+    rows = []
+    with open(os.path.join(GOLDEN, "cell_index_worked.txt")) as fh:
+        for ln in fh:
+            ln = ln.strip()
+            if not ln or ln.startswith("#"):
+                continue
+            f, n, dl, u, v, iu, iv, cell = ln.split()
+            rows.append((float(f), int(n), float(dl), float(u), float(v), int(iu), int(iv),
+                         int(cell)))
+    return rows
+
+
+def read_tiny_fixture():
+    sections = {}
+    cur = None
+    with open(os.path.join(GOLDEN, "tiny_grid_n8.txt")) as fh:
+        for ln in fh:
+            ln = ln.strip()
+            if not ln or ln.startswith("#"):
+                continue
+            if ln.startswith("["):
+                cur = ln.strip("[]")
+                sections[cur] = []
+                continue
+            if cur is not None:
+                sections[cur].append(ln.split())
+    return sections
+
+
+def small_problem(seed, B=300, N=64, P=1, flag_frac=0.1, extent=0.45, n_src=4):
+    """Random baselines inside the grid (mostly), point-source visibilities plus noise."""
+    g = np.random.default_rng(seed)
+    f = 150.0e6
+    dl = 1.0 / 300.0
+    k = (f / C_LIGHT) * (N * dl)
+    rmax = extent * N / k                           # metres reaching `extent` of the grid
+    uvw = np.zeros((B, 3))
+    uvw[:, :2] = g.uniform(-rmax, rmax, size=(B, 2))
+    src = [(g.uniform(1, 5), g.uniform(-0.05, 0.05), g.uniform(-0.05, 0.05)) for _ in range(n_src)]
+    vis = np.zeros((P, B), np.complex128)
+    for s, l, m in src:
+        vis += s * np.exp(-2j * np.pi * (uvw[:, 0] * l + uvw[:, 1] * m) * f / C_LIGHT)
+    vis += g.normal(0, 0.3, (P, B)) + 1j * g.normal(0, 0.3, (P, B))
+    flags = (g.random(B) < flag_frac).astype(np.uint8)
+    return vis.astype(np.complex64), flags, uvw, f, N, dl
+
+
+def direct_image_from_grid(G, W, shift):
+    """Brute-force definition: I[y][x] = Re(sum_{kv,ku} G[kv][ku] e^{+2 pi i (ku X + kv Y)/N})/W."""
+    N = G.shape[0]
+    pos = np.arange(N) - (N // 2 if shift else 0)
+    ang = 2.0 * np.pi * np.outer(np.arange(N), pos) / N            # [k][pixel]
+    E = np.exp(1j * ang)
+    full = E.T @ G @ E                                              # [y][x]
+    return full.real / W, np.abs(full.imag).max() / W
+
+
+def snapped_sum_image(vis, flags, uvw, f, N, dl, shift=True):
+    """Whole path as a sum over baselines at their snapped cells (natural weighting):
+    I = (1/W) sum_b 2 Re(V_b exp(+2 pi i (iu X + iv Y)/N))."""
+    k = (f / C_LIGHT) * (N * dl)
+    ru = np.rint(uvw[:, 0] * k)
+    rv = np.rint(uvw[:, 1] * k)
+    keep = (flags == 0) & (np.abs(ru) < N // 2) & (np.abs(rv) < N // 2)
+    W = 2.0 * keep.sum()
+    pos = np.arange(N) - (N // 2 if shift else 0)
+    Ex = np.exp(2j * np.pi * np.outer(ru[keep], pos) / N)          # [b][x]
+    Ey = np.exp(2j * np.pi * np.outer(rv[keep], pos) / N)          # [b][y]
+    v = vis[keep].astype(np.complex128)
+    img = 2.0 * np.real(np.einsum("b,by,bx->yx", v, Ey, Ex)) / W
+    return img, keep, W
+
+
+def ungridded_image(vis, keep, uvw, f, N, dl, W):
+    """Direct transform of the unsnapped visibilities at every pixel."""
+    k = (f / C_LIGHT) * (N * dl)
+    pos = np.arange(N) - N // 2
+    xu = uvw[keep, 0] * k
+    xv = uvw[keep, 1] * k
+    Ex = np.exp(2j * np.pi * np.outer(xu, pos) / N)
+    Ey = np.exp(2j * np.pi * np.outer(xv, pos) / N)
+    v = vis[keep].astype(np.complex128)
+    return 2.0 * np.real(np.einsum("b,by,bx->yx", v, Ey, Ex)) / W
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ----------------------------------------------------------------------------- pins
+
+def pin_cell_worked(O):
+    """Hand-worked k and cell indices, including ties (round half to even) and the strict edge."""
+    rows = read_cell_fixture()
+    kA = O.cells_per_metre(150.0e6, 256, math.pi / 10800.0)
+    assert abs(kA - 0.03725946705691879) <= 1e-17, kA
+    assert O.cells_per_metre(C_LIGHT, 8, 1.0 / 64.0) == 0.125
+    for f, n, dl, u, v, iu, iv, cell in rows:
+        out = O.grid(np.array([[1 + 0j]], np.complex64), None, np.array([[u, v, 0.0]]), f, n, dl)
+        assert int(out["cell_idx"][0]) == cell, (f, n, u, v, cell, out["cell_idx"][0])
+        assert out["n_out"] == (1 if cell == -2 else 0)
+
+
+def pin_tiny_grid(O):
+    """Hand-enumerated 7-baseline grid, counts, weights and closed-form image pixels."""
+    fx = read_tiny_fixture()
+    bl = np.array([[float(x) for x in r] for r in fx["baselines"]])
+    uvw = np.zeros((bl.shape[0], 3))
+    uvw[:, :2] = bl[:, 0:2]
+    flags = bl[:, 2].astype(np.uint8)
+    vis = (bl[:, 3] + 1j * bl[:, 4]).astype(np.complex64)
+    expect_cells = [int(x) for x in fx["cell_idx"][0]]
+    weights = {r[0]: float(r[1]) for r in fx["weights"]}
+    for wname, wcode in (("natural", 0), ("uniform", 1)):
+        out = O.grid(vis, flags, uvw, C_LIGHT, 8, 1.0 / 64.0, weighting=wcode)
+        assert list(out["cell_idx"]) == expect_cells, out["cell_idx"]
+        assert out["n_out"] == int(weights["n_out"])
+        assert out["weight_sum"] == weights[wname], out["weight_sum"]
+        g = out["grid"][0].reshape(-1)
+        expect = np.zeros(64, np.complex128)
+        counts = np.zeros(64, np.int32)
+        for cell, re, im, cnt in fx[f"{wname}_grid"]:
+            expect[int(cell)] = float(re) + 1j * float(im)
+            counts[int(cell)] = int(cnt)
+        assert np.array_equal(g, expect), (wname, g)
+        assert np.array_equal(out["counts"].reshape(-1), counts)
+        img, _ = O.ifft2d(out["grid"][0], out["weight_sum"], shift=True)
+        for w, x, y, val in fx["pixels"]:
+            if w == wname:
+                assert abs(img[int(y), int(x)] - float(val)) < 1e-14, (w, x, y, img[int(y), int(x)])
+        # unshifted: the phase-centre value sits at the corner
+        img0, _ = O.ifft2d(out["grid"][0], out["weight_sum"], shift=False)
+        assert abs(img0[0, 0] - img[4, 4]) < 1e-14
+
+
+def pin_ifft1d_bruteforce(O):
+    """Radix-2 FFT against the O(n^2) definition and against numpy's FFT."""
+    g = np.random.default_rng(1)
+    for n in (1, 2, 4, 8, 16, 32, 64, 256):
+        x = g.normal(size=n) + 1j * g.normal(size=n)
+        y = O.ifft1d(x)
+        j = np.arange(n)
+        direct = np.exp(2j * np.pi * np.outer(j, j) / n) @ x
+        assert np.abs(y - direct).max() <= 1e-12 * max(1.0, np.abs(direct).max()), n
+        assert np.abs(y - np.fft.ifft(x) * n).max() <= 1e-12 * max(1.0, np.abs(direct).max()), n
+
+
+def pin_ifft2d_bruteforce(O):
+    """2D image of a random (non-Hermitian) grid against the direct O(N^4) definition."""
+    g = np.random.default_rng(2)
+    for N in (2, 4, 8, 16):
+        G = g.normal(size=(N, N)) + 1j * g.normal(size=(N, N))
+        for shift in (True, False):
+            img, im = O.ifft2d(G, 3.5, shift=shift)
+            ref, ref_im = direct_image_from_grid(G, 3.5, shift)
+            assert np.abs(img - ref).max() <= 1e-12 * np.abs(ref).max(), (N, shift)
+            assert abs(im - ref_im) <= 1e-12 * ref_im, (N, shift)
+
+
+def pin_ifft2d_library(O):
+    """2D image against numpy.fft.ifft2 (+ sign, 1/N^2) followed by fftshift."""
+    g = np.random.default_rng(3)
+    for N in (32, 128):
+        G = g.normal(size=(N, N)) + 1j * g.normal(size=(N, N))
+        img, _ = O.ifft2d(G, 2.0, shift=True)
+        ref = np.fft.fftshift(np.fft.ifft2(G) * N * N).real / 2.0
+        assert np.abs(img - ref).max() <= 1e-11 * np.abs(ref).max(), N
+        img0, _ = O.ifft2d(G, 2.0, shift=False)
+        ref0 = (np.fft.ifft2(G) * N * N).real / 2.0
+        assert np.abs(img0 - ref0).max() <= 1e-11 * np.abs(ref0).max(), N
+
+
+def pin_closed_forms(O):
+    """Flat grid -> centred delta of height N^2/W; one unit cell -> a cosine plane wave."""
+    for N in (8, 64):
+        img, _ = O.ifft2d(np.ones((N, N), np.complex128), 4.0, shift=True)
+        delta = np.zeros((N, N))
+        delta[N // 2, N // 2] = N * N / 4.0
+        assert np.abs(img - delta).max() <= 1e-12 * N * N, N
+        a, b = 3, N - 2                                     # ku = 3, kv = -2
+        G = np.zeros((N, N), np.complex128)
+        G[b, a] = 1.0
+        img, im = O.ifft2d(G, 1.0, shift=True)
+        X = np.arange(N) - N // 2
+        ref = np.cos(2 * np.pi * (a * X[None, :] + b * X[:, None]) / N)
+        assert np.abs(img - ref).max() <= 1e-12, N
+        assert abs(im - 1.0) <= 1e-12                     # |sin| reaches 1 on this grid
+
+
+def pin_parseval_and_sum(O):
+    """Parseval and the sum rule on a Hermitian grid produced by gridding."""
+    vis, flags, uvw, f, N, dl = small_problem(4, B=400, N=64)
+    out = O.grid(vis, flags, uvw, f, N, dl)
+    G, W = out["grid"][0], out["weight_sum"]
+    img, _ = O.ifft2d(G, W, shift=True)
+    lhs = float((img ** 2).sum())
+    rhs = N * N / W ** 2 * float((np.abs(G) ** 2).sum())
+    assert abs(lhs - rhs) <= 1e-11 * rhs, (lhs, rhs)
+    assert abs(img.sum() - N * N * G[0, 0].real / W) <= 1e-10 * abs(img).sum()
+
+
+def pin_snapped_dft(O):
+    """Grid + FFT + shift + 1/W equals the direct sum over baselines at their snapped cells."""
+    for seed, N in ((5, 32), (6, 64)):
+        vis, flags, uvw, f, N, dl = small_problem(seed, B=300, N=N, extent=0.6)
+        res = O.image_batch(vis[None, None], flags[None, None], uvw[None], np.array([f]), N, dl)
+        img = res["images"][0, 0, 0]
+        ref, keep, W = snapped_sum_image(vis[0], flags, uvw, f, N, dl)
+        assert res["weight_sum"][0, 0, 0] == W
+        assert res["n_out"][0, 0] == int(((flags == 0) & ~keep).sum())
+        assert np.abs(img - ref).max() <= 1e-12 * np.abs(ref).max(), seed
+
+
+def pin_ungridded_bound(O):
+    """Against the direct transform of the unsnapped visibilities: equal at the phase centre,
+    and within (2/W) sum |V| pi (|X|+|Y|)/N everywhere (snapping moves a sample <= half a cell)."""
+    vis, flags, uvw, f, N, dl = small_problem(7, B=250, N=64, extent=0.4)
+    res = O.image_batch(vis[None, None], flags[None, None], uvw[None], np.array([f]), N, dl)
+    img = res["images"][0, 0, 0]
+    k = (f / C_LIGHT) * (N * dl)
+    keep = (flags == 0) & (np.abs(np.rint(uvw[:, 0] * k)) < N // 2) & (np.abs(np.rint(uvw[:, 1] * k)) < N // 2)
+    W = res["weight_sum"][0, 0, 0]
+    Id = ungridded_image(vis[0], keep, uvw, f, N, dl, W)
+    X = np.abs(np.arange(N) - N // 2)
+    bound = (2.0 / W) * np.abs(vis[0][keep]).astype(np.float64).sum() * np.pi * (X[None, :] + X[:, None]) / N
+    assert abs(img[N // 2, N // 2] - Id[N // 2, N // 2]) <= 1e-12 * abs(Id[N // 2, N // 2])
+    assert np.all(np.abs(img - Id) <= bound + 1e-12)
+    # the bound must not be vacuous: snapping error is far below it on average
+    assert np.abs(img - Id).max() < 0.5 * bound.max()
+
+
+def pin_point_source_centre(O):
+    """V = 1 (a unit source at the phase centre): the dirty beam, 1 at the centre, <= 1, even."""
+    vis, flags, uvw, f, N, dl = small_problem(8, B=300, N=64)
+    ones = np.ones_like(vis)
+    for weighting in (0, 1):
+        res = O.image_batch(ones[None, None], flags[None, None], uvw[None], np.array([f]), N, dl,
+                            weighting=weighting)
+        img = res["images"][0, 0, 0]
+        c = N // 2
+        assert abs(img[c, c] - 1.0) <= 1e-12
+        assert np.abs(img).max() <= 1.0 + 1e-12
+        inner = img[1:, 1:]                                   # X, Y in [-N/2+1, N/2-1]
+        assert np.abs(inner - inner[::-1, ::-1]).max() <= 1e-12
+
+
+def pin_shift_theorem(O):
+    """A point source at (l, m) = (p dl, q dl) through Eq. 4 images as the dirty beam rolled by
+    (+p, +q): +l is +x (column), +m is +y (row), and the transform sign is the inverse one."""
+    N, f, dl = 32, C_LIGHT, 1.0 / 256.0                    # k = 0.125: 8 m per cell
+    g = np.random.default_rng(9)
+    cells = g.integers(-12, 13, size=(120, 2))
+    uvw = np.zeros((120, 3))
+    uvw[:, :2] = cells * 8.0
+    flags = np.zeros(120, np.uint8)
+    beam = O.image_batch(np.ones((1, 1, 1, 120), np.complex64), flags[None, None], uvw[None],
+                         np.array([f]), N, dl)["images"][0, 0, 0]
+    for p, q in ((3, 0), (0, 5), (-4, 2)):
+        l, m = p * dl, q * dl
+        vis = np.exp(-2j * np.pi * (uvw[:, 0] * l + uvw[:, 1] * m) * f / C_LIGHT)
+        img = O.image_batch(vis.astype(np.complex64)[None, None, None], flags[None, None], uvw[None],
+                            np.array([f]), N, dl)["images"][0, 0, 0]
+        rolled = np.roll(np.roll(beam, q, axis=0), p, axis=1)
+        assert np.abs(img - rolled).max() <= 2e-7, (p, q)       # complex64 rounding of V
+        y, x = np.unravel_index(np.argmax(img), img.shape)
+        assert (x, y) == (N // 2 + p, N // 2 + q), (p, q, x, y)
+
+
+def pin_realness(O):
+    """The Hermitian-completed grid transforms to a real image (imaginary part at rounding level)."""
+    vis, flags, uvw, f, N, dl = small_problem(10, B=400, N=128)
+    out = O.grid(vis, flags, uvw, f, N, dl)
+    img, im = O.ifft2d(out["grid"][0], out["weight_sum"], shift=True)
+    assert im <= 1e-12 * np.abs(img).max(), im
+
+
+def pin_invariants(O):
+    """Count, weight and symmetry invariants of gridding (natural and uniform)."""
+    vis, flags, uvw, f, N, dl = small_problem(11, B=500, N=32, extent=0.7, P=2)
+    nat = O.grid(vis, flags, uvw, f, N, dl, weighting=0)
+    uni = O.grid(vis, flags, uvw, f, N, dl, weighting=1)
+    cell = nat["cell_idx"]
+    kept = int((cell >= 0).sum())
+    assert np.array_equal(cell == -1, flags == 1)
+    assert nat["n_out"] == int((cell == -2).sum()) and nat["n_out"] > 0
+    cnt = nat["counts"]
+    assert int(cnt.sum()) == 2 * kept
+    mirror = np.roll(np.roll(cnt[::-1, ::-1], 1, axis=0), 1, axis=1)   # counts[-kv][-ku]
+    assert np.array_equal(cnt, mirror)
+    assert nat["weight_sum"] == 2 * kept
+    assert uni["weight_sum"] == int((cnt > 0).sum())
+    assert np.array_equal(uni["counts"], cnt) and np.array_equal(uni["cell_idx"], cell)
+    vmax = np.abs(vis.astype(np.complex128)).max()
+    assert np.abs(uni["grid"]).max() <= vmax * (1 + 1e-12)
+    occupied = cnt > 0
+    assert np.all(uni["grid"][:, ~occupied] == 0) and np.all(nat["grid"][:, ~occupied] == 0)
+    # the natural cell sum is the uniform cell mean times the count
+    assert np.allclose(nat["grid"], uni["grid"] * cnt[None], rtol=1e-12, atol=1e-12)
+    # Hermitian grid
+    G = nat["grid"][0]
+    Gm = np.conj(np.roll(np.roll(G[::-1, ::-1], 1, axis=0), 1, axis=1))
+    assert np.abs(G - Gm).max() <= 1e-12 * np.abs(G).max()
+
+
+def pin_degenerate(O):
+    """All flagged, or all outside the grid: W = 0 and an all-zero image; empty baseline list."""
+    vis, flags, uvw, f, N, dl = small_problem(12, B=50, N=16)
+    allf = np.ones_like(flags)
+    res = O.image_batch(vis[None, None], allf[None, None], uvw[None], np.array([f]), N, dl)
+    assert res["weight_sum"][0, 0, 0] == 0 and not res["images"].any()
+    assert np.all(res["cell_idx"] == -1) and res["n_out"][0, 0] == 0
+    far = uvw * 1000.0
+    res = O.image_batch(vis[None, None], None, far[None], np.array([f]), N, dl)
+    assert res["weight_sum"][0, 0, 0] == 0 and not res["images"].any()
+    assert res["n_out"][0, 0] == 50
+    res = O.image_batch(np.zeros((1, 1, 1, 0), np.complex64), None, np.zeros((1, 0, 3)),
+                        np.array([f]), N, dl)
+    assert res["weight_sum"][0, 0, 0] == 0 and not res["images"].any()
+
+
+def pin_pols_share_flags(O):
+    """Polarisations are independent images that share cells and flags."""
+    vis, flags, uvw, f, N, dl = small_problem(13, B=200, N=32, P=2)
+    both = O.image_batch(vis[None, None], flags[None, None], uvw[None], np.array([f]), N, dl)
+    for p in range(2):
+        one = O.image_batch(vis[None, None, p:p + 1], flags[None, None], uvw[None], np.array([f]), N, dl)
+        assert np.array_equal(both["images"][0, 0, p], one["images"][0, 0, 0])
+    assert not np.allclose(both["images"][0, 0, 0], both["images"][0, 0, 1])
+
+
+PINS = [pin_cell_worked, pin_tiny_grid, pin_ifft1d_bruteforce, pin_ifft2d_bruteforce,
+        pin_ifft2d_library, pin_closed_forms, pin_parseval_and_sum, pin_snapped_dft,
+        pin_ungridded_bound, pin_point_source_centre, pin_shift_theorem, pin_realness,
+        pin_invariants, pin_degenerate, pin_pols_share_flags]

@@ -1,0 +1,53 @@
+"""CPU tests: the pins catch plausible mistakes planted in copies of the oracle.
+
+Each case copies the oracle source into a temporary directory, plants one mistake by text
+substitution, builds it, and checks that at least one pin fails. The oracle itself is never
+modified.
+"""
+import os
+
+import pytest
+
+import oracle
+import oracle_pins
+
+MUTANTS = {
+    "twiddle_sign": ("double wr = cos(ang), wi = sin(ang);", "double wr = cos(ang), wi = -sin(ang);"),
+    "twiddle_angle": ("(double)k / (double)len", "(double)k / (double)h"),
+    "mirror_not_conjugated": ("g[2 * c2 + 1] -= im;", "g[2 * c2 + 1] += im;"),
+    "cell_transposed": ("size_t c1 = (size_t)mod_n(iv, N) * N + mod_n(iu, N);",
+                        "size_t c1 = (size_t)mod_n(iu, N) * N + mod_n(iv, N);"),
+    "round_half_up": ("double ru = nearbyint(xu);", "double ru = floor(xu + 0.5);"),
+    "natural_weight_halved": ("W = 2.0 * (double)kept;", "W = (double)kept;"),
+    "no_shift": ("const int s = shift ? N / 2 : 0;", "const int s = 0;"),
+    "edge_not_strict": ("fabs(ru) < half && fabs(rv) < half", "fabs(ru) <= half && fabs(rv) <= half"),
+    "cell_size_missing_dl": ("return cycles_per_metre * cells_per_wavelength;",
+                             "return cycles_per_metre * (double)grid_n;"),
+    "uniform_not_divided": ("g[2 * c] /= (double)cnt[c];\n                g[2 * c + 1] /= (double)cnt[c];",
+                            "(void)g;"),
+    "column_pass_drops_imag": ("col[2 * r + 1] = work[2 * ((size_t)r * N + c) + 1];",
+                               "col[2 * r + 1] = 0.0;"),
+    "image_transposed": ("image[(size_t)y * N + x] = w[0] * inv;", "image[(size_t)x * N + y] = w[0] * inv;"),
+    "mirror_cell_wrong": ("size_t c2 = (size_t)mod_n(-iv, N) * N + mod_n(-iu, N);",
+                          "size_t c2 = (size_t)mod_n(-iv, N) * N + mod_n(iu, N);"),
+    "butterfly_sign": ("y[0] = x[0] - tr; y[1] = x[1] - ti;", "y[0] = x[0] + tr; y[1] = x[1] - ti;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(tmp_path, name):
+    before, after = MUTANTS[name]
+    src = open(oracle.SRC).read()
+    assert src.count(before) == 1, f"mutation site for {name} not found exactly once"
+    path = tmp_path / "blink_ref_mutant.c"
+    path.write_text(src.replace(before, after))
+    lib = oracle.compile_library(str(path), str(tmp_path / f"libmut_{name}.so"))
+    O = oracle.Oracle(oracle.load(lib))
+    caught = []
+    for pin in oracle_pins.PINS:
+        try:
+            pin(O)
+        except Exception:  # any failure of a pin counts as caught
+            caught.append(pin.__name__)
+    assert caught, f"no pin caught the planted mistake {name}"
+    os.remove(lib)
