@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark: batched dirty imaging of the MWA VCS-scale workload on one MI355X.
+
+Workload (synthetic, MWA-shaped): 128 tiles -> 8128 cross baselines, 2 polarisations,
+768 fine channels of 40 kHz from 139 MHz, 100 time steps of 1 ms, 1024 x 1024 FP32 images,
+natural weighting, 50 point sources plus noise, 10% random flags. All inputs are generated on
+the GPU and stay resident in HBM; a step images one time step (768 x 2 = 1536 images) into an
+HBM ring buffer; the default run times all 100 steps (153,600 images).
+
+Prints one JSON line with images/s, the roofline position of the dominant kernel (bytes from
+the algorithmic byte model / its hipEvent-measured launch time), per-kernel figures, and the
+FP64 CPU oracle timed on a bounded sample of the same workload on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "dirty images/sec (1024² grid, 8128 baselines) and % HBM roofline; MFMA vs FP32"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_bytes(spec, n_tc):
+    """Algorithmic HBM bytes of one launch of each kernel for n_tc (time, channel) pairs.
+
+    grid_colfft: per image, write the half-spectrum intermediate N x N/2 complex64 (4 N^2 B) and
+                 read each visibility once (8 B) plus its placement record (8 B).
+    row_fft:     per image, read the intermediate (4 N^2 B) and write the FP32 image (4 N^2 B).
+    bin:         per (t,c), read u, v (16 B) and the flag (1 B) of each baseline, write ~one
+                 placement record (8 B) per baseline.
+    weights:     per image, 4 B in, 4 B + 8 B out.
+    """
+    N, B, P = spec.grid_n, spec.B, spec.P
+    n_img = n_tc * P
+    return {
+        "grid_colfft": n_img * (4 * N * N + 16 * B),
+        "row_fft": n_img * (8 * N * N),
+        "bin": n_tc * (25 * B),
+        "weights": n_img * 16,
+    }
+
+
+def cpu_baseline(d, spec, budget_s):
+    """Time the FP64 oracle (as it stands) on channels 0..k-1 of time step 0, both pols."""
+    import oracle
+
+    oracle.build(force=False)
+    threads = oracle.max_threads()
+    vis = d["vis"][0:1].cpu().numpy()
+    flags = d["flags"][0:1].cpu().numpy()
+    uvw = d["uvw_m"][0:1].cpu().numpy()
+    freq = d["freq_hz"].cpu().numpy()
+
+    def run(k):
+        t0 = time.perf_counter()
+        oracle.image_batch(vis[:, :k], flags[:, :k], uvw, freq[:k], spec.grid_n, spec.pixel_scale, 0,
+                           n_threads=threads)
+        return time.perf_counter() - t0
+
+    per_pair = run(threads)/threads          # one pair per thread for calibration
+    k = max(threads, min(spec.C, int(budget_s / max(per_pair, 1e-6))))
+    k = (k // threads) * threads or threads
+    dt = run(k)
+    n_img = k * spec.P
+    return {"value": round(n_img / dt, 3), "unit": "images/s", "cores": threads, "kind": "oracle",
+            "sample": f"time step 0, channels 0..{k - 1}, {spec.P} pols: {n_img} images of "
+                      f"{spec.grid_n}^2 in {dt:.1f} s (FP64 C oracle, OpenMP over (t,c))"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100, help="time steps to image (1536 images each)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU: every image is independent, so a multi-GPU run is this "
+              f"single-GPU path on each GPU's share of time steps; --gpus {args.gpus} is not supported.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2505_15204_amd as blink
+    from paper_2505_15204_amd import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    spec = synth.spec_vcs()
+    T, C, P, B, N = spec.T, spec.C, spec.P, spec.B, spec.grid_n
+    log(f"generating workload {spec.name}: T={T} C={C} P={P} B={B} N={N} on cuda:0")
+    d = synth.make_problem_device(spec, "cuda:0")
+    torch.cuda.synchronize()
+    ctx = blink.Context(0)
+    images = torch.empty((1, C, P, N, N), dtype=torch.float32, device="cuda:0")   # ring: one time step
+    wsum = torch.empty((1, C, P), dtype=torch.float64, device="cuda:0")
+    nout = torch.empty((1, C), dtype=torch.int32, device="cuda:0")
+    ws = torch.empty(blink.image_batch_workspace_size(1, C, P, B, N), dtype=torch.uint8, device="cuda:0")
+
+    def step(i):
+        t = i % T
+        ctx.blink_image_batch(d["vis"][t:t + 1], d["flags"][t:t + 1], d["uvw_m"][t:t + 1], d["freq_hz"], N,
+                              spec.pixel_scale, 0, out=images, weight_sum=wsum, n_out=nout, workspace=ws)
+
+    log(f"warmup {args.warmup} steps")
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record()
+    for i in range(args.steps):
+        step(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = ev0.elapsed_time(ev1)
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    n_images = args.steps * C * P
+    value = n_images / (gpu_ms / 1e3)
+    log(f"{n_images} images in {gpu_ms:.1f} ms (wall {wall * 1e3:.1f} ms): {value:.0f} images/s")
+
+    kb = kernel_bytes(spec, C)
+    kernels = {}
+    for name, (ms, launches) in prof.items():
+        if launches == 0:
+            continue
+        avg_s = ms / launches / 1e3
+        entry = {"launches": launches, "avg_ms": round(ms / launches, 4), "total_ms": round(ms, 3)}
+        if name in kb:
+            gbs = kb[name] / avg_s / 1e9
+            entry.update({"bytes_per_launch": kb[name], "achieved_GB_s": round(gbs, 1),
+                          "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
+        kernels[name] = entry
+    dom = max((k for k in kernels if k in kb), key=lambda k: kernels[k]["total_ms"])
+    roof = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["achieved_GB_s"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": kernels[dom]["frac_hbm"], "traffic": None}
+    per_image = 12 * N * N + 8 * B + B // P
+    path = {"bytes_per_image_model": per_image,
+            "achieved_GB_s": round(value * per_image / 1e9, 1),
+            "frac_hbm": round(value * per_image / 1e9 / HBM_PEAK_GBS, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
+        cpu = cpu_baseline(d, spec, args.cpu_seconds)
+        log(f"CPU oracle: {cpu['value']} images/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(gpu_ms / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {
+            "workload": "vcs-1024: 128 tiles (8128 cross baselines), 2 pols, 768 x 40 kHz channels from "
+                        "139 MHz, 100 x 1 ms time steps, 1024^2 FP32 grid, 1 arcmin pixels, natural weighting, "
+                        "50 point sources + noise, 10% flags; one step = one time step = 1536 images",
+            "images_per_step": C * P,
+            "grid_n": N,
+            "baselines": B,
+            "path": "fp32: bin -> fused grid+column FFT -> weights -> row FFT (C2R)",
+        },
+        "roofline": roof,
+        "path_roofline": path,
+        "kernels": kernels,
+        "wall_s": round(wall, 4),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,267 @@
+"""MI355X batched dirty imaging (BLINK's gridding + inverse 2D FFT hot path).
+
+Thin ctypes binding of ``libblink.so`` (declared in ``include/blink.h``). The functions
+take torch tensors that already live on the GPU and pass their device pointers and the
+current HIP stream to the library; every step of the computation runs in the library's
+HIP kernels. PyTorch is used only to allocate device memory (outputs, workspace) and for
+streams. There is no CPU fallback: if the library is missing, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libblink.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "blink.h")
+
+BLINK_OK, BLINK_ERR_ARG, BLINK_ERR_SIZE, BLINK_ERR_NOMEM, BLINK_ERR_HIP, BLINK_ERR_STATE = range(6)
+WEIGHT_NATURAL, WEIGHT_UNIFORM = 0, 1
+KERNELS = ("bin", "grid", "grid_colfft", "dense_colfft", "weights", "row_fft")   # BLINK_KERNEL_* ids
+PREC_FP32 = 0
+
+_lib = None
+
+
+class BlinkError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+def header_functions() -> list:
+    """Names of the functions declared in include/blink.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(blink_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib() -> ctypes.CDLL:
+    """Load libblink.so and declare its signatures. Raises if the library was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2505_15204_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, f64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    L.blink_version.restype = i32
+    L.blink_status_string.restype = ctypes.c_char_p
+    L.blink_status_string.argtypes = [i32]
+    L.blink_create.restype = i32
+    L.blink_create.argtypes = [ctypes.POINTER(P), i32]
+    L.blink_destroy.restype = i32
+    L.blink_destroy.argtypes = [P]
+    L.blink_last_error.restype = ctypes.c_char_p
+    L.blink_last_error.argtypes = [P]
+    L.blink_grid_workspace_size.restype = i32
+    L.blink_grid_workspace_size.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz)]
+    L.blink_ifft2d_workspace_size.restype = i32
+    L.blink_ifft2d_workspace_size.argtypes = [i32, i32, i32, ctypes.POINTER(sz)]
+    L.blink_image_batch_workspace_size.restype = i32
+    L.blink_image_batch_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
+    L.blink_grid.restype = i32
+    L.blink_grid.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, P, P, P, P, P, P, sz, P]
+    L.blink_ifft2d.restype = i32
+    L.blink_ifft2d.argtypes = [P, P, P, i32, i32, i32, i32, P, P, sz, P]
+    L.blink_image_batch.restype = i32
+    L.blink_image_batch.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32, P, P, P,
+                                    P, sz, P]
+    L.blink_profile_enable.restype = i32
+    L.blink_profile_enable.argtypes = [P, i32]
+    L.blink_profile_read.restype = i32
+    L.blink_profile_read.argtypes = [P, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
+    _lib = L
+    return L
+
+
+def status_string(st: int) -> str:
+    return lib().blink_status_string(st).decode()
+
+
+def _check(st: int, ctx=None, what: str = ""):
+    if st != BLINK_OK:
+        detail = lib().blink_last_error(ctx).decode() if ctx else ""
+        raise BlinkError(st, f"{what}: {status_string(st)}" + (f" ({detail})" if detail else ""))
+
+
+def grid_workspace_size(T: int, C: int, B: int, grid_n: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().blink_grid_workspace_size(T, C, B, grid_n, ctypes.byref(n)), what="blink_grid_workspace_size")
+    return n.value
+
+
+def ifft2d_workspace_size(n_img: int, grid_n: int, precision: int = PREC_FP32) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().blink_ifft2d_workspace_size(n_img, grid_n, precision, ctypes.byref(n)),
+           what="blink_ifft2d_workspace_size")
+    return n.value
+
+
+def image_batch_workspace_size(T: int, C: int, P: int, B: int, grid_n: int, weighting: int = 0,
+                               precision: int = PREC_FP32) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().blink_image_batch_workspace_size(T, C, P, B, grid_n, weighting, precision, ctypes.byref(n)),
+           what="blink_image_batch_workspace_size")
+    return n.value
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Context:
+    """One library context (device tables and error state) on a HIP device."""
+
+    def __init__(self, device: int = 0):
+        import torch  # noqa: F401  (device memory and streams come from torch)
+
+        self.device = device
+        h = ctypes.c_void_p()
+        st = lib().blink_create(ctypes.byref(h), device)
+        _check(st, None, f"blink_create(device={device})")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().blink_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- kernel timing (hipEvents around every launch while enabled)
+    def profile_enable(self, enable: bool = True):
+        _check(lib().blink_profile_enable(self.handle, int(bool(enable))), self.handle, "blink_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{kernel name: (total ms, launches)} for every kernel id; waits for the recorded events."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            ms = ctypes.c_double()
+            n = ctypes.c_int64()
+            _check(lib().blink_profile_read(self.handle, k, ctypes.byref(ms), ctypes.byref(n)), self.handle,
+                   "blink_profile_read")
+            out[name] = (ms.value, n.value)
+        return out
+
+    # -- helpers
+    def _torch(self):
+        import torch
+        return torch
+
+    def _stream(self, stream):
+        torch = self._torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def _require(self, name, t, dtype, shape=None):
+        torch = self._torch()
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must be on the GPU, got {t.device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        return t
+
+    def _workspace(self, nbytes, workspace):
+        torch = self._torch()
+        if workspace is None:
+            workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        self._require("workspace", workspace, torch.uint8)
+        return workspace
+
+    # -- entry points (same names as the C ABI)
+    def blink_grid(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float, weighting: int = 0,
+                   want_counts: bool = True, want_cell_idx: bool = True, workspace=None, stream=None):
+        """Nearest-cell gridding. vis complex64 [T][C][P][B]; flags uint8 [T][C][B] or None;
+        uvw_m float64 [T][B][3]; freq_hz float64 [C]. Returns a dict of device tensors:
+        grids complex64 [T][C][P][N][N], counts int32 [T][C][N][N], weight_sum float64 [T][C][P],
+        cell_idx int32 [T][C][B], n_out int32 [T][C]."""
+        torch = self._torch()
+        T, C, P, B = vis.shape
+        N = int(grid_n)
+        self._require("vis", vis, torch.complex64)
+        if flags is not None:
+            self._require("flags", flags, torch.uint8, (T, C, B))
+        self._require("uvw_m", uvw_m, torch.float64, (T, B, 3))
+        self._require("freq_hz", freq_hz, torch.float64, (C,))
+        dev = vis.device
+        grids = torch.empty((T, C, P, N, N), dtype=torch.complex64, device=dev)
+        counts = torch.empty((T, C, N, N), dtype=torch.int32, device=dev) if want_counts else None
+        wsum = torch.empty((T, C, P), dtype=torch.float64, device=dev)
+        cell = torch.empty((T, C, B), dtype=torch.int32, device=dev) if want_cell_idx else None
+        nout = torch.empty((T, C), dtype=torch.int32, device=dev)
+        ws = self._workspace(grid_workspace_size(T, C, B, N), workspace)
+        st = lib().blink_grid(self.handle, _ptr(vis), _ptr(flags), _ptr(uvw_m), _ptr(freq_hz), T, C, P, B, N,
+                              float(pixel_scale), int(weighting), _ptr(grids), _ptr(counts), _ptr(wsum),
+                              _ptr(cell), _ptr(nout), _ptr(ws), ws.numel(), self._stream(stream))
+        _check(st, self.handle, "blink_grid")
+        return {"grids": grids, "counts": counts, "weight_sum": wsum, "cell_idx": cell, "n_out": nout}
+
+    def blink_ifft2d(self, grids, weight_sum=None, shift: bool = True, precision: int = PREC_FP32,
+                     out=None, workspace=None, stream=None):
+        """Dirty images Re(IDFT2(G))/W of complex64 grids [..., N, N]; returns float32 [..., N, N]."""
+        torch = self._torch()
+        self._require("grids", grids, torch.complex64)
+        N = int(grids.shape[-1])
+        if grids.shape[-2] != N:
+            raise ValueError("grids must be square")
+        n_img = grids.numel() // (N * N)
+        if weight_sum is not None:
+            self._require("weight_sum", weight_sum, torch.float64)
+            if weight_sum.numel() != n_img:
+                raise ValueError("weight_sum must hold one value per grid")
+        if out is None:
+            out = torch.empty(grids.shape, dtype=torch.float32, device=grids.device)
+        self._require("out", out, torch.float32, grids.shape)
+        ws = self._workspace(ifft2d_workspace_size(n_img, N, precision), workspace)
+        st = lib().blink_ifft2d(self.handle, _ptr(grids), _ptr(weight_sum), n_img, N, int(precision),
+                                int(bool(shift)), _ptr(out), _ptr(ws), ws.numel(), self._stream(stream))
+        _check(st, self.handle, "blink_ifft2d")
+        return out
+
+    def blink_image_batch(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float,
+                          weighting: int = 0, precision: int = PREC_FP32, shift: bool = True, out=None,
+                          weight_sum=None, n_out=None, workspace=None, stream=None):
+        """Fused gridding + inverse 2D FFT. Returns dict(images float32 [T][C][P][N][N],
+        weight_sum float64 [T][C][P], n_out int32 [T][C]) of device tensors."""
+        torch = self._torch()
+        T, C, P, B = vis.shape
+        N = int(grid_n)
+        self._require("vis", vis, torch.complex64)
+        if flags is not None:
+            self._require("flags", flags, torch.uint8, (T, C, B))
+        self._require("uvw_m", uvw_m, torch.float64, (T, B, 3))
+        self._require("freq_hz", freq_hz, torch.float64, (C,))
+        dev = vis.device
+        if out is None:
+            out = torch.empty((T, C, P, N, N), dtype=torch.float32, device=dev)
+        self._require("out", out, torch.float32, (T, C, P, N, N))
+        if weight_sum is None:
+            weight_sum = torch.empty((T, C, P), dtype=torch.float64, device=dev)
+        if n_out is None:
+            n_out = torch.empty((T, C), dtype=torch.int32, device=dev)
+        ws = self._workspace(image_batch_workspace_size(T, C, P, B, N, weighting, precision), workspace)
+        st = lib().blink_image_batch(self.handle, _ptr(vis), _ptr(flags), _ptr(uvw_m), _ptr(freq_hz), T, C, P,
+                                     B, N, float(pixel_scale), int(weighting), int(precision), int(bool(shift)),
+                                     _ptr(out), _ptr(weight_sum), _ptr(n_out), _ptr(ws), ws.numel(),
+                                     self._stream(stream))
+        _check(st, self.handle, "blink_image_batch")
+        return {"images": out, "weight_sum": weight_sum, "n_out": n_out}

@@ -1,0 +1,582 @@
+// api.hip — C ABI of libblink.so (declared in include/blink.h): argument checks, workspace
+// layout, chunking over (time, channel) pairs and kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "blink.h"
+#include "launch.hpp"
+
+struct blink_ctx_s {
+  int device = 0;
+  float2* tw_base = nullptr;      // twiddle tables for N = 8 .. 4096, concatenated
+  float2* tw[13] = {};
+  bool broken = false;
+  std::string err;
+  // kernel timing (blink_profile_enable)
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> records[BLINK_KERNEL_COUNT];
+  std::vector<hipEvent_t> spare;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int log2_exact(int n) {
+  if (n < BLINK_MIN_GRID || n > BLINK_MAX_GRID || (n & (n - 1))) return -1;
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+blink_status fail(blink_ctx ctx, blink_status st, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+blink_status hip_fail(blink_ctx ctx, hipError_t e, const char* where) {
+  if (ctx) ctx->broken = true;
+  return fail(ctx, BLINK_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+// Sets the context's device for the duration of a call and restores the caller's.
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+hipEvent_t take_event(blink_ctx ctx) {
+  if (!ctx->spare.empty()) {
+    hipEvent_t e = ctx->spare.back();
+    ctx->spare.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void release_records(blink_ctx ctx) {
+  for (auto& v : ctx->records) {
+    for (auto& pr : v) {
+      ctx->spare.push_back(pr.first);
+      ctx->spare.push_back(pr.second);
+    }
+    v.clear();
+  }
+}
+
+// Brackets one kernel launch with events when timing is enabled.
+struct KernelTimer {
+  blink_ctx ctx;
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  KernelTimer(blink_ctx c, int k, hipStream_t st) : ctx(c), kind(k), s(st) {
+    if (!ctx->profiling) return;
+    a = take_event(ctx);
+    b = take_event(ctx);
+    if (a && b) (void)hipEventRecord(a, s);
+  }
+  ~KernelTimer() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, s);
+    ctx->records[kind].emplace_back(a, b);
+  }
+};
+
+bool mul_ok(size_t a, size_t b, size_t* out) {
+  if (a != 0 && b > SIZE_MAX / a) return false;
+  *out = a * b;
+  return true;
+}
+
+// ---------------------------------------------------------------- workspace layouts
+struct Carve {
+  size_t off = 0;
+  bool ok = true;
+  size_t take(size_t count, size_t elem) {
+    size_t bytes;
+    if (!mul_ok(count, elem, &bytes)) ok = false;
+    size_t at = off;
+    off = align_up(off + (ok ? bytes : 0));
+    return at;
+  }
+};
+
+struct BinLayout {
+  size_t plc, off, kept, occ;
+};
+
+BinLayout carve_bins(Carve& c, size_t Q, size_t P, size_t B, size_t nstrips) {
+  BinLayout L;
+  L.plc = c.take(Q, 2 * B * sizeof(int2));
+  L.off = c.take(Q, (nstrips + 1) * sizeof(int));
+  L.kept = c.take(Q, sizeof(int));
+  L.occ = c.take(Q, P * sizeof(int));
+  return L;
+}
+
+struct ImageLayout {
+  BinLayout bins;
+  size_t inv, H, total;
+  bool ok;
+};
+
+ImageLayout image_layout(size_t Q, int P, int B, int logn, int uniform) {
+  const size_t N = size_t(1) << logn;
+  const size_t nstrips = (N / 2) / blink::col_strip_width(logn, uniform != 0);
+  Carve c;
+  ImageLayout L;
+  L.bins = carve_bins(c, Q, P, B, nstrips);
+  L.inv = c.take(Q * P, sizeof(float));
+  L.H = c.take(Q * P, N * (N / 2) * sizeof(float2));
+  L.total = c.off;
+  L.ok = c.ok;
+  return L;
+}
+
+struct GridLayout {
+  BinLayout bins;
+  size_t total;
+  bool ok;
+};
+
+GridLayout grid_layout(size_t Q, int P, int B, int logn) {
+  const size_t N = size_t(1) << logn;
+  const size_t nstrips = N / blink::grid_strip_width(logn);
+  Carve c;
+  GridLayout L;
+  L.bins = carve_bins(c, Q, P, B, nstrips);
+  L.total = c.off;
+  L.ok = c.ok;
+  return L;
+}
+
+struct FftLayout {
+  size_t inv, H, total;
+  bool ok;
+};
+
+FftLayout fft_layout(size_t n_img, int logn) {
+  const size_t N = size_t(1) << logn;
+  Carve c;
+  FftLayout L;
+  L.inv = c.take(n_img, sizeof(float));
+  L.H = c.take(n_img, N * (N / 2) * sizeof(float2));
+  L.total = c.off;
+  L.ok = c.ok;
+  return L;
+}
+
+template <class F>
+size_t largest_fitting_chunk(size_t n_tc, size_t ws_bytes, F total_for) {
+  // total_for(Q) is increasing in Q; find the largest Q <= n_tc that fits.
+  size_t lo = 0, hi = n_tc;
+  while (lo < hi) {
+    size_t mid = lo + (hi - lo + 1) / 2;
+    if (total_for(mid) <= ws_bytes) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Shared argument checks of blink_grid and blink_image_batch. Order: sizes, enums, ctx, pointers.
+blink_status check_problem(blink_ctx ctx, const void* vis, const void* uvw, const void* freq, int T,
+                           int C, int P, int B, int grid_n, double pixel_scale, int weighting,
+                           const void* out, void* ws, int* logn) {
+  if (T < 0 || C < 0 || P < 1 || B < 0)
+    return fail(ctx, BLINK_ERR_ARG, "negative size (T=%d C=%d P=%d B=%d) or P < 1", T, C, P, B);
+  if (B > (1 << 30)) return fail(ctx, BLINK_ERR_SIZE, "B=%d exceeds 2^30 baselines", B);
+  *logn = log2_exact(grid_n);
+  if (*logn < 0)
+    return fail(ctx, BLINK_ERR_SIZE, "grid_n=%d is not a power of two in [%d, %d]", grid_n,
+                BLINK_MIN_GRID, BLINK_MAX_GRID);
+  if (weighting != BLINK_WEIGHT_NATURAL && weighting != BLINK_WEIGHT_UNIFORM)
+    return fail(ctx, BLINK_ERR_ARG, "unknown weighting %d", weighting);
+  if (!(pixel_scale > 0.0) || !std::isfinite(pixel_scale))
+    return fail(ctx, BLINK_ERR_ARG, "pixel_scale must be finite and > 0");
+  if (!ctx) return BLINK_ERR_ARG;
+  if (ctx->broken) return fail(ctx, BLINK_ERR_STATE, "context unusable after an earlier HIP error");
+  const bool empty = (size_t)T * C == 0;
+  if (!empty && (!vis && B > 0)) return fail(ctx, BLINK_ERR_ARG, "vis is NULL");
+  if (!empty && (!uvw && B > 0)) return fail(ctx, BLINK_ERR_ARG, "uvw_m is NULL");
+  if (!empty && !freq) return fail(ctx, BLINK_ERR_ARG, "freq_hz is NULL");
+  if (!empty && !out) return fail(ctx, BLINK_ERR_ARG, "output array is NULL");
+  if (!empty && !ws) return fail(ctx, BLINK_ERR_ARG, "workspace is NULL");
+  if ((uintptr_t)ws % kAlign) return fail(ctx, BLINK_ERR_ARG, "workspace is not 256-byte aligned");
+  return BLINK_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+int blink_version(void) { return 100; }
+
+const char* blink_status_string(blink_status s) {
+  switch (s) {
+    case BLINK_OK: return "ok";
+    case BLINK_ERR_ARG: return "invalid argument";
+    case BLINK_ERR_SIZE: return "unsupported size or workspace too small";
+    case BLINK_ERR_NOMEM: return "out of memory";
+    case BLINK_ERR_HIP: return "HIP runtime error";
+    case BLINK_ERR_STATE: return "context unusable";
+  }
+  return "unknown status";
+}
+
+const char* blink_last_error(blink_ctx ctx) {
+  if (!ctx) return "no context";
+  return ctx->err.c_str();
+}
+
+blink_status blink_create(blink_ctx* out, int hip_device) {
+  if (!out) return BLINK_ERR_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return BLINK_ERR_HIP;
+  if (hip_device < 0 || hip_device >= count) return BLINK_ERR_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return BLINK_ERR_HIP;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return BLINK_ERR_HIP;
+  blink_ctx ctx = new (std::nothrow) blink_ctx_s;
+  if (!ctx) return BLINK_ERR_NOMEM;
+  ctx->device = hip_device;
+  DeviceGuard g(hip_device);
+  if (g.err != hipSuccess) {
+    delete ctx;
+    return BLINK_ERR_HIP;
+  }
+  size_t total = 0;
+  for (int l = 3; l <= 12; ++l) total += size_t(1) << l;
+  if (hipMalloc(&ctx->tw_base, total * sizeof(float2)) != hipSuccess) {
+    delete ctx;
+    return BLINK_ERR_NOMEM;
+  }
+  size_t off = 0;
+  hipError_t e = hipSuccess;
+  for (int l = 3; l <= 12 && e == hipSuccess; ++l) {
+    ctx->tw[l] = ctx->tw_base + off;
+    e = blink::launch_twiddles(ctx->tw[l], 1 << l, nullptr);
+    off += size_t(1) << l;
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    (void)hipFree(ctx->tw_base);
+    delete ctx;
+    return BLINK_ERR_HIP;
+  }
+  *out = ctx;
+  return BLINK_OK;
+}
+
+blink_status blink_destroy(blink_ctx ctx) {
+  if (!ctx) return BLINK_OK;
+  {
+    DeviceGuard g(ctx->device);
+    if (ctx->tw_base) (void)hipFree(ctx->tw_base);
+    release_records(ctx);
+    for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
+  }
+  delete ctx;
+  return BLINK_OK;
+}
+
+blink_status blink_grid_workspace_size(int T, int C, int B, int grid_n, size_t* bytes) {
+  if (!bytes || T < 0 || C < 0 || B < 0) return BLINK_ERR_ARG;
+  const int logn = log2_exact(grid_n);
+  if (logn < 0) return BLINK_ERR_SIZE;
+  // P only sizes the small occupancy array; the maximum supported polarisation count is 4.
+  GridLayout L = grid_layout((size_t)T * C, 4, B, logn);
+  if (!L.ok) return BLINK_ERR_SIZE;
+  *bytes = L.total;
+  return BLINK_OK;
+}
+
+blink_status blink_ifft2d_workspace_size(int n_img, int grid_n, int precision, size_t* bytes) {
+  if (!bytes || n_img < 0) return BLINK_ERR_ARG;
+  if (precision != BLINK_PREC_FP32) return BLINK_ERR_ARG;
+  const int logn = log2_exact(grid_n);
+  if (logn < 0) return BLINK_ERR_SIZE;
+  FftLayout L = fft_layout((size_t)n_img, logn);
+  if (!L.ok) return BLINK_ERR_SIZE;
+  *bytes = L.total;
+  return BLINK_OK;
+}
+
+blink_status blink_image_batch_workspace_size(int T, int C, int P, int B, int grid_n, int weighting,
+                                              int precision, size_t* bytes) {
+  if (!bytes || T < 0 || C < 0 || P < 1 || B < 0) return BLINK_ERR_ARG;
+  if (weighting != BLINK_WEIGHT_NATURAL && weighting != BLINK_WEIGHT_UNIFORM) return BLINK_ERR_ARG;
+  if (precision != BLINK_PREC_FP32) return BLINK_ERR_ARG;
+  const int logn = log2_exact(grid_n);
+  if (logn < 0) return BLINK_ERR_SIZE;
+  ImageLayout L = image_layout((size_t)T * C, P, B, logn, weighting);
+  if (!L.ok) return BLINK_ERR_SIZE;
+  *bytes = L.total;
+  return BLINK_OK;
+}
+
+blink_status blink_grid(blink_ctx ctx, const blink_cf32* vis, const uint8_t* flags, const double* uvw_m,
+                        const double* freq_hz, int T, int C, int P, int B, int grid_n, double pixel_scale,
+                        int weighting, blink_cf32* grids, int32_t* counts, double* weight_sum,
+                        int32_t* cell_idx, int32_t* n_out, void* workspace, size_t workspace_bytes,
+                        void* hip_stream) {
+  int logn = 0;
+  blink_status st = check_problem(ctx, vis, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting,
+                                  grids, workspace, &logn);
+  if (st != BLINK_OK) return st;
+  if (P > 4) return fail(ctx, BLINK_ERR_ARG, "blink_grid supports P <= 4 polarisations");
+  const size_t n_tc = (size_t)T * C;
+  if (n_tc == 0) return BLINK_OK;
+  const size_t Q = largest_fitting_chunk(n_tc, workspace_bytes,
+                                         [&](size_t q) { return grid_layout(q, P, B, logn).total; });
+  if (Q == 0) {
+    return fail(ctx, BLINK_ERR_SIZE, "workspace of %zu bytes is smaller than one (t,c) pair needs (%zu)",
+                workspace_bytes, grid_layout(1, P, B, logn).total);
+  }
+  if (Q * P > (size_t)INT32_MAX) return fail(ctx, BLINK_ERR_SIZE, "batch too large");
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t N = size_t(1) << logn;
+  const int S = blink::grid_strip_width(logn);
+  int log_s = 0;
+  while ((1 << log_s) < S) ++log_s;
+  char* ws = (char*)workspace;
+  GridLayout L = grid_layout(Q, P, B, logn);
+  for (size_t tc0 = 0; tc0 < n_tc; tc0 += Q) {
+    const int q = (int)((n_tc - tc0) < Q ? (n_tc - tc0) : Q);
+    blink::BinArgs ba{};
+    ba.uvw = uvw_m;
+    ba.freq = freq_hz;
+    ba.flags = flags;
+    ba.tc0 = (int)tc0;
+    ba.Q = q;
+    ba.C = C;
+    ba.B = B;
+    ba.logn = logn;
+    ba.log_strip = log_s;
+    ba.ku_limit = (int)N;
+    ba.P = P;
+    ba.pixel_scale = pixel_scale;
+    ba.plc = (int2*)(ws + L.bins.plc);
+    ba.strip_off = (int*)(ws + L.bins.off);
+    ba.n_kept = (int*)(ws + L.bins.kept);
+    ba.occ = (int*)(ws + L.bins.occ);
+    ba.cell_idx = cell_idx;
+    ba.n_out = n_out;
+    hipError_t e;
+    {
+      KernelTimer kt(ctx, BLINK_KERNEL_BIN, s);
+      e = blink::launch_bin(ba, s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "bin kernel");
+    blink::GridArgs ga{};
+    ga.vis = (const float2*)vis + tc0 * P * B;
+    ga.plc = ba.plc;
+    ga.strip_off = ba.strip_off;
+    ga.Q = q;
+    ga.P = P;
+    ga.B = B;
+    ga.logn = logn;
+    ga.uniform = weighting;
+    ga.grids = (float2*)grids + tc0 * P * N * N;
+    ga.counts = counts ? counts + tc0 * N * N : nullptr;
+    ga.occ = ba.occ;
+    {
+      KernelTimer kt(ctx, BLINK_KERNEL_GRID, s);
+      e = blink::launch_grid_full(ga, s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "grid kernel");
+    if (weight_sum) {
+      KernelTimer kt(ctx, BLINK_KERNEL_WEIGHTS, s);
+      e = blink::launch_image_weights(ba.n_kept, ba.occ, weighting, P, q * P, nullptr,
+                                      weight_sum + tc0 * P, s);
+      if (e != hipSuccess) return hip_fail(ctx, e, "weights kernel");
+    }
+  }
+  return BLINK_OK;
+}
+
+blink_status blink_ifft2d(blink_ctx ctx, const blink_cf32* grids, const double* weight_sum, int n_img,
+                          int grid_n, int precision, int shift, float* images, void* workspace,
+                          size_t workspace_bytes, void* hip_stream) {
+  if (n_img < 0) return fail(ctx, BLINK_ERR_ARG, "n_img < 0");
+  const int logn = log2_exact(grid_n);
+  if (logn < 0) return fail(ctx, BLINK_ERR_SIZE, "grid_n=%d is not a power of two in [8, 4096]", grid_n);
+  if (precision != BLINK_PREC_FP32) return fail(ctx, BLINK_ERR_ARG, "unsupported precision %d", precision);
+  if (!ctx) return BLINK_ERR_ARG;
+  if (ctx->broken) return fail(ctx, BLINK_ERR_STATE, "context unusable after an earlier HIP error");
+  if (n_img == 0) return BLINK_OK;
+  if (!grids || !images || !workspace) return fail(ctx, BLINK_ERR_ARG, "NULL grids, images or workspace");
+  if ((uintptr_t)workspace % kAlign) return fail(ctx, BLINK_ERR_ARG, "workspace is not 256-byte aligned");
+  const size_t Q = largest_fitting_chunk((size_t)n_img, workspace_bytes,
+                                         [&](size_t q) { return fft_layout(q, logn).total; });
+  if (Q == 0)
+    return fail(ctx, BLINK_ERR_SIZE, "workspace of %zu bytes is smaller than one image needs (%zu)",
+                workspace_bytes, fft_layout(1, logn).total);
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t N = size_t(1) << logn;
+  char* ws = (char*)workspace;
+  FftLayout L = fft_layout(Q, logn);
+  for (size_t i0 = 0; i0 < (size_t)n_img; i0 += Q) {
+    const int q = (int)(((size_t)n_img - i0) < Q ? ((size_t)n_img - i0) : Q);
+    float* inv = (float*)(ws + L.inv);
+    float2* H = (float2*)(ws + L.H);
+    hipError_t e;
+    {
+      KernelTimer kt(ctx, BLINK_KERNEL_WEIGHTS, s);
+      e = blink::launch_user_weights(weight_sum ? weight_sum + i0 : nullptr, q, inv, s);
+    }
+    if (e == hipSuccess) {
+      KernelTimer kt(ctx, BLINK_KERNEL_DENSE_COLFFT, s);
+      e = blink::launch_dense_colfft((const float2*)grids + i0 * N * N, q, logn, shift != 0, H, ctx->tw[logn], s);
+    }
+    if (e == hipSuccess) {
+      KernelTimer kt(ctx, BLINK_KERNEL_ROW_FFT, s);
+      e = blink::launch_row_c2r(H, inv, q, logn, images + i0 * N * N, ctx->tw[logn], s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "ifft2d kernels");
+  }
+  return BLINK_OK;
+}
+
+blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8_t* flags, const double* uvw_m,
+                               const double* freq_hz, int T, int C, int P, int B, int grid_n, double pixel_scale,
+                               int weighting, int precision, int shift, float* images, double* weight_sum,
+                               int32_t* n_out, void* workspace, size_t workspace_bytes, void* hip_stream) {
+  int logn = 0;
+  blink_status st = check_problem(ctx, vis, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting,
+                                  images, workspace, &logn);
+  if (st != BLINK_OK) return st;
+  if (precision != BLINK_PREC_FP32) return fail(ctx, BLINK_ERR_ARG, "unsupported precision %d", precision);
+  const size_t n_tc = (size_t)T * C;
+  if (n_tc == 0) return BLINK_OK;
+  const size_t Q = largest_fitting_chunk(n_tc, workspace_bytes,
+                                         [&](size_t q) { return image_layout(q, P, B, logn, weighting).total; });
+  if (Q == 0)
+    return fail(ctx, BLINK_ERR_SIZE, "workspace of %zu bytes is smaller than one (t,c) pair needs (%zu)",
+                workspace_bytes, image_layout(1, P, B, logn, weighting).total);
+  if (Q * P > (size_t)INT32_MAX) return fail(ctx, BLINK_ERR_SIZE, "batch too large");
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t N = size_t(1) << logn;
+  const int S = blink::col_strip_width(logn, weighting == BLINK_WEIGHT_UNIFORM);
+  int log_s = 0;
+  while ((1 << log_s) < S) ++log_s;
+  char* ws = (char*)workspace;
+  ImageLayout L = image_layout(Q, P, B, logn, weighting);
+  for (size_t tc0 = 0; tc0 < n_tc; tc0 += Q) {
+    const int q = (int)((n_tc - tc0) < Q ? (n_tc - tc0) : Q);
+    blink::BinArgs ba{};
+    ba.uvw = uvw_m;
+    ba.freq = freq_hz;
+    ba.flags = flags;
+    ba.tc0 = (int)tc0;
+    ba.Q = q;
+    ba.C = C;
+    ba.B = B;
+    ba.logn = logn;
+    ba.log_strip = log_s;
+    ba.ku_limit = (int)(N / 2);
+    ba.P = P;
+    ba.pixel_scale = pixel_scale;
+    ba.plc = (int2*)(ws + L.bins.plc);
+    ba.strip_off = (int*)(ws + L.bins.off);
+    ba.n_kept = (int*)(ws + L.bins.kept);
+    ba.occ = (int*)(ws + L.bins.occ);
+    ba.cell_idx = nullptr;
+    ba.n_out = n_out;
+    hipError_t e;
+    {
+      KernelTimer kt(ctx, BLINK_KERNEL_BIN, s);
+      e = blink::launch_bin(ba, s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "bin kernel");
+    blink::ColArgs ca{};
+    ca.vis = (const float2*)vis + tc0 * P * B;
+    ca.plc = ba.plc;
+    ca.strip_off = ba.strip_off;
+    ca.Q = q;
+    ca.P = P;
+    ca.B = B;
+    ca.logn = logn;
+    ca.uniform = weighting;
+    ca.shift = shift != 0;
+    ca.H = (float2*)(ws + L.H);
+    ca.occ = ba.occ;
+    {
+      KernelTimer kt(ctx, BLINK_KERNEL_GRID_COLFFT, s);
+      e = blink::launch_grid_colfft(ca, ctx->tw[logn], s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "grid+column FFT kernel");
+    float* inv = (float*)(ws + L.inv);
+    {
+      KernelTimer kt(ctx, BLINK_KERNEL_WEIGHTS, s);
+      e = blink::launch_image_weights(ba.n_kept, ba.occ, weighting, P, q * P, inv,
+                                      weight_sum ? weight_sum + tc0 * P : nullptr, s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "weights kernel");
+    {
+      KernelTimer kt(ctx, BLINK_KERNEL_ROW_FFT, s);
+      e = blink::launch_row_c2r(ca.H, inv, q * P, logn, images + tc0 * P * N * N, ctx->tw[logn], s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "row FFT kernel");
+  }
+  return BLINK_OK;
+}
+
+blink_status blink_profile_enable(blink_ctx ctx, int enable) {
+  if (!ctx) return BLINK_ERR_ARG;
+  release_records(ctx);
+  ctx->profiling = enable != 0;
+  return BLINK_OK;
+}
+
+blink_status blink_profile_read(blink_ctx ctx, int kernel, double* total_ms, int64_t* launches) {
+  if (!ctx || !total_ms || !launches || kernel < 0 || kernel >= BLINK_KERNEL_COUNT) return BLINK_ERR_ARG;
+  DeviceGuard g(ctx->device);
+  double sum = 0.0;
+  for (auto& pr : ctx->records[kernel]) {
+    hipError_t e = hipEventSynchronize(pr.second);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    if (e != hipSuccess) return hip_fail(ctx, e, "blink_profile_read");
+    sum += ms;
+  }
+  *total_ms = sum;
+  *launches = (int64_t)ctx->records[kernel].size();
+  return BLINK_OK;
+}
+
+}  // extern "C"

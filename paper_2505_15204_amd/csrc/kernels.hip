@@ -1,0 +1,578 @@
+// kernels.hip — gfx950 kernels of the batched dirty-imaging path.
+//
+//   k_twiddles       FP64 sincospi -> FP32 twiddle table
+//   k_bin            cell indices (FP64 product + rint), flags, out-of-grid drop, counting sort
+//                    of the placements into column strips (Section 6.2.4 gridding, one
+//                    workgroup per (time, channel), shared by the polarisations)
+//   k_grid_full      LDS-private strip grid -> complex grid in HBM (plain stores), counts
+//   k_grid_colfft    LDS-private strip grid -> inverse FFT along v -> half-spectrum H
+//   k_dense_colfft   Hermitian part of a dense grid -> inverse FFT along v -> H
+//   k_row_c2r        two H rows -> Hermitian-extended inverse FFT along u -> two image rows
+//
+// The dirty image is I = Re(IDFT2(G)) / W (Section 4, Eq. 5). The shift of Section 6.2.4 is
+// folded into the input as the modulation (-1)^(ku + kv), which for even N moves the phase
+// centre to pixel (N/2, N/2). Because the grid is Hermitian only the columns ku < N/2 are
+// transformed along v; the row pass rebuilds the other half by symmetry, and H's column 0 packs
+// the two real-valued columns ku = 0 (real part) and ku = N/2 (imaginary part).
+#include <hip/hip_runtime.h>
+
+#include "fft_device.hpp"
+#include "launch.hpp"
+
+namespace blink {
+
+constexpr int kLdsBytes = 160 * 1024;
+constexpr double kSpeedOfLight = 299792458.0;
+
+__host__ __device__ constexpr int pow2_floor(int x) {
+  int p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// ---------------------------------------------------------------- configuration
+template <int LOGN, bool UNIFORM>
+struct ColCfg {
+  using P = FftPlan<LOGN>;
+  static constexpr int N = P::N;
+  static constexpr int per_col = P::NP * 8 + (UNIFORM ? N * 4 : 0);
+  static constexpr int avail = kLdsBytes - N * 8 - 1024;
+  static constexpr int S = pow2_floor(cmin(cmin(N / 2, 1024 / P::T), avail / per_col));
+  static constexpr int THREADS = S * P::T;
+};
+
+template <int LOGN>
+struct GridCfg {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int S = pow2_floor(cmin(N, (128 * 1024) / (N * 12)));
+  static constexpr int THREADS = 256;
+};
+
+template <int LOGN>
+struct RowCfg {
+  using P = FftPlan<LOGN>;
+  static constexpr int TPB = cmin(P::N / 2, (256 / P::T) > 0 ? 256 / P::T : 1);
+  static constexpr int THREADS = TPB * P::T;
+};
+
+// ---------------------------------------------------------------- twiddles
+__global__ void k_twiddles(float2* tw, int n) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s, c;
+  sincospi(2.0 * (double)j / (double)n, &s, &c);   // exact argument: 2j/n is a dyadic rational
+  tw[j] = make_float2((float)c, (float)s);
+}
+
+hipError_t launch_twiddles(float2* tw, int n, hipStream_t s) {
+  k_twiddles<<<(n + 255) / 256, 256, 0, s>>>(tw, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- block scan
+// Exclusive scan of v[0..n) in place with 1024 threads (n <= 4096); v[n] receives the total.
+__device__ void block_exclusive_scan_1024(int* v, int n, int* s_wave) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int base = tid * 4;
+  int a[4];
+  int tsum = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    a[j] = (base + j < n) ? v[base + j] : 0;
+    tsum += a[j];
+  }
+  int x = tsum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) s_wave[w] = x;
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int i = 0; i < 16; ++i) {
+      int t = s_wave[i];
+      s_wave[i] = run;
+      run += t;
+    }
+    s_wave[16] = run;
+  }
+  __syncthreads();
+  int excl = s_wave[w] + x - tsum;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (base + j < n) v[base + j] = excl;
+    excl += a[j];
+  }
+  if (tid == 0) v[n] = s_wave[16];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- binning
+// Nearest cell of one visibility. Returns 1 when kept (and sets iu, iv), 0 when out of grid.
+__device__ __forceinline__ int nearest_cell(double u, double v, double k, double half, int& iu, int& iv) {
+  const double ru = rint(u * k);      // one IEEE double product, round half to even
+  const double rv = rint(v * k);
+  if (!(fabs(ru) < half && fabs(rv) < half)) return 0;   // NaN lands here too
+  iu = (int)ru;
+  iv = (int)rv;
+  return 1;
+}
+
+constexpr int kBinThreads = 1024;
+constexpr int kMaxStrips = 4096;
+
+__global__ __launch_bounds__(kBinThreads) void k_bin(BinArgs a) {
+  __shared__ int s_cnt[kMaxStrips + 1];
+  __shared__ int s_wave[17];
+  __shared__ int s_red[2];
+  const int tcl = blockIdx.x;
+  const long tc = (long)a.tc0 + tcl;
+  const int t = (int)(tc / a.C), c = (int)(tc % a.C);
+  const int N = 1 << a.logn, mask = N - 1;
+  const int nstrips = a.ku_limit >> a.log_strip;
+  const double k = (a.freq[c] / kSpeedOfLight) * ((double)N * a.pixel_scale);
+  const double half = (double)(N / 2);
+  const double* uvw = a.uvw + (size_t)t * a.B * 3;
+  const uint8_t* fl = a.flags ? a.flags + (size_t)tc * a.B : nullptr;
+
+  for (int i = threadIdx.x; i <= nstrips; i += blockDim.x) s_cnt[i] = 0;
+  if (threadIdx.x < 2) s_red[threadIdx.x] = 0;
+  __syncthreads();
+
+  int kept = 0, outside = 0;
+  for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
+    int cell = -1;
+    if (!(fl && fl[b])) {
+      int iu, iv;
+      if (nearest_cell(uvw[3 * b], uvw[3 * b + 1], k, half, iu, iv)) {
+        const int ku1 = iu & mask, kv1 = iv & mask, ku2 = (-iu) & mask;
+        cell = kv1 * N + ku1;
+        ++kept;
+        if (ku1 < a.ku_limit) atomicAdd(&s_cnt[ku1 >> a.log_strip], 1);
+        if (ku2 < a.ku_limit) atomicAdd(&s_cnt[ku2 >> a.log_strip], 1);
+      } else {
+        cell = -2;
+        ++outside;
+      }
+    }
+    if (a.cell_idx) a.cell_idx[(size_t)tc * a.B + b] = cell;
+  }
+  // block reduction of the two counters
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    kept += __shfl_down(kept, off, 64);
+    outside += __shfl_down(outside, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&s_red[0], kept);
+    atomicAdd(&s_red[1], outside);
+  }
+  __syncthreads();
+  block_exclusive_scan_1024(s_cnt, nstrips, s_wave);
+  int* off = a.strip_off + (size_t)tcl * (nstrips + 1);
+  for (int i = threadIdx.x; i <= nstrips; i += blockDim.x) off[i] = s_cnt[i];
+  if (threadIdx.x == 0) {
+    a.n_kept[tcl] = s_red[0];
+    if (a.n_out) a.n_out[tc] = s_red[1];
+  }
+  if (threadIdx.x < a.P) a.occ[(size_t)tcl * a.P + threadIdx.x] = 0;
+  __syncthreads();
+
+  int2* plc = a.plc + (size_t)tcl * 2 * a.B;
+  for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
+    if (fl && fl[b]) continue;
+    int iu, iv;
+    if (!nearest_cell(uvw[3 * b], uvw[3 * b + 1], k, half, iu, iv)) continue;
+    const int ku1 = iu & mask, kv1 = iv & mask;
+    const int ku2 = (-iu) & mask, kv2 = (-iv) & mask;
+    if (ku1 < a.ku_limit) {
+      int pos = atomicAdd(&s_cnt[ku1 >> a.log_strip], 1);
+      plc[pos] = make_int2(kv1 * N + ku1, b);
+    }
+    if (ku2 < a.ku_limit) {
+      int pos = atomicAdd(&s_cnt[ku2 >> a.log_strip], 1);
+      plc[pos] = make_int2(kv2 * N + ku2, (int)((unsigned)b | 0x80000000u));
+    }
+  }
+}
+
+hipError_t launch_bin(const BinArgs& a, hipStream_t s) {
+  if (a.Q <= 0) return hipSuccess;
+  k_bin<<<a.Q, kBinThreads, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- scatter into an LDS strip
+// Accumulates the placements of strip `strip` of one (t,c) pair into the LDS strip buffer
+// (column c at sbuf[c*stride + pad(kv)] when PADDED, else sbuf[c*stride + kv]).
+template <int LOGN, int S, bool PADDED, bool COUNT>
+__device__ __forceinline__ void scatter_strip(const int2* __restrict__ plc, int o0, int o1,
+                                              const float2* __restrict__ V, int strip, int stride,
+                                              bool modulate, float2* sbuf, unsigned* scnt) {
+  constexpr int N = 1 << LOGN;
+  for (int i = o0 + (int)threadIdx.x; i < o1; i += blockDim.x) {
+    const int2 r = plc[i];
+    const int kv = r.x >> LOGN, ku = r.x & (N - 1);
+    const int b = r.y & 0x7fffffff;
+    float2 val = V[b];
+    if (r.y < 0) val.y = -val.y;
+    if (modulate && ((kv + ku) & 1)) {
+      val.x = -val.x;
+      val.y = -val.y;
+    }
+    const int col = ku - strip * S;
+    float2* dst = sbuf + col * stride + (PADDED ? pad_index(kv) : kv);
+    atomicAdd(&dst->x, val.x);
+    atomicAdd(&dst->y, val.y);
+    if constexpr (COUNT) atomicAdd(&scnt[col * N + kv], 1u);
+  }
+}
+
+// Uniform weighting: cell mean; returns this thread's occupied-cell count (weighted).
+template <int LOGN, int S, bool PADDED>
+__device__ __forceinline__ int uniform_divide(float2* sbuf, const unsigned* scnt, int stride, int col_weight0,
+                                              int col_weight) {
+  constexpr int N = 1 << LOGN;
+  int occ = 0;
+  for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
+    const int col = i >> LOGN, kv = i & (N - 1);
+    const unsigned n = scnt[i];
+    if (n) {
+      float2* p = sbuf + col * stride + (PADDED ? pad_index(kv) : kv);
+      const float inv = 1.0f / (float)n;
+      p->x *= inv;
+      p->y *= inv;
+      occ += (col == 0) ? col_weight0 : col_weight;
+    }
+  }
+  return occ;
+}
+
+__device__ __forceinline__ void block_add_to_global(int val, int* s_tmp, int* dst) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) val += __shfl_down(val, off, 64);
+  if ((threadIdx.x & 63) == 0 && val) atomicAdd(s_tmp, val);
+  __syncthreads();
+  if (threadIdx.x == 0 && *s_tmp) atomicAdd(dst, *s_tmp);
+}
+
+// ---------------------------------------------------------------- full grid (blink_grid)
+template <int LOGN, bool UNIFORM>
+__global__ __launch_bounds__(256) void k_grid_full(GridArgs a) {
+  constexpr int N = 1 << LOGN;
+  constexpr int S = GridCfg<LOGN>::S;
+  __shared__ float2 sbuf[S * N];
+  __shared__ unsigned scnt[S * N];
+  __shared__ int s_tmp;
+  const int img = blockIdx.x, strip = blockIdx.y;
+  const int tcl = img / a.P, p = img - tcl * a.P;
+  const int nstrips = N / S;
+  for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
+    sbuf[i] = make_float2(0.f, 0.f);
+    scnt[i] = 0u;
+  }
+  if (threadIdx.x == 0) s_tmp = 0;
+  __syncthreads();
+  const int* so = a.strip_off + (size_t)tcl * (nstrips + 1);
+  scatter_strip<LOGN, S, false, true>(a.plc + (size_t)tcl * 2 * a.B, so[strip], so[strip + 1],
+                                      a.vis + (size_t)img * a.B, strip, N, false, sbuf, scnt);
+  __syncthreads();
+  if constexpr (UNIFORM) {
+    int occ = uniform_divide<LOGN, S, false>(sbuf, scnt, N, 1, 1);
+    block_add_to_global(occ, &s_tmp, a.occ + img);
+    __syncthreads();
+  }
+  float2* G = a.grids + (size_t)img * N * N;
+  for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
+    const int kv = i / S, col = i % S;
+    G[(size_t)kv * N + strip * S + col] = sbuf[col * N + kv];
+  }
+  if (a.counts && p == 0) {
+    int32_t* cnt = a.counts + (size_t)tcl * N * N;
+    for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
+      const int kv = i / S, col = i % S;
+      cnt[(size_t)kv * N + strip * S + col] = (int32_t)scnt[col * N + kv];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- fused grid + column FFT
+template <int LOGN, bool UNIFORM>
+__global__ __launch_bounds__((ColCfg<LOGN, UNIFORM>::THREADS)) void k_grid_colfft(ColArgs a, const float2* __restrict__ twg) {
+  using P = FftPlan<LOGN>;
+  using Cfg = ColCfg<LOGN, UNIFORM>;
+  constexpr int N = P::N, T = P::T, S = Cfg::S, NP = P::NP;
+  __shared__ float2 sbuf[S * NP];
+  __shared__ float2 stw[N];
+  __shared__ unsigned scnt[UNIFORM ? S * N : 1];
+  __shared__ int s_tmp;
+  const int img = blockIdx.x, strip = blockIdx.y;
+  const int tcl = img / a.P;
+  const int nstrips = (N / 2) / S;
+  for (int i = threadIdx.x; i < S * NP; i += blockDim.x) sbuf[i] = make_float2(0.f, 0.f);
+  if constexpr (UNIFORM)
+    for (int i = threadIdx.x; i < S * N; i += blockDim.x) scnt[i] = 0u;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = twg[i];
+  if (threadIdx.x == 0) s_tmp = 0;
+  __syncthreads();
+  const int* so = a.strip_off + (size_t)tcl * (nstrips + 1);
+  scatter_strip<LOGN, S, true, UNIFORM>(a.plc + (size_t)tcl * 2 * a.B, so[strip], so[strip + 1],
+                                        a.vis + (size_t)img * a.B, strip, NP, a.shift != 0, sbuf, scnt);
+  __syncthreads();
+  if constexpr (UNIFORM) {
+    // Column 0 of the grid is its own mirror; every other column ku < N/2 stands for itself
+    // and its mirror N - ku, so its occupied cells count twice.
+    int occ = uniform_divide<LOGN, S, true>(sbuf, scnt, NP, strip == 0 ? 1 : 2, 2);
+    block_add_to_global(occ, &s_tmp, a.occ + img);
+    __syncthreads();
+  }
+  const int col = threadIdx.x / T, lt = threadIdx.x % T;
+  float2* cb = sbuf + col * NP;
+  float2 v[P::R];
+#pragma unroll
+  for (int m = 0; m < P::R; ++m) v[m] = cb[pad_index(lt + m * T)];
+  fft_inverse<LOGN, true>(v, cb, stw, lt, [](int, float2) {});
+  // H[img][y][strip*S + c]; column 0 carries (Re of the ku = 0 transform, ku = N/2 transform = 0).
+  float2* Hi = a.H + (size_t)img * N * (N / 2);
+  for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
+    const int y = i / S, c = i % S;
+    float2 val = sbuf[c * NP + pad_index(y)];
+    if (strip == 0 && c == 0) val.y = 0.f;
+    Hi[(size_t)y * (N / 2) + strip * S + c] = val;
+  }
+}
+
+// ---------------------------------------------------------------- dense grid column FFT
+template <int LOGN>
+__global__ __launch_bounds__((ColCfg<LOGN, false>::THREADS)) void k_dense_colfft(const float2* __restrict__ grids, int shift,
+                                                                             float2* __restrict__ H,
+                                                                             const float2* __restrict__ twg) {
+  using P = FftPlan<LOGN>;
+  using Cfg = ColCfg<LOGN, false>;
+  constexpr int N = P::N, T = P::T, S = Cfg::S, NP = P::NP, mask = N - 1;
+  __shared__ float2 sbuf[S * NP];
+  __shared__ float2 stw[N];
+  const int img = blockIdx.x, strip = blockIdx.y;
+  const float2* G = grids + (size_t)img * N * N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = twg[i];
+  // Hermitian part Gh[kv][ku] = (G[kv][ku] + conj G[-kv][-ku]) / 2; column 0 packs
+  // Gh[.][0] + i Gh[.][N/2], whose transforms are both real.
+  for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
+    const int kv = i / S, c = i % S, ku = strip * S + c;
+    const int mkv = (N - kv) & mask;
+    const float2 g1 = G[(size_t)kv * N + ku];
+    const float2 g2 = G[(size_t)mkv * N + ((N - ku) & mask)];
+    float2 h = make_float2(0.5f * (g1.x + g2.x), 0.5f * (g1.y - g2.y));
+    if (ku == 0) {
+      const float2 n1 = G[(size_t)kv * N + N / 2];
+      const float2 n2 = G[(size_t)mkv * N + N / 2];
+      const float2 hn = make_float2(0.5f * (n1.x + n2.x), 0.5f * (n1.y - n2.y));
+      h = make_float2(h.x - hn.y, h.y + hn.x);
+    }
+    if (shift && ((kv + ku) & 1)) {
+      h.x = -h.x;
+      h.y = -h.y;
+    }
+    sbuf[c * NP + pad_index(kv)] = h;
+  }
+  __syncthreads();
+  const int col = threadIdx.x / T, lt = threadIdx.x % T;
+  float2* cb = sbuf + col * NP;
+  float2 v[P::R];
+#pragma unroll
+  for (int m = 0; m < P::R; ++m) v[m] = cb[pad_index(lt + m * T)];
+  fft_inverse<LOGN, true>(v, cb, stw, lt, [](int, float2) {});
+  float2* Hi = H + (size_t)img * N * (N / 2);
+  for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
+    const int y = i / S, c = i % S;
+    Hi[(size_t)y * (N / 2) + strip * S + c] = sbuf[c * NP + pad_index(y)];
+  }
+}
+
+// ---------------------------------------------------------------- weights
+__global__ void k_image_weights(const int* n_kept, const int* occ, int uniform, int P, int n_img,
+                                float* inv_w, double* weight_sum) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_img) return;
+  const int W = uniform ? occ[i] : 2 * n_kept[i / P];
+  if (inv_w) inv_w[i] = W > 0 ? (float)(1.0 / (double)W) : 0.f;
+  if (weight_sum) weight_sum[i] = (double)W;
+}
+
+hipError_t launch_image_weights(const int* n_kept, const int* occ, int uniform, int P, int n_img,
+                                float* inv_w, double* weight_sum, hipStream_t s) {
+  if (n_img <= 0) return hipSuccess;
+  k_image_weights<<<(n_img + 255) / 256, 256, 0, s>>>(n_kept, occ, uniform, P, n_img, inv_w, weight_sum);
+  return hipGetLastError();
+}
+
+__global__ void k_user_weights(const double* w, int n_img, float* inv_w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_img) return;
+  const double W = w ? w[i] : 1.0;
+  inv_w[i] = (W > 0.0 && isfinite(W)) ? (float)(1.0 / W) : 0.f;
+}
+
+hipError_t launch_user_weights(const double* w, int n_img, float* inv_w, hipStream_t s) {
+  if (n_img <= 0) return hipSuccess;
+  k_user_weights<<<(n_img + 255) / 256, 256, 0, s>>>(w, n_img, inv_w);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- row pass
+// Transform j of block (img, blk) handles rows y1 = 2 r, y2 = 2 r + 1 (r = blk*TPB + j).
+// Z[e] = Hf1[e] + i Hf2[e] where Hf is the Hermitian extension of the stored half row:
+// Hf[0] = Re H[0], Hf[N/2] = Im H[0], Hf[e] = H[e] (0 < e < N/2), Hf[e] = conj H[N-e].
+// The inverse FFT of Z is I1 + i I2 with both rows real.
+template <int LOGN>
+__global__ __launch_bounds__(RowCfg<LOGN>::THREADS) void k_row_c2r(const float2* __restrict__ H,
+                                                                 const float* __restrict__ inv_w,
+                                                                 float* __restrict__ images,
+                                                                 const float2* __restrict__ twg) {
+  using P = FftPlan<LOGN>;
+  constexpr int N = P::N, T = P::T, NP = P::NP, HALF = N / 2, TPB = RowCfg<LOGN>::TPB;
+  __shared__ float2 sbuf[TPB * NP];
+  __shared__ float2 stw[N];
+  const int img = blockIdx.x;
+  const int j = threadIdx.x / T, lt = threadIdx.x % T;
+  const int r = blockIdx.y * TPB + j;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = twg[i];
+  const float2* h1 = H + ((size_t)img * N + 2 * r) * HALF;
+  const float2* h2 = h1 + HALF;
+  float2 v[P::R];
+#pragma unroll
+  for (int m = 0; m < P::R; ++m) {
+    const int e = lt + m * T;
+    const int idx = (e < HALF) ? e : ((e == HALF) ? 0 : N - e);
+    const float2 a = h1[idx], b = h2[idx];
+    if (e == 0) v[m] = make_float2(a.x, b.x);
+    else if (e == HALF) v[m] = make_float2(a.y, b.y);
+    else if (e < HALF) v[m] = make_float2(a.x - b.y, a.y + b.x);
+    else v[m] = make_float2(a.x + b.y, b.x - a.y);
+  }
+  __syncthreads();   // twiddles in LDS
+  const float s = inv_w[img];
+  float* o1 = images + ((size_t)img * N + 2 * r) * N;
+  float* o2 = o1 + N;
+  fft_inverse<LOGN, false>(v, sbuf + j * NP, stw, lt, [&](int e, float2 z) {
+    o1[e] = z.x * s;
+    o2[e] = z.y * s;
+  });
+}
+
+// ---------------------------------------------------------------- dispatch
+template <template <int> class F, class... Args>
+static hipError_t by_logn(int logn, Args... args) {
+  switch (logn) {
+    case 3: return F<3>::run(args...);
+    case 4: return F<4>::run(args...);
+    case 5: return F<5>::run(args...);
+    case 6: return F<6>::run(args...);
+    case 7: return F<7>::run(args...);
+    case 8: return F<8>::run(args...);
+    case 9: return F<9>::run(args...);
+    case 10: return F<10>::run(args...);
+    case 11: return F<11>::run(args...);
+    case 12: return F<12>::run(args...);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int LOGN>
+struct StripWidths {
+  static hipError_t run(int* col_nat, int* col_uni, int* grid) {
+    *col_nat = ColCfg<LOGN, false>::S;
+    *col_uni = ColCfg<LOGN, true>::S;
+    *grid = GridCfg<LOGN>::S;
+    return hipSuccess;
+  }
+};
+
+int col_strip_width(int logn, bool uniform) {
+  int a = 0, b = 0, c = 0;
+  (void)by_logn<StripWidths>(logn, &a, &b, &c);
+  return uniform ? b : a;
+}
+
+int grid_strip_width(int logn) {
+  int a = 0, b = 0, c = 0;
+  (void)by_logn<StripWidths>(logn, &a, &b, &c);
+  return c;
+}
+
+template <int LOGN>
+struct GridFullL {
+  static hipError_t run(const GridArgs* a, hipStream_t s) {
+    constexpr int N = 1 << LOGN;
+    dim3 grid(a->Q * a->P, N / GridCfg<LOGN>::S);
+    if (a->uniform) k_grid_full<LOGN, true><<<grid, GridCfg<LOGN>::THREADS, 0, s>>>(*a);
+    else k_grid_full<LOGN, false><<<grid, GridCfg<LOGN>::THREADS, 0, s>>>(*a);
+    return hipGetLastError();
+  }
+};
+
+hipError_t launch_grid_full(const GridArgs& a, hipStream_t s) {
+  if (a.Q <= 0) return hipSuccess;
+  return by_logn<GridFullL>(a.logn, &a, s);
+}
+
+template <int LOGN>
+struct ColL {
+  static hipError_t run(const ColArgs* a, const float2* tw, hipStream_t s) {
+    constexpr int N = 1 << LOGN;
+    if (a->uniform) {
+      using Cfg = ColCfg<LOGN, true>;
+      dim3 grid(a->Q * a->P, (N / 2) / Cfg::S);
+      k_grid_colfft<LOGN, true><<<grid, Cfg::THREADS, 0, s>>>(*a, tw);
+    } else {
+      using Cfg = ColCfg<LOGN, false>;
+      dim3 grid(a->Q * a->P, (N / 2) / Cfg::S);
+      k_grid_colfft<LOGN, false><<<grid, Cfg::THREADS, 0, s>>>(*a, tw);
+    }
+    return hipGetLastError();
+  }
+};
+
+hipError_t launch_grid_colfft(const ColArgs& a, const float2* tw, hipStream_t s) {
+  if (a.Q <= 0) return hipSuccess;
+  return by_logn<ColL>(a.logn, &a, tw, s);
+}
+
+template <int LOGN>
+struct DenseL {
+  static hipError_t run(const float2* g, int n_img, int shift, float2* H, const float2* tw, hipStream_t s) {
+    constexpr int N = 1 << LOGN;
+    using Cfg = ColCfg<LOGN, false>;
+    dim3 grid(n_img, (N / 2) / Cfg::S);
+    k_dense_colfft<LOGN><<<grid, Cfg::THREADS, 0, s>>>(g, shift, H, tw);
+    return hipGetLastError();
+  }
+};
+
+hipError_t launch_dense_colfft(const float2* grids, int n_img, int logn, int shift, float2* H,
+                               const float2* tw, hipStream_t s) {
+  if (n_img <= 0) return hipSuccess;
+  return by_logn<DenseL>(logn, grids, n_img, shift, H, tw, s);
+}
+
+template <int LOGN>
+struct RowL {
+  static hipError_t run(const float2* H, const float* inv_w, int n_img, float* images, const float2* tw,
+                        hipStream_t s) {
+    constexpr int N = 1 << LOGN;
+    dim3 grid(n_img, (N / 2) / RowCfg<LOGN>::TPB);
+    k_row_c2r<LOGN><<<grid, RowCfg<LOGN>::THREADS, 0, s>>>(H, inv_w, images, tw);
+    return hipGetLastError();
+  }
+};
+
+hipError_t launch_row_c2r(const float2* H, const float* inv_w, int n_img, int logn, float* images,
+                          const float2* tw, hipStream_t s) {
+  if (n_img <= 0) return hipSuccess;
+  return by_logn<RowL>(logn, H, inv_w, n_img, images, tw, s);
+}
+
+}  // namespace blink

@@ -1,0 +1,72 @@
+// launch.hpp — host-side launchers of the imaging kernels (internal to libblink.so).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace blink {
+
+// Strip widths (columns per workgroup) chosen per grid size and weighting.
+int col_strip_width(int logn, bool uniform);     // fused grid + column FFT kernel
+int grid_strip_width(int logn);                   // full-grid gridding kernel
+
+// FP32 twiddle table exp(+2 pi i j / N), j < N, generated in FP64 on the device.
+hipError_t launch_twiddles(float2* tw, int n, hipStream_t s);
+
+// Cell indices and strip-binned placement lists, one workgroup per (time, channel) pair.
+// Pairs tc0 .. tc0+Q-1 of the [T][C] batch. Placements with column >= ku_limit are dropped
+// from the list (the half-spectrum path only needs ku < N/2).
+struct BinArgs {
+  const double* uvw;        // [T][B][3]
+  const double* freq;       // [C]
+  const uint8_t* flags;     // [T][C][B] or null
+  int tc0, Q, C, B, logn, log_strip, ku_limit, P;
+  double pixel_scale;
+  int2* plc;                // [Q][2B]
+  int* strip_off;           // [Q][nstrips+1]
+  int* n_kept;              // [Q]
+  int* occ;                 // [Q][P], zeroed here
+  int32_t* cell_idx;        // [T][C][B] or null (global)
+  int32_t* n_out;           // [T][C] or null (global)
+};
+hipError_t launch_bin(const BinArgs& a, hipStream_t s);
+
+// Full complex grids (unshifted) plus counts for blink_grid.
+struct GridArgs {
+  const float2* vis;        // chunk base: [Q][P][B]
+  const int2* plc;
+  const int* strip_off;
+  int Q, P, B, logn, uniform;
+  float2* grids;            // chunk base: [Q][P][N][N]
+  int32_t* counts;          // chunk base: [Q][N][N] or null
+  int* occ;                 // [Q][P]
+};
+hipError_t launch_grid_full(const GridArgs& a, hipStream_t s);
+
+// Fused gridding + column (v) FFT of the half spectrum ku < N/2 into H [img][N][N/2].
+struct ColArgs {
+  const float2* vis;        // chunk base: [Q][P][B]
+  const int2* plc;
+  const int* strip_off;
+  int Q, P, B, logn, uniform, shift;
+  float2* H;                // [Q*P][N][N/2]
+  int* occ;                 // [Q][P]
+};
+hipError_t launch_grid_colfft(const ColArgs& a, const float2* tw, hipStream_t s);
+
+// Column FFT of the Hermitian part of dense grids into H (blink_ifft2d).
+hipError_t launch_dense_colfft(const float2* grids, int n_img, int logn, int shift, float2* H,
+                               const float2* tw, hipStream_t s);
+
+// Per-image 1/W (and W as double) from kept counts (natural) or occupancy (uniform).
+hipError_t launch_image_weights(const int* n_kept, const int* occ, int uniform, int P, int n_img,
+                                float* inv_w, double* weight_sum, hipStream_t s);
+// Per-image 1/W from a caller's double array (null means W = 1).
+hipError_t launch_user_weights(const double* w, int n_img, float* inv_w, hipStream_t s);
+
+// Row (u) pass: Hermitian-extended complex FFT of two H rows at a time, real part * 1/W.
+hipError_t launch_row_c2r(const float2* H, const float* inv_w, int n_img, int logn, float* images,
+                          const float2* tw, hipStream_t s);
+
+}  // namespace blink

@@ -1,0 +1,91 @@
+"""CPU tests of the C ABI: the library loads, exports every declared entry point, and rejects bad
+arguments on the host before touching a GPU. No compute call is made here."""
+import ctypes
+import os
+
+import pytest
+
+import paper_2505_15204_amd as blink
+from paper_2505_15204_amd import build as blink_build
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(blink.LIB_PATH):
+        blink_build.build()
+    return blink.lib()
+
+
+def test_exports_every_declared_function(L):
+    names = blink.header_functions()
+    assert {"blink_grid", "blink_ifft2d", "blink_image_batch", "blink_create"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in include/blink.h but not exported"
+
+
+def test_status_strings(L):
+    for st in range(6):
+        assert blink.status_string(st)
+    assert L.blink_version() >= 100
+
+
+def test_create_without_gpu_reports_hip_error(L):
+    h = ctypes.c_void_p()
+    st = L.blink_create(ctypes.byref(h), 0)
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    if not has_gpu:
+        assert st == blink.BLINK_ERR_HIP and not h.value
+    elif st == blink.BLINK_OK:
+        L.blink_destroy(h)
+    assert L.blink_create(None, 0) == blink.BLINK_ERR_ARG
+    assert L.blink_destroy(None) == blink.BLINK_OK
+    assert L.blink_last_error(None) == b"no context"
+
+
+def _image_batch(L, T=1, C=1, P=1, B=10, N=64, dl=1e-3, weighting=0, precision=0, ctx=None, ws=1 << 20):
+    dummy = ctypes.c_void_p(0x1000)                    # never dereferenced: validation fails first
+    return L.blink_image_batch(ctx, dummy, None, dummy, dummy, T, C, P, B, N, dl, weighting, precision, 1,
+                               dummy, None, None, ctypes.c_void_p(0x10000), ws, None)
+
+
+def test_argument_errors_precede_any_device_work(L):
+    E = blink
+    assert _image_batch(L, N=100) == E.BLINK_ERR_SIZE        # not a power of two
+    assert _image_batch(L, N=4) == E.BLINK_ERR_SIZE          # below 8
+    assert _image_batch(L, N=8192) == E.BLINK_ERR_SIZE       # above 4096
+    assert _image_batch(L, T=-1) == E.BLINK_ERR_ARG
+    assert _image_batch(L, P=0) == E.BLINK_ERR_ARG
+    assert _image_batch(L, B=-5) == E.BLINK_ERR_ARG
+    assert _image_batch(L, weighting=7) == E.BLINK_ERR_ARG
+    assert _image_batch(L, dl=0.0) == E.BLINK_ERR_ARG
+    assert _image_batch(L, dl=float("nan")) == E.BLINK_ERR_ARG
+    assert _image_batch(L) == E.BLINK_ERR_ARG                # NULL context
+    dummy = ctypes.c_void_p(0x1000)
+    assert L.blink_ifft2d(None, dummy, None, 1, 24, 0, 1, dummy, dummy, 1 << 20, None) == E.BLINK_ERR_SIZE
+    assert L.blink_ifft2d(None, dummy, None, -1, 64, 0, 1, dummy, dummy, 1 << 20, None) == E.BLINK_ERR_ARG
+    assert L.blink_ifft2d(None, dummy, None, 1, 64, 9, 1, dummy, dummy, 1 << 20, None) == E.BLINK_ERR_ARG
+    assert L.blink_grid(None, dummy, None, dummy, dummy, 1, 1, 1, 10, 48, 1e-3, 0, dummy, None, None, None,
+                        None, dummy, 1 << 20, None) == E.BLINK_ERR_SIZE
+
+
+def test_workspace_sizes(L):
+    s1 = blink.image_batch_workspace_size(1, 1, 2, 8128, 1024)
+    s2 = blink.image_batch_workspace_size(1, 2, 2, 8128, 1024)
+    # one (t,c) pair holds at least its two half-spectrum intermediates (N x N/2 complex64 each)
+    assert s1 >= 2 * 1024 * 512 * 8
+    assert s2 > s1 and s2 <= 2 * s1 + 4096
+    assert blink.image_batch_workspace_size(0, 0, 1, 10, 64) == 0
+    assert blink.ifft2d_workspace_size(3, 256) >= 3 * 256 * 128 * 8
+    assert blink.grid_workspace_size(2, 3, 100, 64) >= 6 * 2 * 100 * 8
+    for fn, args in ((blink.image_batch_workspace_size, (1, 1, 1, 10, 96)),
+                     (blink.ifft2d_workspace_size, (1, 96)),
+                     (blink.grid_workspace_size, (1, 1, 10, 96))):
+        with pytest.raises(blink.BlinkError) as e:
+            fn(*args)
+        assert e.value.status == blink.BLINK_ERR_SIZE
+    with pytest.raises(blink.BlinkError):
+        blink.image_batch_workspace_size(1, 1, 1, 10, 64, precision=5)
