@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy (read + write of this many MiB) --steps times; used "
+                         "to scale the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU: every image is independent, so a multi-GPU run is this "
@@ -98,6 +101,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            torch.mul(src, 1.0, out=dst)       # elementwise: reads n*4 bytes, writes n*4 bytes
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                          "launches": args.steps}), flush=True)
+        return
     spec = synth.spec_vcs()
     T, C, P, B, N = spec.T, spec.C, spec.P, spec.B, spec.grid_n
     log(f"generating workload {spec.name}: T={T} C={C} P={P} B={B} N={N} on cuda:0")

@@ -39,8 +39,9 @@ def ctx(torch):
 
 
 def rel_l2(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
+    kind = np.complex128 if (np.iscomplexobj(a) or np.iscomplexobj(b)) else np.float64
+    a = np.asarray(a, kind)
+    b = np.asarray(b, kind)
     nb = np.linalg.norm(b)
     if nb == 0:
         return float(np.linalg.norm(a))
