@@ -29,6 +29,34 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    """SHA-256 prefix of the kernel sources; byte counters are reported only for the sources they came from."""
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_2505_15204_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(tag, kernel):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of `kernel` from profiles/<tag>_hbm_counters.md,
+    or None when absent or taken from different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{tag}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    for ln in open(path):
+        if ln.startswith("traffic-json:"):
+            rec = json.loads(ln.split(":", 1)[1])
+            if rec.get("source_hash") != kernel_source_hash():
+                return None
+            return rec.get("bytes_per_launch", {}).get(kernel)
+    return None
+
+
 def kernel_bytes(spec, n_tc):
     """Algorithmic HBM bytes of one launch of each kernel for n_tc (time, channel) pairs.
 
@@ -164,7 +192,7 @@ def main():
         kernels[name] = entry
     dom = max((k for k in kernels if k in kb), key=lambda k: kernels[k]["total_ms"])
     roof = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["achieved_GB_s"], "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": kernels[dom]["frac_hbm"], "traffic": None}
+            "unit": "GB/s", "frac": kernels[dom]["frac_hbm"], "traffic": counter_traffic("vcs1024_fp32", dom)}
     per_image = 12 * N * N + 8 * B + B // P
     path = {"bytes_per_image_model": per_image,
             "achieved_GB_s": round(value * per_image / 1e9, 1),
