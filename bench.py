@@ -42,38 +42,35 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(tag, kernel):
+def counter_traffic(tag, kernel, plan):
     """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of `kernel` from profiles/<tag>_hbm_counters.md,
-    or None when absent or taken from different kernel sources."""
+    or None when absent or taken from different kernel sources or a different execution plan."""
     path = os.path.join(ROOT, "profiles", f"{tag}_hbm_counters.md")
     if not os.path.exists(path):
         return None
     for ln in open(path):
         if ln.startswith("traffic-json:"):
             rec = json.loads(ln.split(":", 1)[1])
-            if rec.get("source_hash") != kernel_source_hash():
+            if rec.get("source_hash") != kernel_source_hash() or rec.get("plan") != plan:
                 return None
             return rec.get("bytes_per_launch", {}).get(kernel)
     return None
 
 
-def kernel_bytes(spec, n_tc):
-    """Algorithmic HBM bytes of one launch of each kernel for n_tc (time, channel) pairs.
+def kernel_unit_bytes(spec):
+    """Algorithmic HBM bytes per unit of work of each kernel (unit, bytes).
 
     grid_colfft: per image, write the half-spectrum intermediate N x N/2 complex64 (4 N^2 B) and
                  read each visibility once (8 B) plus its placement record (8 B).
     row_fft:     per image, read the intermediate (4 N^2 B) and write the FP32 image (4 N^2 B).
-    bin:         per (t,c), read u, v (16 B) and the flag (1 B) of each baseline, write ~one
-                 placement record (8 B) per baseline.
-    weights:     per image, 4 B in, 4 B + 8 B out.
+    bin:         per (t,c) pair, read u, v (16 B) and the flag (1 B) of each baseline and write
+                 ~one placement record (8 B) per baseline.
     """
-    N, B, P = spec.grid_n, spec.B, spec.P
-    n_img = n_tc * P
+    N, B = spec.grid_n, spec.B
     return {
-        "grid_colfft": n_img * (4 * N * N + 16 * B),
-        "row_fft": n_img * (8 * N * N),
-        "bin": n_tc * (25 * B),
-        "weights": n_img * 16,
+        "grid_colfft": ("image", 4 * N * N + 16 * B),
+        "row_fft": ("image", 8 * N * N),
+        "bin": ("pair", 25 * B),
     }
 
 
@@ -111,6 +108,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the execution plan on time step 0 instead of loading the committed plan file")
+    ap.add_argument("--save-plans", default="", help="write the context's plans (JSON) to this path")
+    ap.add_argument("--plan", default="", help="force a plan col_strip,row_block,group")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy (read + write of this many MiB) --steps times; used "
                          "to scale the HBM byte counters")
@@ -155,11 +156,28 @@ def main():
         ctx.blink_image_batch(d["vis"][t:t + 1], d["flags"][t:t + 1], d["uvw_m"][t:t + 1], d["freq_hz"], N,
                               spec.pixel_scale, 0, out=images, weight_sum=wsum, n_out=nout, workspace=ws)
 
+    tune = None
+    if args.plan:
+        c, r, g = (int(x) for x in args.plan.split(","))
+        ctx.set_plan(N, 0, c, r, g)
+    elif not args.autotune and os.path.exists(blink.PLANS_PATH):
+        ctx.load_plans(blink.PLANS_PATH)
+        tune = {"source": os.path.relpath(blink.PLANS_PATH, ROOT)}
+    else:
+        log("autotuning the execution plan on time step 0")
+        t0 = time.perf_counter()
+        plan, best_ms = ctx.autotune_image_batch(d["vis"][0:1], d["flags"][0:1], d["uvw_m"][0:1], d["freq_hz"], N,
+                                                 spec.pixel_scale, 0, out=images, workspace=ws)
+        tune = {"source": "autotuned", "best_step_ms": round(best_ms, 4),
+                "seconds": round(time.perf_counter() - t0, 2)}
+        log(f"plan {plan}: {best_ms:.3f} ms per step")
+    if args.save_plans:
+        ctx.save_plans(args.save_plans)
+    plan = ctx.get_plan(N, 0)
     log(f"warmup {args.warmup} steps")
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    ctx.profile_enable(True)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     log(f"timing {args.steps} steps")
@@ -172,31 +190,49 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     gpu_ms = ev0.elapsed_time(ev1)
-    prof = ctx.profile_read()
-    ctx.profile_enable(False)
     n_images = args.steps * C * P
     value = n_images / (gpu_ms / 1e3)
     log(f"{n_images} images in {gpu_ms:.1f} ms (wall {wall * 1e3:.1f} ms): {value:.0f} images/s")
 
-    kb = kernel_bytes(spec, C)
+    # Per-kernel durations: the same steps again with hipEvents around every launch (the events
+    # cost a little time per launch, so they are kept out of the headline pass).
+    log(f"kernel timing pass: {args.steps} steps with per-launch events")
+    ctx.profile_enable(True)
+    pe0 = torch.cuda.Event(enable_timing=True)
+    pe1 = torch.cuda.Event(enable_timing=True)
+    pe0.record()
+    for i in range(args.steps):
+        step(i)
+    pe1.record()
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    prof_ms = pe0.elapsed_time(pe1)
+
+    units = {"image": n_images, "pair": args.steps * C}
+    ub = kernel_unit_bytes(spec)
     kernels = {}
     for name, (ms, launches) in prof.items():
         if launches == 0:
             continue
         avg_s = ms / launches / 1e3
-        entry = {"launches": launches, "avg_ms": round(ms / launches, 4), "total_ms": round(ms, 3)}
-        if name in kb:
-            gbs = kb[name] / avg_s / 1e9
-            entry.update({"bytes_per_launch": kb[name], "achieved_GB_s": round(gbs, 1),
-                          "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
+        entry = {"launches": launches, "avg_ms": round(ms / launches, 5), "total_ms": round(ms, 3)}
+        if name in ub:
+            unit, per_unit = ub[name]
+            per_launch = per_unit * units[unit] / launches
+            gbs = per_launch / avg_s / 1e9
+            entry.update({"unit": unit, "bytes_per_unit": per_unit, "bytes_per_launch": round(per_launch),
+                          "achieved_GB_s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
         kernels[name] = entry
-    dom = max((k for k in kernels if k in kb), key=lambda k: kernels[k]["total_ms"])
+    dom = max((k for k in kernels if k in ub), key=lambda k: kernels[k]["total_ms"])
     roof = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["achieved_GB_s"], "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": kernels[dom]["frac_hbm"], "traffic": counter_traffic("vcs1024_fp32", dom)}
+            "unit": "GB/s", "frac": kernels[dom]["frac_hbm"],
+            "traffic": counter_traffic("vcs1024_fp32", dom, plan)}
     per_image = 12 * N * N + 8 * B + B // P
     path = {"bytes_per_image_model": per_image,
             "achieved_GB_s": round(value * per_image / 1e9, 1),
-            "frac_hbm": round(value * per_image / 1e9 / HBM_PEAK_GBS, 4)}
+            "frac_hbm": round(value * per_image / 1e9 / HBM_PEAK_GBS, 4),
+            "kernel_timing_pass_ms": round(prof_ms, 3)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -225,6 +261,8 @@ def main():
             "grid_n": N,
             "baselines": B,
             "path": "fp32: bin -> fused grid+column FFT -> weights -> row FFT (C2R)",
+            "plan": plan,
+            "autotune": tune,
         },
         "roofline": roof,
         "path_roofline": path,

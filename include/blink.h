@@ -139,6 +139,39 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32 *vis, const uint8
                                int32_t *n_out, void *workspace, size_t workspace_bytes,
                                void *hip_stream);
 
+/* ---------------------------------------------------------------- execution plans and autotuning
+ * Not part of the method: how blink_image_batch schedules its kernels for one grid size and
+ * weighting. A plan never changes results beyond FP32 rounding order. Fields:
+ *   col_strip  columns of the half spectrum per workgroup of the fused gridding + column FFT kernel
+ *   row_block  row-pair transforms per workgroup of the row FFT kernel
+ *   group      images per column/row launch pair (0 = as many as the workspace holds, at most 256
+ *              with the queried workspace); small groups keep the intermediates in the last-level
+ *              cache between the two passes. */
+
+/* Compiled options for grid_n and weighting: up to 4 strip widths and 4 row blocks each. */
+blink_status blink_plan_options(int grid_n, int weighting, int *col_strips, int *n_col,
+                                int *row_blocks, int *n_row);
+
+/* Current plan of a context (a default until set or tuned). */
+blink_status blink_get_plan(blink_ctx ctx, int grid_n, int weighting, int *col_strip,
+                            int *row_block, int *group);
+
+/* Set a plan; col_strip and row_block must be compiled options, group >= 0. */
+blink_status blink_set_plan(blink_ctx ctx, int grid_n, int weighting, int col_strip,
+                            int row_block, int group);
+
+/* Autotuner: runs blink_image_batch on the caller's problem (same arguments) for every compiled
+ * (col_strip, row_block) pair and group sizes 16 .. 256, times each with hipEvents on hip_stream,
+ * and keeps the fastest in the context. Synchronises with the host. On return `images` etc. hold
+ * a valid result, and col_strip, row_block, group, best_ms (any may be NULL) describe the choice. */
+blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32 *vis, const uint8_t *flags,
+                                        const double *uvw_m, const double *freq_hz, int T, int C,
+                                        int P, int B, int grid_n, double pixel_scale, int weighting,
+                                        int precision, int shift, float *images, double *weight_sum,
+                                        int32_t *n_out, void *workspace, size_t workspace_bytes,
+                                        void *hip_stream, int *col_strip, int *row_block,
+                                        int *group, double *best_ms);
+
 /* ---------------------------------------------------------------- kernel timing
  * Not part of the method: per-kernel timing for measurement. While enabled, every kernel launch
  * of the entry points above is bracketed by a pair of hipEvents recorded on the caller's stream.

@@ -16,6 +16,7 @@ from typing import Optional
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libblink.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "blink.h")
+PLANS_PATH = os.path.join(PKG, "plans_gfx950.json")     # autotuned execution plans (blink_set_plan)
 
 BLINK_OK, BLINK_ERR_ARG, BLINK_ERR_SIZE, BLINK_ERR_NOMEM, BLINK_ERR_HIP, BLINK_ERR_STATE = range(6)
 WEIGHT_NATURAL, WEIGHT_UNIFORM = 0, 1
@@ -69,6 +70,15 @@ def lib() -> ctypes.CDLL:
     L.blink_image_batch.restype = i32
     L.blink_image_batch.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32, P, P, P,
                                     P, sz, P]
+    L.blink_plan_options.restype = i32
+    L.blink_plan_options.argtypes = [i32, i32, P, P, P, P]
+    L.blink_get_plan.restype = i32
+    L.blink_get_plan.argtypes = [P, i32, i32, P, P, P]
+    L.blink_set_plan.restype = i32
+    L.blink_set_plan.argtypes = [P, i32, i32, i32, i32, i32]
+    L.blink_autotune_image_batch.restype = i32
+    L.blink_autotune_image_batch.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32, P, P,
+                                             P, P, sz, P, P, P, P, P]
     L.blink_profile_enable.restype = i32
     L.blink_profile_enable.argtypes = [P, i32]
     L.blink_profile_read.restype = i32
@@ -106,6 +116,16 @@ def image_batch_workspace_size(T: int, C: int, P: int, B: int, grid_n: int, weig
     _check(lib().blink_image_batch_workspace_size(T, C, P, B, grid_n, weighting, precision, ctypes.byref(n)),
            what="blink_image_batch_workspace_size")
     return n.value
+
+
+def plan_options(grid_n: int, weighting: int = 0):
+    """Compiled (col_strip, row_block) options for a grid size: two lists, largest first."""
+    col = (ctypes.c_int * 4)()
+    row = (ctypes.c_int * 4)()
+    nc, nr = ctypes.c_int(), ctypes.c_int()
+    _check(lib().blink_plan_options(grid_n, weighting, col, ctypes.byref(nc), row, ctypes.byref(nr)),
+           what="blink_plan_options")
+    return list(col)[:nc.value], list(row)[:nr.value]
 
 
 def _ptr(t) -> Optional[int]:
@@ -155,6 +175,62 @@ class Context:
                    "blink_profile_read")
             out[name] = (ms.value, n.value)
         return out
+
+    # -- execution plans (scheduling only; results are the same up to FP32 rounding order)
+    def get_plan(self, grid_n: int, weighting: int = 0) -> dict:
+        c, r, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().blink_get_plan(self.handle, grid_n, weighting, ctypes.byref(c), ctypes.byref(r), ctypes.byref(g)),
+               self.handle, "blink_get_plan")
+        return {"col_strip": c.value, "row_block": r.value, "group": g.value}
+
+    def set_plan(self, grid_n: int, weighting: int = 0, col_strip: int = 0, row_block: int = 0, group: int = 0):
+        _check(lib().blink_set_plan(self.handle, grid_n, weighting, col_strip, row_block, group), self.handle,
+               "blink_set_plan")
+
+    def save_plans(self, path: str, sizes=(256, 512, 1024, 2048, 4096)):
+        """Write the context's plans as JSON keyed by device name, grid size and weighting."""
+        import json
+        torch = self._torch()
+        name = torch.cuda.get_device_properties(self.device).gcnArchName
+        rec = {f"{name}/{n}/{w}": self.get_plan(n, w) for n in sizes for w in (0, 1)}
+        with open(path, "w") as fh:
+            json.dump(rec, fh, indent=1, sort_keys=True)
+
+    def load_plans(self, path: str):
+        import json
+        torch = self._torch()
+        name = torch.cuda.get_device_properties(self.device).gcnArchName
+        for key, p in json.load(open(path)).items():
+            dev, n, w = key.rsplit("/", 2)
+            if dev == name:
+                self.set_plan(int(n), int(w), p["col_strip"], p["row_block"], p["group"])
+
+    def autotune_image_batch(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float, weighting: int = 0,
+                             precision: int = PREC_FP32, shift: bool = True, out=None, workspace=None, stream=None):
+        """Time every compiled plan on this problem and keep the fastest; returns (plan dict, best ms)."""
+        torch = self._torch()
+        T, C, P, B = vis.shape
+        N = int(grid_n)
+        self._require("vis", vis, torch.complex64)
+        self._require("uvw_m", uvw_m, torch.float64, (T, B, 3))
+        self._require("freq_hz", freq_hz, torch.float64, (C,))
+        if flags is not None:
+            self._require("flags", flags, torch.uint8, (T, C, B))
+        dev = vis.device
+        if out is None:
+            out = torch.empty((T, C, P, N, N), dtype=torch.float32, device=dev)
+        self._require("out", out, torch.float32, (T, C, P, N, N))
+        wsum = torch.empty((T, C, P), dtype=torch.float64, device=dev)
+        nout = torch.empty((T, C), dtype=torch.int32, device=dev)
+        ws = self._workspace(image_batch_workspace_size(T, C, P, B, N, weighting, precision), workspace)
+        c, r, g, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        st = lib().blink_autotune_image_batch(self.handle, _ptr(vis), _ptr(flags), _ptr(uvw_m), _ptr(freq_hz), T, C,
+                                              P, B, N, float(pixel_scale), int(weighting), int(precision),
+                                              int(bool(shift)), _ptr(out), _ptr(wsum), _ptr(nout), _ptr(ws),
+                                              ws.numel(), self._stream(stream), ctypes.byref(c), ctypes.byref(r),
+                                              ctypes.byref(g), ctypes.byref(ms))
+        _check(st, self.handle, "blink_autotune_image_batch")
+        return {"col_strip": c.value, "row_block": r.value, "group": g.value}, ms.value
 
     # -- helpers
     def _torch(self):

@@ -20,6 +20,11 @@ struct blink_ctx_s {
   float2* tw[13] = {};
   bool broken = false;
   std::string err;
+  // execution plan per (log2 N, weighting): fused-kernel strip width, row transforms per
+  // workgroup, images per column/row launch pair (0 = as many as the workspace holds)
+  struct Plan {
+    int col_strip = 0, row_tpb = 0, group = 0;
+  } plan[13][2];
   // kernel timing (blink_profile_enable)
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> records[BLINK_KERNEL_COUNT];
@@ -143,18 +148,27 @@ BinLayout carve_bins(Carve& c, size_t Q, size_t P, size_t B, size_t nstrips) {
 
 struct ImageLayout {
   BinLayout bins;
-  size_t inv, H, total;
+  size_t H, total;
   bool ok;
 };
 
-ImageLayout image_layout(size_t Q, int P, int B, int logn, int uniform) {
+// The fused path keeps at most kMaxGroupImages half-spectrum intermediates per launch pair
+// unless a plan asks for more.
+constexpr size_t kMaxGroupImages = 256;
+
+int min_col_strip(int logn, int uniform) {
+  int opts[4];
+  int n = blink::col_strip_options(logn, uniform != 0, opts);
+  return n > 0 ? opts[n - 1] : 1;
+}
+
+ImageLayout image_layout(size_t Q, int P, int B, int logn, int uniform, size_t h_images) {
   const size_t N = size_t(1) << logn;
-  const size_t nstrips = (N / 2) / blink::col_strip_width(logn, uniform != 0);
+  const size_t nstrips = (N / 2) / min_col_strip(logn, uniform);
   Carve c;
   ImageLayout L;
   L.bins = carve_bins(c, Q, P, B, nstrips);
-  L.inv = c.take(Q * P, sizeof(float));
-  L.H = c.take(Q * P, N * (N / 2) * sizeof(float2));
+  L.H = c.take(h_images, N * (N / 2) * sizeof(float2));
   L.total = c.off;
   L.ok = c.ok;
   return L;
@@ -178,7 +192,7 @@ GridLayout grid_layout(size_t Q, int P, int B, int logn) {
 }
 
 struct FftLayout {
-  size_t inv, H, total;
+  size_t H, total;
   bool ok;
 };
 
@@ -186,7 +200,6 @@ FftLayout fft_layout(size_t n_img, int logn) {
   const size_t N = size_t(1) << logn;
   Carve c;
   FftLayout L;
-  L.inv = c.take(n_img, sizeof(float));
   L.H = c.take(n_img, N * (N / 2) * sizeof(float2));
   L.total = c.off;
   L.ok = c.ok;
@@ -286,6 +299,21 @@ blink_status blink_create(blink_ctx* out, int hip_device) {
     e = blink::launch_twiddles(ctx->tw[l], 1 << l, nullptr);
     off += size_t(1) << l;
   }
+  for (int l = 3; l <= 12; ++l) {
+    for (int u = 0; u < 2; ++u) {
+      int col[4], row[4];
+      blink::col_strip_options(l, u != 0, col);
+      int nr = blink::row_block_options(l, row);
+      // default: the widest strip, and the row block closest to 256 threads
+      ctx->plan[l][u].col_strip = col[0];
+      int t = (1 << l) / 16 > 0 ? (1 << l) / 16 : 1;
+      int best = row[0];
+      for (int i = 0; i < nr; ++i)
+        if (row[i] * t <= 256) { best = row[i]; break; }
+      ctx->plan[l][u].row_tpb = best;
+      ctx->plan[l][u].group = 0;
+    }
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     (void)hipFree(ctx->tw_base);
@@ -337,7 +365,9 @@ blink_status blink_image_batch_workspace_size(int T, int C, int P, int B, int gr
   if (precision != BLINK_PREC_FP32) return BLINK_ERR_ARG;
   const int logn = log2_exact(grid_n);
   if (logn < 0) return BLINK_ERR_SIZE;
-  ImageLayout L = image_layout((size_t)T * C, P, B, logn, weighting);
+  const size_t n_img = (size_t)T * C * P;
+  ImageLayout L = image_layout((size_t)T * C, P, B, logn, weighting,
+                               n_img < kMaxGroupImages ? n_img : kMaxGroupImages);
   if (!L.ok) return BLINK_ERR_SIZE;
   *bytes = L.total;
   return BLINK_OK;
@@ -417,7 +447,7 @@ blink_status blink_grid(blink_ctx ctx, const blink_cf32* vis, const uint8_t* fla
     if (e != hipSuccess) return hip_fail(ctx, e, "grid kernel");
     if (weight_sum) {
       KernelTimer kt(ctx, BLINK_KERNEL_WEIGHTS, s);
-      e = blink::launch_image_weights(ba.n_kept, ba.occ, weighting, P, q * P, nullptr,
+      e = blink::launch_image_weights(ba.n_kept, ba.occ, weighting, P, 0, q * P, nullptr,
                                       weight_sum + tc0 * P, s);
       if (e != hipSuccess) return hip_fail(ctx, e, "weights kernel");
     }
@@ -450,20 +480,23 @@ blink_status blink_ifft2d(blink_ctx ctx, const blink_cf32* grids, const double* 
   FftLayout L = fft_layout(Q, logn);
   for (size_t i0 = 0; i0 < (size_t)n_img; i0 += Q) {
     const int q = (int)(((size_t)n_img - i0) < Q ? ((size_t)n_img - i0) : Q);
-    float* inv = (float*)(ws + L.inv);
     float2* H = (float2*)(ws + L.H);
     hipError_t e;
     {
-      KernelTimer kt(ctx, BLINK_KERNEL_WEIGHTS, s);
-      e = blink::launch_user_weights(weight_sum ? weight_sum + i0 : nullptr, q, inv, s);
-    }
-    if (e == hipSuccess) {
       KernelTimer kt(ctx, BLINK_KERNEL_DENSE_COLFFT, s);
       e = blink::launch_dense_colfft((const float2*)grids + i0 * N * N, q, logn, shift != 0, H, ctx->tw[logn], s);
     }
     if (e == hipSuccess) {
+      blink::RowArgs ra{};
+      ra.H = H;
+      ra.images = images + i0 * N * N;
+      ra.logn = logn;
+      ra.P = 1;
+      ra.img0 = (int)i0;
+      ra.wmode = blink::kWeightUser;
+      ra.w_user = weight_sum;
       KernelTimer kt(ctx, BLINK_KERNEL_ROW_FFT, s);
-      e = blink::launch_row_c2r(H, inv, q, logn, images + i0 * N * N, ctx->tw[logn], s);
+      e = blink::launch_row_c2r(ra, q, ctx->plan[logn][0].row_tpb, ctx->tw[logn], s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "ifft2d kernels");
   }
@@ -481,21 +514,30 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
   if (precision != BLINK_PREC_FP32) return fail(ctx, BLINK_ERR_ARG, "unsupported precision %d", precision);
   const size_t n_tc = (size_t)T * C;
   if (n_tc == 0) return BLINK_OK;
-  const size_t Q = largest_fitting_chunk(n_tc, workspace_bytes,
-                                         [&](size_t q) { return image_layout(q, P, B, logn, weighting).total; });
+  const auto& plan = ctx->plan[logn][weighting];
+  const size_t want = plan.group > 0 ? (size_t)plan.group : kMaxGroupImages;
+  size_t Q = largest_fitting_chunk(n_tc, workspace_bytes, [&](size_t q) {
+    return image_layout(q, P, B, logn, weighting, q * P < want ? q * P : want).total;
+  });
+  size_t h_images = Q * P < want ? Q * P : want;
+  if (Q == 0 && image_layout(1, P, B, logn, weighting, 1).total <= workspace_bytes) {
+    Q = 1;                       // fall back to one intermediate at a time
+    h_images = 1;
+  }
   if (Q == 0)
     return fail(ctx, BLINK_ERR_SIZE, "workspace of %zu bytes is smaller than one (t,c) pair needs (%zu)",
-                workspace_bytes, image_layout(1, P, B, logn, weighting).total);
+                workspace_bytes, image_layout(1, P, B, logn, weighting, 1).total);
   if (Q * P > (size_t)INT32_MAX) return fail(ctx, BLINK_ERR_SIZE, "batch too large");
   DeviceGuard g(ctx->device);
   if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t N = size_t(1) << logn;
-  const int S = blink::col_strip_width(logn, weighting == BLINK_WEIGHT_UNIFORM);
+  const int S = plan.col_strip;
   int log_s = 0;
   while ((1 << log_s) < S) ++log_s;
   char* ws = (char*)workspace;
-  ImageLayout L = image_layout(Q, P, B, logn, weighting);
+  ImageLayout L = image_layout(Q, P, B, logn, weighting, h_images);
+  const int G = (int)h_images;
   for (size_t tc0 = 0; tc0 < n_tc; tc0 += Q) {
     const int q = (int)((n_tc - tc0) < Q ? (n_tc - tc0) : Q);
     blink::BinArgs ba{};
@@ -535,25 +577,151 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
     ca.shift = shift != 0;
     ca.H = (float2*)(ws + L.H);
     ca.occ = ba.occ;
-    {
-      KernelTimer kt(ctx, BLINK_KERNEL_GRID_COLFFT, s);
-      e = blink::launch_grid_colfft(ca, ctx->tw[logn], s);
+    const int n_img = q * P;
+    blink::RowArgs ra{};
+    ra.H = ca.H;
+    ra.logn = logn;
+    ra.P = P;
+    ra.wmode = weighting == BLINK_WEIGHT_UNIFORM ? blink::kWeightUniform : blink::kWeightNatural;
+    ra.n_kept = ba.n_kept;
+    ra.occ = ba.occ;
+    ra.weight_sum = weight_sum ? weight_sum + tc0 * P : nullptr;
+    // Images go through the two passes G at a time so that their intermediates can stay in the
+    // last-level cache between the column and the row launch.
+    for (int i0 = 0; i0 < n_img; i0 += G) {
+      const int gi = (n_img - i0) < G ? (n_img - i0) : G;
+      ca.img0 = i0;
+      {
+        KernelTimer kt(ctx, BLINK_KERNEL_GRID_COLFFT, s);
+        e = blink::launch_grid_colfft(ca, gi, S, ctx->tw[logn], s);
+      }
+      if (e != hipSuccess) return hip_fail(ctx, e, "grid+column FFT kernel");
+      ra.img0 = i0;
+      ra.images = images + (tc0 * P + i0) * N * N;
+      {
+        KernelTimer kt(ctx, BLINK_KERNEL_ROW_FFT, s);
+        e = blink::launch_row_c2r(ra, gi, plan.row_tpb, ctx->tw[logn], s);
+      }
+      if (e != hipSuccess) return hip_fail(ctx, e, "row FFT kernel");
     }
-    if (e != hipSuccess) return hip_fail(ctx, e, "grid+column FFT kernel");
-    float* inv = (float*)(ws + L.inv);
-    {
-      KernelTimer kt(ctx, BLINK_KERNEL_WEIGHTS, s);
-      e = blink::launch_image_weights(ba.n_kept, ba.occ, weighting, P, q * P, inv,
-                                      weight_sum ? weight_sum + tc0 * P : nullptr, s);
-    }
-    if (e != hipSuccess) return hip_fail(ctx, e, "weights kernel");
-    {
-      KernelTimer kt(ctx, BLINK_KERNEL_ROW_FFT, s);
-      e = blink::launch_row_c2r(ca.H, inv, q * P, logn, images + tc0 * P * N * N, ctx->tw[logn], s);
-    }
-    if (e != hipSuccess) return hip_fail(ctx, e, "row FFT kernel");
   }
   return BLINK_OK;
+}
+
+blink_status blink_plan_options(int grid_n, int weighting, int* col_strips, int* n_col, int* row_blocks,
+                                int* n_row) {
+  const int logn = log2_exact(grid_n);
+  if (logn < 0) return BLINK_ERR_SIZE;
+  if (weighting != 0 && weighting != 1) return BLINK_ERR_ARG;
+  int col[4], row[4];
+  const int nc = blink::col_strip_options(logn, weighting != 0, col);
+  const int nr = blink::row_block_options(logn, row);
+  if (n_col) *n_col = nc;
+  if (n_row) *n_row = nr;
+  for (int i = 0; i < nc && col_strips; ++i) col_strips[i] = col[i];
+  for (int i = 0; i < nr && row_blocks; ++i) row_blocks[i] = row[i];
+  return BLINK_OK;
+}
+
+blink_status blink_get_plan(blink_ctx ctx, int grid_n, int weighting, int* col_strip, int* row_block, int* group) {
+  const int logn = log2_exact(grid_n);
+  if (logn < 0) return fail(ctx, BLINK_ERR_SIZE, "grid_n=%d unsupported", grid_n);
+  if (!ctx || (weighting != 0 && weighting != 1)) return BLINK_ERR_ARG;
+  const auto& p = ctx->plan[logn][weighting];
+  if (col_strip) *col_strip = p.col_strip;
+  if (row_block) *row_block = p.row_tpb;
+  if (group) *group = p.group;
+  return BLINK_OK;
+}
+
+blink_status blink_set_plan(blink_ctx ctx, int grid_n, int weighting, int col_strip, int row_block, int group) {
+  const int logn = log2_exact(grid_n);
+  if (logn < 0) return fail(ctx, BLINK_ERR_SIZE, "grid_n=%d unsupported", grid_n);
+  if (!ctx || (weighting != 0 && weighting != 1) || group < 0) return BLINK_ERR_ARG;
+  int col[4], row[4];
+  const int nc = blink::col_strip_options(logn, weighting != 0, col);
+  const int nr = blink::row_block_options(logn, row);
+  bool okc = false, okr = false;
+  for (int i = 0; i < nc; ++i) okc |= col[i] == col_strip;
+  for (int i = 0; i < nr; ++i) okr |= row[i] == row_block;
+  if (!okc || !okr)
+    return fail(ctx, BLINK_ERR_ARG, "plan (col_strip=%d, row_block=%d) is not a compiled option for N=%d", col_strip,
+                row_block, grid_n);
+  auto& p = ctx->plan[logn][weighting];
+  p.col_strip = col_strip;
+  p.row_tpb = row_block;
+  p.group = group;
+  return BLINK_OK;
+}
+
+blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8_t* flags,
+                                        const double* uvw_m, const double* freq_hz, int T, int C, int P, int B,
+                                        int grid_n, double pixel_scale, int weighting, int precision, int shift,
+                                        float* images, double* weight_sum, int32_t* n_out, void* workspace,
+                                        size_t workspace_bytes, void* hip_stream, int* col_strip, int* row_block,
+                                        int* group, double* best_ms) {
+  int logn = 0;
+  blink_status st = check_problem(ctx, vis, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting, images,
+                                  workspace, &logn);
+  if (st != BLINK_OK) return st;
+  const auto saved = ctx->plan[logn][weighting];
+  const bool was_profiling = ctx->profiling;
+  ctx->profiling = false;
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    ctx->profiling = was_profiling;
+    return hip_fail(ctx, hipErrorOutOfMemory, "hipEventCreate");
+  }
+  int col[4], row[4];
+  const int nc = blink::col_strip_options(logn, weighting != 0, col);
+  const int nr = blink::row_block_options(logn, row);
+  const int groups[] = {16, 32, 64, 128, 256};
+  double best = 1e300;
+  auto best_plan = saved;
+  blink_status result = BLINK_OK;
+  for (int gi = 0; gi < 5 && result == BLINK_OK; ++gi) {
+    for (int ci = 0; ci < nc && result == BLINK_OK; ++ci) {
+      for (int ri = 0; ri < nr && result == BLINK_OK; ++ri) {
+        auto& p = ctx->plan[logn][weighting];
+        p.col_strip = col[ci];
+        p.row_tpb = row[ri];
+        p.group = groups[gi];
+        double t = 1e300;
+        for (int rep = 0; rep < 3 && result == BLINK_OK; ++rep) {
+          hipError_t he = hipEventRecord(e0, s);
+          result = blink_image_batch(ctx, vis, flags, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting,
+                                     precision, shift, images, weight_sum, n_out, workspace, workspace_bytes,
+                                     hip_stream);
+          if (he == hipSuccess) he = hipEventRecord(e1, s);
+          if (he == hipSuccess) he = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+          if (he != hipSuccess && result == BLINK_OK) result = hip_fail(ctx, he, "autotune timing");
+          if (rep > 0 && ms < t) t = ms;        // the first run warms caches and code
+        }
+        if (result == BLINK_OK && t < best) {
+          best = t;
+          best_plan = p;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->profiling = was_profiling;
+  ctx->plan[logn][weighting] = result == BLINK_OK ? best_plan : saved;
+  if (result != BLINK_OK) return result;
+  // leave a result computed with the chosen plan in the outputs
+  result = blink_image_batch(ctx, vis, flags, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting, precision,
+                             shift, images, weight_sum, n_out, workspace, workspace_bytes, hip_stream);
+  if (col_strip) *col_strip = best_plan.col_strip;
+  if (row_block) *row_block = best_plan.row_tpb;
+  if (group) *group = best_plan.group;
+  if (best_ms) *best_ms = best;
+  return result;
 }
 
 blink_status blink_profile_enable(blink_ctx ctx, int enable) {

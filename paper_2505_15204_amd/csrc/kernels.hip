@@ -7,7 +7,8 @@
 //   k_grid_full      LDS-private strip grid -> complex grid in HBM (plain stores), counts
 //   k_grid_colfft    LDS-private strip grid -> inverse FFT along v -> half-spectrum H
 //   k_dense_colfft   Hermitian part of a dense grid -> inverse FFT along v -> H
-//   k_row_c2r        two H rows -> Hermitian-extended inverse FFT along u -> two image rows
+//   k_row_c2r        two H rows -> Hermitian-extended inverse FFT along u -> two image rows,
+//                    scaled by 1/W of the image (computed from the kept count or occupancy)
 //
 // The dirty image is I = Re(IDFT2(G)) / W (Section 4, Eq. 5). The shift of Section 6.2.4 is
 // folded into the input as the modulation (-1)^(ku + kv), which for even N moves the phase
@@ -32,15 +33,20 @@ __host__ __device__ constexpr int pow2_floor(int x) {
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
 // ---------------------------------------------------------------- configuration
+// Largest strip width (columns per workgroup) of the fused column kernel that fits 1024 threads
+// and the 160 KB of LDS (strip buffer, twiddle table and, for uniform weighting, counts).
 template <int LOGN, bool UNIFORM>
-struct ColCfg {
+struct ColSmax {
   using P = FftPlan<LOGN>;
   static constexpr int N = P::N;
   static constexpr int per_col = P::NP * 8 + (UNIFORM ? N * 4 : 0);
   static constexpr int avail = kLdsBytes - N * 8 - 1024;
-  static constexpr int S = pow2_floor(cmin(cmin(N / 2, 1024 / P::T), avail / per_col));
-  static constexpr int THREADS = S * P::T;
+  static constexpr int value = pow2_floor(cmin(cmin(N / 2, 1024 / P::T), avail / per_col));
 };
+
+// Tunable variants are compiled for N >= 256: strip widths Smax, Smax/2, Smax/4 and 1, 2, 4, 8
+// row-pair transforms per workgroup. Smaller grids get one variant each.
+constexpr int kTunedLogn = 8;
 
 template <int LOGN>
 struct GridCfg {
@@ -49,11 +55,17 @@ struct GridCfg {
   static constexpr int THREADS = 256;
 };
 
+// A row variant fits when TPB transforms of N padded points plus the twiddle table fit in LDS.
+template <int LOGN, int TPB>
+struct RowFits {
+  static constexpr bool value = TPB >= 1 && TPB * FftPlan<LOGN>::T <= 1024 && TPB <= (1 << LOGN) / 2 &&
+                                TPB * FftPlan<LOGN>::NP * 8 + (1 << LOGN) * 8 <= kLdsBytes;
+};
+
 template <int LOGN>
-struct RowCfg {
+struct RowDefault {
   using P = FftPlan<LOGN>;
-  static constexpr int TPB = cmin(P::N / 2, (256 / P::T) > 0 ? 256 / P::T : 1);
-  static constexpr int THREADS = TPB * P::T;
+  static constexpr int value = cmin(P::N / 2, (256 / P::T) > 0 ? 256 / P::T : 1);
 };
 
 // ---------------------------------------------------------------- twiddles
@@ -300,16 +312,16 @@ __global__ __launch_bounds__(256) void k_grid_full(GridArgs a) {
 }
 
 // ---------------------------------------------------------------- fused grid + column FFT
-template <int LOGN, bool UNIFORM>
-__global__ __launch_bounds__((ColCfg<LOGN, UNIFORM>::THREADS)) void k_grid_colfft(ColArgs a, const float2* __restrict__ twg) {
+template <int LOGN, int S, bool UNIFORM>
+__global__ __launch_bounds__(S * FftPlan<LOGN>::T) void k_grid_colfft(ColArgs a, const float2* __restrict__ twg) {
   using P = FftPlan<LOGN>;
-  using Cfg = ColCfg<LOGN, UNIFORM>;
-  constexpr int N = P::N, T = P::T, S = Cfg::S, NP = P::NP;
+  constexpr int N = P::N, T = P::T, NP = P::NP;
   __shared__ float2 sbuf[S * NP];
   __shared__ float2 stw[N];
   __shared__ unsigned scnt[UNIFORM ? S * N : 1];
   __shared__ int s_tmp;
-  const int img = blockIdx.x, strip = blockIdx.y;
+  // blockIdx.x = slot of the image in this launch's group; the image is img0 + slot in the chunk
+  const int slot = blockIdx.x, img = a.img0 + slot, strip = blockIdx.y;
   const int tcl = img / a.P;
   const int nstrips = (N / 2) / S;
   for (int i = threadIdx.x; i < S * NP; i += blockDim.x) sbuf[i] = make_float2(0.f, 0.f);
@@ -335,8 +347,8 @@ __global__ __launch_bounds__((ColCfg<LOGN, UNIFORM>::THREADS)) void k_grid_colff
 #pragma unroll
   for (int m = 0; m < P::R; ++m) v[m] = cb[pad_index(lt + m * T)];
   fft_inverse<LOGN, true>(v, cb, stw, lt, [](int, float2) {});
-  // H[img][y][strip*S + c]; column 0 carries (Re of the ku = 0 transform, ku = N/2 transform = 0).
-  float2* Hi = a.H + (size_t)img * N * (N / 2);
+  // H[slot][y][strip*S + c]; column 0 carries (Re of the ku = 0 transform, ku = N/2 transform = 0).
+  float2* Hi = a.H + (size_t)slot * N * (N / 2);
   for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
     const int y = i / S, c = i % S;
     float2 val = sbuf[c * NP + pad_index(y)];
@@ -347,12 +359,10 @@ __global__ __launch_bounds__((ColCfg<LOGN, UNIFORM>::THREADS)) void k_grid_colff
 
 // ---------------------------------------------------------------- dense grid column FFT
 template <int LOGN>
-__global__ __launch_bounds__((ColCfg<LOGN, false>::THREADS)) void k_dense_colfft(const float2* __restrict__ grids, int shift,
-                                                                             float2* __restrict__ H,
-                                                                             const float2* __restrict__ twg) {
+__global__ __launch_bounds__((ColSmax<LOGN, false>::value * FftPlan<LOGN>::T)) void k_dense_colfft(
+    const float2* __restrict__ grids, int shift, float2* __restrict__ H, const float2* __restrict__ twg) {
   using P = FftPlan<LOGN>;
-  using Cfg = ColCfg<LOGN, false>;
-  constexpr int N = P::N, T = P::T, S = Cfg::S, NP = P::NP, mask = N - 1;
+  constexpr int N = P::N, T = P::T, S = ColSmax<LOGN, false>::value, NP = P::NP, mask = N - 1;
   __shared__ float2 sbuf[S * NP];
   __shared__ float2 stw[N];
   const int img = blockIdx.x, strip = blockIdx.y;
@@ -393,32 +403,22 @@ __global__ __launch_bounds__((ColCfg<LOGN, false>::THREADS)) void k_dense_colfft
 }
 
 // ---------------------------------------------------------------- weights
-__global__ void k_image_weights(const int* n_kept, const int* occ, int uniform, int P, int n_img,
+// Images img0 .. img0+n_img-1 of a chunk: W from the pair's kept count (natural) or the image's
+// occupancy (uniform); inv_w and weight_sum are indexed by the chunk image index.
+__global__ void k_image_weights(const int* n_kept, const int* occ, int uniform, int P, int img0, int n_img,
                                 float* inv_w, double* weight_sum) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_img) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_img) return;
+  const int i = img0 + j;
   const int W = uniform ? occ[i] : 2 * n_kept[i / P];
   if (inv_w) inv_w[i] = W > 0 ? (float)(1.0 / (double)W) : 0.f;
   if (weight_sum) weight_sum[i] = (double)W;
 }
 
-hipError_t launch_image_weights(const int* n_kept, const int* occ, int uniform, int P, int n_img,
+hipError_t launch_image_weights(const int* n_kept, const int* occ, int uniform, int P, int img0, int n_img,
                                 float* inv_w, double* weight_sum, hipStream_t s) {
   if (n_img <= 0) return hipSuccess;
-  k_image_weights<<<(n_img + 255) / 256, 256, 0, s>>>(n_kept, occ, uniform, P, n_img, inv_w, weight_sum);
-  return hipGetLastError();
-}
-
-__global__ void k_user_weights(const double* w, int n_img, float* inv_w) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_img) return;
-  const double W = w ? w[i] : 1.0;
-  inv_w[i] = (W > 0.0 && isfinite(W)) ? (float)(1.0 / W) : 0.f;
-}
-
-hipError_t launch_user_weights(const double* w, int n_img, float* inv_w, hipStream_t s) {
-  if (n_img <= 0) return hipSuccess;
-  k_user_weights<<<(n_img + 255) / 256, 256, 0, s>>>(w, n_img, inv_w);
+  k_image_weights<<<(n_img + 255) / 256, 256, 0, s>>>(n_kept, occ, uniform, P, img0, n_img, inv_w, weight_sum);
   return hipGetLastError();
 }
 
@@ -427,20 +427,23 @@ hipError_t launch_user_weights(const double* w, int n_img, float* inv_w, hipStre
 // Z[e] = Hf1[e] + i Hf2[e] where Hf is the Hermitian extension of the stored half row:
 // Hf[0] = Re H[0], Hf[N/2] = Im H[0], Hf[e] = H[e] (0 < e < N/2), Hf[e] = conj H[N-e].
 // The inverse FFT of Z is I1 + i I2 with both rows real.
-template <int LOGN>
-__global__ __launch_bounds__(RowCfg<LOGN>::THREADS) void k_row_c2r(const float2* __restrict__ H,
-                                                                 const float* __restrict__ inv_w,
-                                                                 float* __restrict__ images,
-                                                                 const float2* __restrict__ twg) {
+__device__ __forceinline__ double image_weight(const RowArgs& a, int img) {
+  if (a.wmode == kWeightUser) return a.w_user ? a.w_user[img] : 1.0;
+  if (a.wmode == kWeightNatural) return 2.0 * (double)a.n_kept[img / a.P];
+  return (double)a.occ[img];
+}
+
+template <int LOGN, int TPB>
+__global__ __launch_bounds__(TPB * FftPlan<LOGN>::T) void k_row_c2r(RowArgs a, const float2* __restrict__ twg) {
   using P = FftPlan<LOGN>;
-  constexpr int N = P::N, T = P::T, NP = P::NP, HALF = N / 2, TPB = RowCfg<LOGN>::TPB;
+  constexpr int N = P::N, T = P::T, NP = P::NP, HALF = N / 2;
   __shared__ float2 sbuf[TPB * NP];
   __shared__ float2 stw[N];
-  const int img = blockIdx.x;
+  const int slot = blockIdx.x, img = a.img0 + slot;
   const int j = threadIdx.x / T, lt = threadIdx.x % T;
   const int r = blockIdx.y * TPB + j;
   for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = twg[i];
-  const float2* h1 = H + ((size_t)img * N + 2 * r) * HALF;
+  const float2* h1 = a.H + ((size_t)slot * N + 2 * r) * HALF;
   const float2* h2 = h1 + HALF;
   float2 v[P::R];
 #pragma unroll
@@ -454,8 +457,10 @@ __global__ __launch_bounds__(RowCfg<LOGN>::THREADS) void k_row_c2r(const float2*
     else v[m] = make_float2(a.x + b.y, b.x - a.y);
   }
   __syncthreads();   // twiddles in LDS
-  const float s = inv_w[img];
-  float* o1 = images + ((size_t)img * N + 2 * r) * N;
+  const double W = image_weight(a, img);
+  const float s = (W > 0.0 && isfinite(W)) ? (float)(1.0 / W) : 0.f;
+  if (a.weight_sum && blockIdx.y == 0 && threadIdx.x == 0) a.weight_sum[img] = W;
+  float* o1 = a.images + ((size_t)slot * N + 2 * r) * N;
   float* o2 = o1 + N;
   fft_inverse<LOGN, false>(v, sbuf + j * NP, stw, lt, [&](int e, float2 z) {
     o1[e] = z.x * s;
@@ -481,26 +486,46 @@ static hipError_t by_logn(int logn, Args... args) {
   }
 }
 
+// Strip-width and row-block options compiled for each size (largest first).
 template <int LOGN>
-struct StripWidths {
-  static hipError_t run(int* col_nat, int* col_uni, int* grid) {
-    *col_nat = ColCfg<LOGN, false>::S;
-    *col_uni = ColCfg<LOGN, true>::S;
+struct Options {
+  static hipError_t run(bool uniform, int* col, int* ncol, int* row, int* nrow, int* grid) {
+    const int sm = uniform ? ColSmax<LOGN, true>::value : ColSmax<LOGN, false>::value;
+    *ncol = 0;
+    for (int k = 0; k < (LOGN >= kTunedLogn ? 3 : 1); ++k)
+      if ((sm >> k) >= 1) col[(*ncol)++] = sm >> k;
+    *nrow = 0;
+    if (LOGN >= kTunedLogn) {
+      if (RowFits<LOGN, 8>::value) row[(*nrow)++] = 8;
+      if (RowFits<LOGN, 4>::value) row[(*nrow)++] = 4;
+      if (RowFits<LOGN, 2>::value) row[(*nrow)++] = 2;
+      if (RowFits<LOGN, 1>::value) row[(*nrow)++] = 1;
+    } else {
+      row[(*nrow)++] = RowDefault<LOGN>::value;
+    }
     *grid = GridCfg<LOGN>::S;
     return hipSuccess;
   }
 };
 
-int col_strip_width(int logn, bool uniform) {
-  int a = 0, b = 0, c = 0;
-  (void)by_logn<StripWidths>(logn, &a, &b, &c);
-  return uniform ? b : a;
+int col_strip_options(int logn, bool uniform, int* out) {
+  int col[4], row[4], nc = 0, nr = 0, g = 0;
+  if (by_logn<Options>(logn, uniform, col, &nc, row, &nr, &g) != hipSuccess) return 0;
+  for (int i = 0; i < nc; ++i) out[i] = col[i];
+  return nc;
+}
+
+int row_block_options(int logn, int* out) {
+  int col[4], row[4], nc = 0, nr = 0, g = 0;
+  if (by_logn<Options>(logn, false, col, &nc, row, &nr, &g) != hipSuccess) return 0;
+  for (int i = 0; i < nr; ++i) out[i] = row[i];
+  return nr;
 }
 
 int grid_strip_width(int logn) {
-  int a = 0, b = 0, c = 0;
-  (void)by_logn<StripWidths>(logn, &a, &b, &c);
-  return c;
+  int col[4], row[4], nc = 0, nr = 0, g = 0;
+  (void)by_logn<Options>(logn, false, col, &nc, row, &nr, &g);
+  return g;
 }
 
 template <int LOGN>
@@ -519,35 +544,47 @@ hipError_t launch_grid_full(const GridArgs& a, hipStream_t s) {
   return by_logn<GridFullL>(a.logn, &a, s);
 }
 
+template <int LOGN, int S, bool U>
+static hipError_t col_one(const ColArgs* a, int n_img, const float2* tw, hipStream_t s) {
+  if constexpr (S >= 1) {
+    dim3 grid(n_img, ((1 << LOGN) / 2) / S);
+    k_grid_colfft<LOGN, S, U><<<grid, S * FftPlan<LOGN>::T, 0, s>>>(*a, tw);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int LOGN, bool U>
+static hipError_t col_variant(const ColArgs* a, int n_img, int S, const float2* tw, hipStream_t s) {
+  constexpr int SM = ColSmax<LOGN, U>::value;
+  if (S == SM) return col_one<LOGN, SM, U>(a, n_img, tw, s);
+  if constexpr (LOGN >= kTunedLogn) {
+    if (S == SM / 2) return col_one<LOGN, SM / 2, U>(a, n_img, tw, s);
+    if (S == SM / 4) return col_one<LOGN, SM / 4, U>(a, n_img, tw, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int LOGN>
 struct ColL {
-  static hipError_t run(const ColArgs* a, const float2* tw, hipStream_t s) {
-    constexpr int N = 1 << LOGN;
-    if (a->uniform) {
-      using Cfg = ColCfg<LOGN, true>;
-      dim3 grid(a->Q * a->P, (N / 2) / Cfg::S);
-      k_grid_colfft<LOGN, true><<<grid, Cfg::THREADS, 0, s>>>(*a, tw);
-    } else {
-      using Cfg = ColCfg<LOGN, false>;
-      dim3 grid(a->Q * a->P, (N / 2) / Cfg::S);
-      k_grid_colfft<LOGN, false><<<grid, Cfg::THREADS, 0, s>>>(*a, tw);
-    }
-    return hipGetLastError();
+  static hipError_t run(const ColArgs* a, int n_img, int S, const float2* tw, hipStream_t s) {
+    return a->uniform ? col_variant<LOGN, true>(a, n_img, S, tw, s) : col_variant<LOGN, false>(a, n_img, S, tw, s);
   }
 };
 
-hipError_t launch_grid_colfft(const ColArgs& a, const float2* tw, hipStream_t s) {
-  if (a.Q <= 0) return hipSuccess;
-  return by_logn<ColL>(a.logn, &a, tw, s);
+hipError_t launch_grid_colfft(const ColArgs& a, int n_img, int strip, const float2* tw, hipStream_t s) {
+  if (n_img <= 0) return hipSuccess;
+  return by_logn<ColL>(a.logn, &a, n_img, strip, tw, s);
 }
 
 template <int LOGN>
 struct DenseL {
   static hipError_t run(const float2* g, int n_img, int shift, float2* H, const float2* tw, hipStream_t s) {
     constexpr int N = 1 << LOGN;
-    using Cfg = ColCfg<LOGN, false>;
-    dim3 grid(n_img, (N / 2) / Cfg::S);
-    k_dense_colfft<LOGN><<<grid, Cfg::THREADS, 0, s>>>(g, shift, H, tw);
+    constexpr int S = ColSmax<LOGN, false>::value;
+    dim3 grid(n_img, (N / 2) / S);
+    k_dense_colfft<LOGN><<<grid, S * FftPlan<LOGN>::T, 0, s>>>(g, shift, H, tw);
     return hipGetLastError();
   }
 };
@@ -558,21 +595,38 @@ hipError_t launch_dense_colfft(const float2* grids, int n_img, int logn, int shi
   return by_logn<DenseL>(logn, grids, n_img, shift, H, tw, s);
 }
 
+template <int LOGN, int TPB>
+static hipError_t row_one(const RowArgs* a, int n_img, const float2* tw, hipStream_t s) {
+  if constexpr (RowFits<LOGN, TPB>::value) {
+    dim3 grid(n_img, ((1 << LOGN) / 2) / TPB);
+    k_row_c2r<LOGN, TPB><<<grid, TPB * FftPlan<LOGN>::T, 0, s>>>(*a, tw);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
 template <int LOGN>
 struct RowL {
-  static hipError_t run(const float2* H, const float* inv_w, int n_img, float* images, const float2* tw,
-                        hipStream_t s) {
-    constexpr int N = 1 << LOGN;
-    dim3 grid(n_img, (N / 2) / RowCfg<LOGN>::TPB);
-    k_row_c2r<LOGN><<<grid, RowCfg<LOGN>::THREADS, 0, s>>>(H, inv_w, images, tw);
-    return hipGetLastError();
+  static hipError_t run(const RowArgs* a, int n_img, int tpb, const float2* tw, hipStream_t s) {
+    if constexpr (LOGN >= kTunedLogn) {
+      switch (tpb) {
+        case 1: return row_one<LOGN, 1>(a, n_img, tw, s);
+        case 2: return row_one<LOGN, 2>(a, n_img, tw, s);
+        case 4: return row_one<LOGN, 4>(a, n_img, tw, s);
+        case 8: return row_one<LOGN, 8>(a, n_img, tw, s);
+        default: return hipErrorInvalidValue;
+      }
+    } else {
+      if (tpb != RowDefault<LOGN>::value) return hipErrorInvalidValue;
+      return row_one<LOGN, RowDefault<LOGN>::value>(a, n_img, tw, s);
+    }
   }
 };
 
-hipError_t launch_row_c2r(const float2* H, const float* inv_w, int n_img, int logn, float* images,
-                          const float2* tw, hipStream_t s) {
+hipError_t launch_row_c2r(const RowArgs& a, int n_img, int tpb, const float2* tw, hipStream_t s) {
   if (n_img <= 0) return hipSuccess;
-  return by_logn<RowL>(logn, H, inv_w, n_img, images, tw, s);
+  return by_logn<RowL>(a.logn, &a, n_img, tpb, tw, s);
 }
 
 }  // namespace blink

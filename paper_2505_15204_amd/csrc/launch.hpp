@@ -7,9 +7,10 @@
 
 namespace blink {
 
-// Strip widths (columns per workgroup) chosen per grid size and weighting.
-int col_strip_width(int logn, bool uniform);     // fused grid + column FFT kernel
-int grid_strip_width(int logn);                   // full-grid gridding kernel
+// Compiled variants per grid size (largest first); each returns the number written to `out` (<= 4).
+int col_strip_options(int logn, bool uniform, int* out);   // columns per workgroup of the fused kernel
+int row_block_options(int logn, int* out);                 // row-pair transforms per workgroup
+int grid_strip_width(int logn);                            // full-grid gridding kernel
 
 // FP32 twiddle table exp(+2 pi i j / N), j < N, generated in FP64 on the device.
 hipError_t launch_twiddles(float2* tw, int n, hipStream_t s);
@@ -45,28 +46,38 @@ struct GridArgs {
 hipError_t launch_grid_full(const GridArgs& a, hipStream_t s);
 
 // Fused gridding + column (v) FFT of the half spectrum ku < N/2 into H [img][N][N/2].
+// One launch covers images img0 .. img0+n_img-1 of the chunk; image img0+j uses H slot j.
 struct ColArgs {
   const float2* vis;        // chunk base: [Q][P][B]
   const int2* plc;
   const int* strip_off;
-  int Q, P, B, logn, uniform, shift;
-  float2* H;                // [Q*P][N][N/2]
+  int Q, P, B, logn, uniform, shift, img0;
+  float2* H;                // [n_img][N][N/2]
   int* occ;                 // [Q][P]
 };
-hipError_t launch_grid_colfft(const ColArgs& a, const float2* tw, hipStream_t s);
+hipError_t launch_grid_colfft(const ColArgs& a, int n_img, int strip, const float2* tw, hipStream_t s);
 
 // Column FFT of the Hermitian part of dense grids into H (blink_ifft2d).
 hipError_t launch_dense_colfft(const float2* grids, int n_img, int logn, int shift, float2* H,
                                const float2* tw, hipStream_t s);
 
 // Per-image 1/W (and W as double) from kept counts (natural) or occupancy (uniform).
-hipError_t launch_image_weights(const int* n_kept, const int* occ, int uniform, int P, int n_img,
+hipError_t launch_image_weights(const int* n_kept, const int* occ, int uniform, int P, int img0, int n_img,
                                 float* inv_w, double* weight_sum, hipStream_t s);
-// Per-image 1/W from a caller's double array (null means W = 1).
-hipError_t launch_user_weights(const double* w, int n_img, float* inv_w, hipStream_t s);
-
 // Row (u) pass: Hermitian-extended complex FFT of two H rows at a time, real part * 1/W.
-hipError_t launch_row_c2r(const float2* H, const float* inv_w, int n_img, int logn, float* images,
-                          const float2* tw, hipStream_t s);
+// A launch covers chunk images img0 .. img0+n_img-1; image img0+j reads H slot j and writes
+// images + j*N*N. W comes from the caller (wmode user; null = 1), from 2 x the pair's kept count
+// (natural) or from the image's occupancy (uniform); weight_sum (chunk base) receives W if non-null.
+enum { kWeightUser = 0, kWeightNatural = 1, kWeightUniform = 2 };
+struct RowArgs {
+  const float2* H;
+  float* images;
+  int logn, P, img0, wmode;
+  const double* w_user;     // chunk base, [n] or null
+  const int* n_kept;        // [Q]
+  const int* occ;           // [Q][P]
+  double* weight_sum;       // chunk base or null
+};
+hipError_t launch_row_c2r(const RowArgs& a, int n_img, int tpb, const float2* tw, hipStream_t s);
 
 }  // namespace blink

@@ -1,0 +1,108 @@
+"""GPU parity of every compiled execution plan (strip width x row block x image group) and of
+the autotuner, against the FP64 oracle. Plans only reschedule work, so every plan must meet the
+same bar as the default one."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_15204_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+IMAGE_TOL = 1e-5
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2505_15204_amd as blink
+    c = blink.Context(0)
+    yield c
+    c.close()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def make(torch, N, weighting, C, P):
+    spec = synth.Spec(f"plans-{N}", 21, 128, 1, P, synth.vcs_channels()[:C * 97:97], N, synth.ARCMIN * 1024 / N,
+                      20, 0.1, weighting=weighting)
+    prob = synth.make_problem(spec)
+    ref = oracle.image_batch(prob.vis, prob.flags, prob.uvw_m, prob.freq_hz, N, spec.pixel_scale, weighting)
+    d = "cuda:0"
+    dev = (torch.from_numpy(prob.vis).to(d), torch.from_numpy(prob.flags).to(d), torch.from_numpy(prob.uvw_m).to(d),
+           torch.from_numpy(prob.freq_hz).to(d))
+    return spec, dev, ref
+
+
+CASES = [(256, 0, 3, 2), (256, 1, 3, 2), (512, 0, 2, 2), (1024, 0, 3, 2), (1024, 1, 2, 2), (2048, 0, 1, 2),
+         (2048, 1, 1, 2), (4096, 0, 1, 2)]
+
+
+@pytest.mark.parametrize("N,weighting,C,P", CASES, ids=[f"N{c[0]}-w{c[1]}" for c in CASES])
+def test_every_plan_matches_oracle(torch, ctx, N, weighting, C, P):
+    import paper_2505_15204_amd as blink
+    spec, (vis, flags, uvw, freq), ref = make(torch, N, weighting, C, P)
+    cols, rows = blink.plan_options(N, weighting)
+    n_img = C * P
+    groups = sorted({0, 1, max(1, n_img - 1)})
+    default = ctx.get_plan(N, weighting)
+    try:
+        for col in cols:
+            for row in rows:
+                for grp in groups:
+                    say(f"plan N={N} w={weighting} col_strip={col} row_block={row} group={grp}")
+                    ctx.set_plan(N, weighting, col, row, grp)
+                    res = ctx.blink_image_batch(vis, flags, uvw, freq, N, spec.pixel_scale, weighting)
+                    assert np.array_equal(res["weight_sum"].cpu().numpy(), ref["weight_sum"])
+                    img = res["images"].cpu().numpy()
+                    for idx in np.ndindex(1, C, P):
+                        e = rel_l2(img[idx], ref["images"][idx])
+                        assert e <= IMAGE_TOL, (col, row, grp, idx, e)
+    finally:
+        ctx.set_plan(N, weighting, default["col_strip"], default["row_block"], default["group"])
+
+
+def test_set_plan_rejects_uncompiled_options(torch, ctx):
+    import paper_2505_15204_amd as blink
+    with pytest.raises(blink.BlinkError):
+        ctx.set_plan(1024, 0, 3, 4, 0)
+    with pytest.raises(blink.BlinkError):
+        ctx.set_plan(1024, 0, 16, 5, 0)
+    with pytest.raises(blink.BlinkError):
+        ctx.set_plan(1024, 0, 16, 4, -1)
+
+
+def test_autotuner_picks_a_compiled_plan_and_leaves_valid_images(torch, ctx, tmp_path):
+    import paper_2505_15204_amd as blink
+    spec, (vis, flags, uvw, freq), ref = make(torch, 1024, 0, 3, 2)
+    say("autotune N=1024 natural, 6 images")
+    default = ctx.get_plan(1024, 0)
+    try:
+        out = torch.empty((1, 3, 2, 1024, 1024), dtype=torch.float32, device="cuda:0")
+        plan, ms = ctx.autotune_image_batch(vis, flags, uvw, freq, 1024, spec.pixel_scale, 0, out=out)
+        cols, rows = blink.plan_options(1024, 0)
+        assert plan["col_strip"] in cols and plan["row_block"] in rows and plan["group"] > 0 and ms > 0
+        assert ctx.get_plan(1024, 0) == plan
+        img = out.cpu().numpy()
+        for idx in np.ndindex(1, 3, 2):
+            assert rel_l2(img[idx], ref["images"][idx]) <= IMAGE_TOL
+        path = tmp_path / "plans.json"
+        ctx.save_plans(str(path))
+        ctx.set_plan(1024, 0, default["col_strip"], default["row_block"], default["group"])
+        ctx.load_plans(str(path))
+        assert ctx.get_plan(1024, 0) == plan
+    finally:
+        ctx.set_plan(1024, 0, default["col_strip"], default["row_block"], default["group"])
