@@ -139,6 +139,81 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32 *vis, const uint8
                                int32_t *n_out, void *workspace, size_t workspace_bytes,
                                void *hip_stream);
 
+/* ---------------------------------------------------------------- uneven batches
+ * Section 6.2.4 grids many fine channels and integration intervals in parallel on one GPU and
+ * transforms all grids at once. blink_image_batch_desc does this for images that differ in grid
+ * size and visibility count: every image is described by one blink_image_desc (device memory) and
+ * the batch runs as two launches: a descriptor pass (checks, largest-grid-first order) and one
+ * persistent fused kernel whose workgroups claim images from a queue and image each one alone
+ * (binning, gridding + column FFT, row FFT) through a per-workgroup intermediate slot.
+ * Workgroups never wait for each other. */
+typedef struct {
+    int64_t vis_offset;    /* first visibility of the image in vis (blink_cf32 elements) */
+    int64_t uvw_offset;    /* first baseline of the image in uvw_m (baselines: uvw_m + 3*uvw_offset) */
+    int64_t flag_offset;   /* first flag of the image in flags (ignored when flags is NULL) */
+    int64_t image_offset;  /* first pixel of the image in images (float elements) */
+    double freq_hz;        /* channel frequency */
+    double pixel_scale;    /* direction-cosine units per pixel */
+    int32_t n_baselines;   /* B of this image, 0 <= B <= max_baselines */
+    int32_t grid_n;        /* power of two in [8, max_grid_n] */
+    int32_t reserved[2];   /* set to 0 */
+} blink_image_desc;
+
+/* Bits of the status word written by blink_image_batch_desc. */
+#define BLINK_DESC_BAD 1       /* a descriptor was invalid or out of bounds; that image was skipped */
+
+/* Workspace bytes for blink_image_batch_desc with n_img images of at most max_baselines
+ * visibilities and grid side at most max_grid_n, run by `workgroups` persistent workgroups (each
+ * owns one intermediate slot of max_grid_n^2/2 complex values). */
+blink_status blink_desc_workspace_size(int n_img, int max_baselines, int max_grid_n, int workgroups,
+                                       size_t *bytes);
+
+/* Images described by desc[0..n_img) (device array). vis_len, uvw_len (baselines), flags_len and
+ * images_len give the element counts of the caller's arrays; every descriptor is checked against
+ * them on the device and an invalid one only sets BLINK_DESC_BAD (its image is left untouched).
+ * weighting and shift apply to the whole batch. Outputs: images at each image_offset; weight_sum
+ * double [n_img] and n_out int32 [n_img] (either may be NULL); status int32 [1] (may be NULL)
+ * receives the BLINK_DESC_* bits. Uses the context's descriptor plan (blink_set_desc_plan); the
+ * number of workgroups is reduced to the slots the workspace holds. Capturable into a hipGraph
+ * (no allocation, copy or memset is issued). */
+blink_status blink_image_batch_desc(blink_ctx ctx, const blink_image_desc *desc, int n_img,
+                                    const blink_cf32 *vis, int64_t vis_len, const double *uvw_m,
+                                    int64_t uvw_len, const uint8_t *flags, int64_t flags_len,
+                                    int max_baselines, int max_grid_n, int weighting, int precision,
+                                    int shift, float *images, int64_t images_len,
+                                    double *weight_sum, int32_t *n_out, int32_t *status,
+                                    void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Descriptor-path plan: block_threads (512 or 1024; uniform weighting uses 512) and the number of
+ * persistent workgroups (0 = as many as are resident on the device). */
+blink_status blink_get_desc_plan(blink_ctx ctx, int *block_threads, int *workgroups);
+blink_status blink_set_desc_plan(blink_ctx ctx, int block_threads, int workgroups);
+
+/* Autotuner of the descriptor plan: times block sizes and workgroup counts on the caller's batch
+ * (same arguments as blink_image_batch_desc) and keeps the fastest. Synchronises. */
+blink_status blink_autotune_desc(blink_ctx ctx, const blink_image_desc *desc, int n_img,
+                                 const blink_cf32 *vis, int64_t vis_len, const double *uvw_m,
+                                 int64_t uvw_len, const uint8_t *flags, int64_t flags_len,
+                                 int max_baselines, int max_grid_n, int weighting, int precision,
+                                 int shift, float *images, int64_t images_len, double *weight_sum,
+                                 int32_t *n_out, int32_t *status, void *workspace,
+                                 size_t workspace_bytes, void *hip_stream, int *block_threads,
+                                 int *workgroups, double *best_ms);
+
+/* A captured hipGraph of one blink_image_batch_desc call (same arguments, same buffers). Launch
+ * replays it on any stream; descriptor and input contents may change between launches within the
+ * maxima given at capture. */
+typedef struct blink_graph_s *blink_graph;
+blink_status blink_graph_create_desc(blink_ctx ctx, const blink_image_desc *desc, int n_img,
+                                     const blink_cf32 *vis, int64_t vis_len, const double *uvw_m,
+                                     int64_t uvw_len, const uint8_t *flags, int64_t flags_len,
+                                     int max_baselines, int max_grid_n, int weighting,
+                                     int precision, int shift, float *images, int64_t images_len,
+                                     double *weight_sum, int32_t *n_out, int32_t *status,
+                                     void *workspace, size_t workspace_bytes, blink_graph *out);
+blink_status blink_graph_launch(blink_graph graph, void *hip_stream);
+blink_status blink_graph_destroy(blink_graph graph);
+
 /* ---------------------------------------------------------------- execution plans and autotuning
  * Not part of the method: how blink_image_batch schedules its kernels for one grid size and
  * weighting. A plan never changes results beyond FP32 rounding order. Fields:
@@ -183,7 +258,9 @@ enum {
     BLINK_KERNEL_DENSE_COLFFT = 3, /* column FFT of dense grids (blink_ifft2d) */
     BLINK_KERNEL_WEIGHTS = 4,      /* per-image 1/W */
     BLINK_KERNEL_ROW_FFT = 5,      /* row FFT, real part, 1/W, image store */
-    BLINK_KERNEL_COUNT = 6
+    BLINK_KERNEL_DESC_PREP = 6,    /* descriptor checks and image order (uneven batches) */
+    BLINK_KERNEL_PERSISTENT = 7,   /* persistent fused binning + gridding + FFT (uneven batches) */
+    BLINK_KERNEL_COUNT = 8
 };
 
 /* Enable (nonzero) or disable timing; either way the recorded launches are discarded. */

@@ -20,7 +20,17 @@ PLANS_PATH = os.path.join(PKG, "plans_gfx950.json")     # autotuned execution pl
 
 BLINK_OK, BLINK_ERR_ARG, BLINK_ERR_SIZE, BLINK_ERR_NOMEM, BLINK_ERR_HIP, BLINK_ERR_STATE = range(6)
 WEIGHT_NATURAL, WEIGHT_UNIFORM = 0, 1
-KERNELS = ("bin", "grid", "grid_colfft", "dense_colfft", "weights", "row_fft")   # BLINK_KERNEL_* ids
+KERNELS = ("bin", "grid", "grid_colfft", "dense_colfft", "weights", "row_fft", "desc_prep",
+           "persistent")   # BLINK_KERNEL_* ids
+DESC_BAD = 1
+
+# blink_image_desc as a NumPy structured dtype (64 bytes, C layout)
+import numpy as _np  # noqa: E402
+
+DESC_DTYPE = _np.dtype([("vis_offset", "<i8"), ("uvw_offset", "<i8"), ("flag_offset", "<i8"),
+                        ("image_offset", "<i8"), ("freq_hz", "<f8"), ("pixel_scale", "<f8"),
+                        ("n_baselines", "<i4"), ("grid_n", "<i4"), ("reserved", "<i4", (2,))])
+assert DESC_DTYPE.itemsize == 64
 PREC_FP32 = 0
 
 _lib = None
@@ -79,6 +89,24 @@ def lib() -> ctypes.CDLL:
     L.blink_autotune_image_batch.restype = i32
     L.blink_autotune_image_batch.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32, P, P,
                                              P, P, sz, P, P, P, P, P]
+    i64 = ctypes.c_int64
+    desc_args = [P, P, i32, P, i64, P, i64, P, i64, i32, i32, i32, i32, i32, P, i64, P, P, P, P, sz]
+    L.blink_desc_workspace_size.restype = i32
+    L.blink_desc_workspace_size.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz)]
+    L.blink_image_batch_desc.restype = i32
+    L.blink_image_batch_desc.argtypes = desc_args + [P]
+    L.blink_get_desc_plan.restype = i32
+    L.blink_get_desc_plan.argtypes = [P, P, P]
+    L.blink_set_desc_plan.restype = i32
+    L.blink_set_desc_plan.argtypes = [P, i32, i32]
+    L.blink_autotune_desc.restype = i32
+    L.blink_autotune_desc.argtypes = desc_args + [P, P, P, P]
+    L.blink_graph_create_desc.restype = i32
+    L.blink_graph_create_desc.argtypes = desc_args + [ctypes.POINTER(P)]
+    L.blink_graph_launch.restype = i32
+    L.blink_graph_launch.argtypes = [P, P]
+    L.blink_graph_destroy.restype = i32
+    L.blink_graph_destroy.argtypes = [P]
     L.blink_profile_enable.restype = i32
     L.blink_profile_enable.argtypes = [P, i32]
     L.blink_profile_read.restype = i32
@@ -126,6 +154,13 @@ def plan_options(grid_n: int, weighting: int = 0):
     _check(lib().blink_plan_options(grid_n, weighting, col, ctypes.byref(nc), row, ctypes.byref(nr)),
            what="blink_plan_options")
     return list(col)[:nc.value], list(row)[:nr.value]
+
+
+def desc_workspace_size(n_img: int, max_baselines: int, max_grid_n: int, workgroups: int = 512) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().blink_desc_workspace_size(n_img, max_baselines, max_grid_n, workgroups, ctypes.byref(n)),
+           what="blink_desc_workspace_size")
+    return n.value
 
 
 def _ptr(t) -> Optional[int]:
@@ -231,6 +266,70 @@ class Context:
                                               ctypes.byref(g), ctypes.byref(ms))
         _check(st, self.handle, "blink_autotune_image_batch")
         return {"col_strip": c.value, "row_block": r.value, "group": g.value}, ms.value
+
+    # -- uneven batches (one descriptor per image)
+    def _desc_args(self, desc, vis, uvw_m, flags, images, weighting, precision, shift, weight_sum, n_out, status,
+                   max_baselines, max_grid_n, workspace, workgroups_for_size=512):
+        torch = self._torch()
+        self._require("desc", desc, torch.uint8)
+        if desc.numel() % 64:
+            raise ValueError("desc must hold 64-byte blink_image_desc records (uint8 tensor)")
+        n_img = desc.numel() // 64
+        self._require("vis", vis, torch.complex64)
+        self._require("uvw_m", uvw_m, torch.float64)
+        if flags is not None:
+            self._require("flags", flags, torch.uint8)
+        self._require("images", images, torch.float32)
+        for name, t, dt in (("weight_sum", weight_sum, torch.float64), ("n_out", n_out, torch.int32),
+                            ("status", status, torch.int32)):
+            if t is not None:
+                self._require(name, t, dt)
+        ws = self._workspace(desc_workspace_size(n_img, max_baselines, max_grid_n, workgroups_for_size), workspace)
+        return [self.handle, _ptr(desc), n_img, _ptr(vis), vis.numel(), _ptr(uvw_m), uvw_m.numel() // 3,
+                _ptr(flags), 0 if flags is None else flags.numel(), int(max_baselines), int(max_grid_n),
+                int(weighting), int(precision), int(bool(shift)), _ptr(images), images.numel(), _ptr(weight_sum),
+                _ptr(n_out), _ptr(status), _ptr(ws), ws.numel()], ws
+
+    def blink_image_batch_desc(self, desc, vis, uvw_m, flags, images, max_baselines: int, max_grid_n: int,
+                               weighting: int = 0, precision: int = PREC_FP32, shift: bool = True, weight_sum=None,
+                               n_out=None, status=None, workspace=None, stream=None):
+        """Uneven batch: desc is a uint8 device tensor of blink_image_desc records (DESC_DTYPE);
+        vis complex64, uvw_m float64 [..][3], flags uint8 or None and images float32 are flat
+        device arrays addressed by the descriptors' offsets."""
+        args, ws = self._desc_args(desc, vis, uvw_m, flags, images, weighting, precision, shift, weight_sum, n_out,
+                                   status, max_baselines, max_grid_n, workspace)
+        st = lib().blink_image_batch_desc(*args, self._stream(stream))
+        _check(st, self.handle, "blink_image_batch_desc")
+        return images
+
+    def get_desc_plan(self) -> dict:
+        b, w = ctypes.c_int(), ctypes.c_int()
+        _check(lib().blink_get_desc_plan(self.handle, ctypes.byref(b), ctypes.byref(w)), self.handle,
+               "blink_get_desc_plan")
+        return {"block_threads": b.value, "workgroups": w.value}
+
+    def set_desc_plan(self, block_threads: int = 512, workgroups: int = 0):
+        _check(lib().blink_set_desc_plan(self.handle, block_threads, workgroups), self.handle, "blink_set_desc_plan")
+
+    def autotune_desc(self, desc, vis, uvw_m, flags, images, max_baselines: int, max_grid_n: int, weighting: int = 0,
+                      precision: int = PREC_FP32, shift: bool = True, workspace=None, stream=None):
+        args, ws = self._desc_args(desc, vis, uvw_m, flags, images, weighting, precision, shift, None, None, None,
+                                   max_baselines, max_grid_n, workspace)
+        b, w, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        st = lib().blink_autotune_desc(*args, self._stream(stream), ctypes.byref(b), ctypes.byref(w), ctypes.byref(ms))
+        _check(st, self.handle, "blink_autotune_desc")
+        return {"block_threads": b.value, "workgroups": w.value}, ms.value
+
+    def graph_desc(self, desc, vis, uvw_m, flags, images, max_baselines: int, max_grid_n: int, weighting: int = 0,
+                   precision: int = PREC_FP32, shift: bool = True, weight_sum=None, n_out=None, status=None,
+                   workspace=None):
+        """Capture one blink_image_batch_desc call (these buffers) into a hipGraph; returns a Graph."""
+        args, ws = self._desc_args(desc, vis, uvw_m, flags, images, weighting, precision, shift, weight_sum, n_out,
+                                   status, max_baselines, max_grid_n, workspace)
+        h = ctypes.c_void_p()
+        st = lib().blink_graph_create_desc(*args, ctypes.byref(h))
+        _check(st, self.handle, "blink_graph_create_desc")
+        return Graph(self, h, keep=(ws, desc, vis, uvw_m, flags, images, weight_sum, n_out, status))
 
     # -- helpers
     def _torch(self):
@@ -341,3 +440,26 @@ class Context:
                                      self._stream(stream))
         _check(st, self.handle, "blink_image_batch")
         return {"images": out, "weight_sum": weight_sum, "n_out": n_out}
+
+
+class Graph:
+    """A captured hipGraph of one uneven-batch call; launch() replays it on the current stream."""
+
+    def __init__(self, ctx: Context, handle, keep=()):
+        self.ctx = ctx
+        self.handle = handle
+        self._keep = keep          # the captured buffers must outlive the graph
+
+    def launch(self, stream=None):
+        _check(lib().blink_graph_launch(self.handle, self.ctx._stream(stream)), self.ctx.handle, "blink_graph_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().blink_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

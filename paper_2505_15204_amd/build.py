@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libblink.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "persistent.hip", "api.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

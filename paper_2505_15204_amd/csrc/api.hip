@@ -25,6 +25,9 @@ struct blink_ctx_s {
   struct Plan {
     int col_strip = 0, row_tpb = 0, group = 0;
   } plan[13][2];
+  // descriptor-path plan (blink_set_desc_plan) and device facts
+  int desc_block = 512, desc_workgroups = 0;
+  int cu_count = 0;
   // kernel timing (blink_profile_enable)
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> records[BLINK_KERNEL_COUNT];
@@ -281,6 +284,7 @@ blink_status blink_create(blink_ctx* out, int hip_device) {
   blink_ctx ctx = new (std::nothrow) blink_ctx_s;
   if (!ctx) return BLINK_ERR_NOMEM;
   ctx->device = hip_device;
+  ctx->cu_count = prop.multiProcessorCount;
   DeviceGuard g(hip_device);
   if (g.err != hipSuccess) {
     delete ctx;
@@ -605,6 +609,307 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
       if (e != hipSuccess) return hip_fail(ctx, e, "row FFT kernel");
     }
   }
+  return BLINK_OK;
+}
+
+// ---------------------------------------------------------------- uneven batches
+}  // extern "C"
+
+namespace {
+
+struct DescLayout {
+  size_t valid, order, counter, status, plc, strip_off, H, total;
+  bool ok;
+};
+
+DescLayout desc_layout(size_t n_img, size_t max_b, size_t max_n, size_t slots) {
+  Carve c;
+  DescLayout L;
+  L.valid = c.take(n_img, sizeof(int));
+  L.order = c.take(n_img, sizeof(int));
+  L.counter = c.take(1, sizeof(int));
+  L.status = c.take(1, sizeof(int));
+  L.plc = c.take(slots, 2 * max_b * sizeof(int2));
+  L.strip_off = c.take(slots, (max_n / 2 + 1) * sizeof(int));
+  L.H = c.take(slots, max_n * (max_n / 2) * sizeof(float2));
+  L.total = c.off;
+  L.ok = c.ok;
+  return L;
+}
+
+struct DescCall {
+  const blink_image_desc* desc;
+  int n_img;
+  const blink_cf32* vis;
+  int64_t vis_len;
+  const double* uvw;
+  int64_t uvw_len;
+  const uint8_t* flags;
+  int64_t flags_len;
+  int max_b, max_n, weighting, precision, shift;
+  float* images;
+  int64_t images_len;
+  double* weight_sum;
+  int32_t* n_out;
+  int32_t* status;
+  void* ws;
+  size_t ws_bytes;
+};
+
+blink_status check_desc(blink_ctx ctx, const DescCall& c, int* max_logn) {
+  if (c.n_img < 0 || c.max_b < 0 || c.vis_len < 0 || c.uvw_len < 0 || c.flags_len < 0 || c.images_len < 0)
+    return fail(ctx, BLINK_ERR_ARG, "negative count or length");
+  if (c.max_b > (1 << 30)) return fail(ctx, BLINK_ERR_SIZE, "max_baselines exceeds 2^30");
+  *max_logn = log2_exact(c.max_n);
+  if (*max_logn < 0) return fail(ctx, BLINK_ERR_SIZE, "max_grid_n=%d is not a power of two in [8, 4096]", c.max_n);
+  if (c.weighting != BLINK_WEIGHT_NATURAL && c.weighting != BLINK_WEIGHT_UNIFORM)
+    return fail(ctx, BLINK_ERR_ARG, "unknown weighting %d", c.weighting);
+  if (c.precision != BLINK_PREC_FP32) return fail(ctx, BLINK_ERR_ARG, "unsupported precision %d", c.precision);
+  if (!ctx) return BLINK_ERR_ARG;
+  if (ctx->broken) return fail(ctx, BLINK_ERR_STATE, "context unusable after an earlier HIP error");
+  if (c.n_img == 0) return BLINK_OK;
+  if (!c.desc || !c.images || !c.ws) return fail(ctx, BLINK_ERR_ARG, "NULL desc, images or workspace");
+  if ((c.vis_len > 0 && !c.vis) || (c.uvw_len > 0 && !c.uvw))
+    return fail(ctx, BLINK_ERR_ARG, "NULL vis or uvw_m with a nonzero length");
+  if ((uintptr_t)c.ws % kAlign) return fail(ctx, BLINK_ERR_ARG, "workspace is not 256-byte aligned");
+  return BLINK_OK;
+}
+
+int desc_block_for(blink_ctx ctx, int weighting) { return weighting ? 512 : ctx->desc_block; }
+
+blink_status run_desc(blink_ctx ctx, const DescCall& c, hipStream_t s) {
+  int max_logn = 0;
+  blink_status st = check_desc(ctx, c, &max_logn);
+  if (st != BLINK_OK || c.n_img == 0) return st;
+  const int block = desc_block_for(ctx, c.weighting);
+  const int per_cu = blink::persistent_blocks_per_cu(block, c.weighting != 0);
+  if (per_cu <= 0) return fail(ctx, BLINK_ERR_ARG, "persistent kernel with %d threads is not available", block);
+  size_t wg = ctx->desc_workgroups > 0 ? (size_t)ctx->desc_workgroups : (size_t)per_cu * ctx->cu_count;
+  if (wg > (size_t)c.n_img) wg = (size_t)c.n_img;
+  while (wg > 1 && desc_layout(c.n_img, c.max_b, c.max_n, wg).total > c.ws_bytes) wg = wg / 2 > 1 ? wg / 2 : 1;
+  while (desc_layout(c.n_img, c.max_b, c.max_n, wg + 1).total <= c.ws_bytes && wg < (size_t)c.n_img &&
+         wg < (ctx->desc_workgroups > 0 ? (size_t)ctx->desc_workgroups : (size_t)per_cu * ctx->cu_count))
+    ++wg;
+  DescLayout L = desc_layout(c.n_img, c.max_b, c.max_n, wg);
+  if (!L.ok || L.total > c.ws_bytes)
+    return fail(ctx, BLINK_ERR_SIZE, "workspace of %zu bytes is smaller than the %zu bytes one slot needs", c.ws_bytes,
+                L.total);
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
+  char* ws = (char*)c.ws;
+  blink::DescArgs a{};
+  a.desc = c.desc;
+  a.n_img = c.n_img;
+  a.vis = (const float2*)c.vis;
+  a.vis_len = c.vis_len;
+  a.uvw = c.uvw;
+  a.uvw_len = c.uvw_len;
+  a.flags = c.flags;
+  a.flags_len = c.flags_len;
+  a.max_b = c.max_b;
+  a.max_logn = max_logn;
+  a.weighting = c.weighting;
+  a.shift = c.shift != 0;
+  a.block = block;
+  a.images = c.images;
+  a.images_len = c.images_len;
+  a.weight_sum = c.weight_sum;
+  a.n_out = c.n_out;
+  a.status = c.status ? c.status : (int32_t*)(ws + L.status);
+  a.valid = (int*)(ws + L.valid);
+  a.order = (int*)(ws + L.order);
+  a.counter = (int*)(ws + L.counter);
+  a.plc = (int2*)(ws + L.plc);
+  a.strip_off = (int*)(ws + L.strip_off);
+  a.strip_stride = c.max_n / 2 + 1;
+  a.H = (float2*)(ws + L.H);
+  for (int l = 3; l <= 12; ++l) a.tw[l] = ctx->tw[l];
+  hipError_t e;
+  {
+    KernelTimer kt(ctx, BLINK_KERNEL_DESC_PREP, s);
+    e = blink::launch_desc_prep(a, s);
+  }
+  if (e == hipSuccess) {
+    KernelTimer kt(ctx, BLINK_KERNEL_PERSISTENT, s);
+    e = blink::launch_persistent(a, (int)wg, s);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "uneven-batch kernels");
+  return BLINK_OK;
+}
+
+}  // namespace
+
+struct blink_graph_s {
+  blink_ctx ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+blink_status blink_desc_workspace_size(int n_img, int max_baselines, int max_grid_n, int workgroups, size_t* bytes) {
+  if (!bytes || n_img < 0 || max_baselines < 0 || workgroups < 1) return BLINK_ERR_ARG;
+  if (log2_exact(max_grid_n) < 0) return BLINK_ERR_SIZE;
+  DescLayout L = desc_layout((size_t)n_img, (size_t)max_baselines, (size_t)max_grid_n,
+                             (size_t)(workgroups < n_img ? workgroups : (n_img > 0 ? n_img : 1)));
+  if (!L.ok) return BLINK_ERR_SIZE;
+  *bytes = L.total;
+  return BLINK_OK;
+}
+
+blink_status blink_image_batch_desc(blink_ctx ctx, const blink_image_desc* desc, int n_img, const blink_cf32* vis,
+                                    int64_t vis_len, const double* uvw_m, int64_t uvw_len, const uint8_t* flags,
+                                    int64_t flags_len, int max_baselines, int max_grid_n, int weighting,
+                                    int precision, int shift, float* images, int64_t images_len,
+                                    double* weight_sum, int32_t* n_out, int32_t* status, void* workspace,
+                                    size_t workspace_bytes, void* hip_stream) {
+  DescCall c{desc, n_img, vis, vis_len, uvw_m, uvw_len, flags, flags_len, max_baselines, max_grid_n, weighting,
+             precision, shift, images, images_len, weight_sum, n_out, status, workspace, workspace_bytes};
+  return run_desc(ctx, c, (hipStream_t)hip_stream);
+}
+
+blink_status blink_get_desc_plan(blink_ctx ctx, int* block_threads, int* workgroups) {
+  if (!ctx) return BLINK_ERR_ARG;
+  if (block_threads) *block_threads = ctx->desc_block;
+  if (workgroups) *workgroups = ctx->desc_workgroups;
+  return BLINK_OK;
+}
+
+blink_status blink_set_desc_plan(blink_ctx ctx, int block_threads, int workgroups) {
+  if (!ctx) return BLINK_ERR_ARG;
+  if ((block_threads != 512 && block_threads != 1024) || workgroups < 0)
+    return fail(ctx, BLINK_ERR_ARG, "descriptor plan needs block 512 or 1024 and workgroups >= 0");
+  ctx->desc_block = block_threads;
+  ctx->desc_workgroups = workgroups;
+  return BLINK_OK;
+}
+
+blink_status blink_autotune_desc(blink_ctx ctx, const blink_image_desc* desc, int n_img, const blink_cf32* vis,
+                                 int64_t vis_len, const double* uvw_m, int64_t uvw_len, const uint8_t* flags,
+                                 int64_t flags_len, int max_baselines, int max_grid_n, int weighting, int precision,
+                                 int shift, float* images, int64_t images_len, double* weight_sum, int32_t* n_out,
+                                 int32_t* status, void* workspace, size_t workspace_bytes, void* hip_stream,
+                                 int* block_threads, int* workgroups, double* best_ms) {
+  DescCall c{desc, n_img, vis, vis_len, uvw_m, uvw_len, flags, flags_len, max_baselines, max_grid_n, weighting,
+             precision, shift, images, images_len, weight_sum, n_out, status, workspace, workspace_bytes};
+  int max_logn = 0;
+  blink_status st = check_desc(ctx, c, &max_logn);
+  if (st != BLINK_OK) return st;
+  const int sb = ctx->desc_block, sw = ctx->desc_workgroups;
+  const bool was_profiling = ctx->profiling;
+  ctx->profiling = false;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    ctx->profiling = was_profiling;
+    return hip_fail(ctx, hipErrorOutOfMemory, "hipEventCreate");
+  }
+  const int blocks[] = {512, 1024};
+  double best = 1e300;
+  int bb = sb, bw = sw;
+  blink_status result = BLINK_OK;
+  for (int bi = 0; bi < 2 && result == BLINK_OK; ++bi) {
+    if (weighting && blocks[bi] != 512) continue;
+    const int resident = blink::persistent_blocks_per_cu(blocks[bi], weighting != 0) * ctx->cu_count;
+    const int counts[] = {0, resident / 2, resident / 4};
+    for (int wi = 0; wi < 3 && result == BLINK_OK; ++wi) {
+      if (wi > 0 && counts[wi] < 1) continue;
+      ctx->desc_block = blocks[bi];
+      ctx->desc_workgroups = counts[wi];
+      double t = 1e300;
+      for (int rep = 0; rep < 3 && result == BLINK_OK; ++rep) {
+        hipError_t he = hipEventRecord(e0, s);
+        result = run_desc(ctx, c, s);
+        if (he == hipSuccess) he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess && result == BLINK_OK) result = hip_fail(ctx, he, "autotune timing");
+        if (rep > 0 && ms < t) t = ms;
+      }
+      if (result == BLINK_OK && t < best) {
+        best = t;
+        bb = ctx->desc_block;
+        bw = ctx->desc_workgroups;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->profiling = was_profiling;
+  if (result != BLINK_OK) {
+    ctx->desc_block = sb;
+    ctx->desc_workgroups = sw;
+    return result;
+  }
+  ctx->desc_block = bb;
+  ctx->desc_workgroups = bw;
+  result = run_desc(ctx, c, s);
+  if (block_threads) *block_threads = bb;
+  if (workgroups) *workgroups = bw;
+  if (best_ms) *best_ms = best;
+  return result;
+}
+
+blink_status blink_graph_create_desc(blink_ctx ctx, const blink_image_desc* desc, int n_img, const blink_cf32* vis,
+                                     int64_t vis_len, const double* uvw_m, int64_t uvw_len, const uint8_t* flags,
+                                     int64_t flags_len, int max_baselines, int max_grid_n, int weighting,
+                                     int precision, int shift, float* images, int64_t images_len,
+                                     double* weight_sum, int32_t* n_out, int32_t* status, void* workspace,
+                                     size_t workspace_bytes, blink_graph* out) {
+  if (!out) return BLINK_ERR_ARG;
+  *out = nullptr;
+  DescCall c{desc, n_img, vis, vis_len, uvw_m, uvw_len, flags, flags_len, max_baselines, max_grid_n, weighting,
+             precision, shift, images, images_len, weight_sum, n_out, status, workspace, workspace_bytes};
+  int max_logn = 0;
+  blink_status st = check_desc(ctx, c, &max_logn);
+  if (st != BLINK_OK) return st;
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
+  blink_graph gr = new (std::nothrow) blink_graph_s;
+  if (!gr) return BLINK_ERR_NOMEM;
+  gr->ctx = ctx;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  const bool was_profiling = ctx->profiling;
+  ctx->profiling = false;                       // no event records inside the graph
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = run_desc(ctx, c, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &gr->graph);
+    if (st == BLINK_OK && e2 != hipSuccess) e = e2;
+  }
+  ctx->profiling = was_profiling;
+  if (e == hipSuccess && st == BLINK_OK) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (e != hipSuccess || st != BLINK_OK) {
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    delete gr;
+    if (st != BLINK_OK) return st;
+    return hip_fail(ctx, e, "graph capture");
+  }
+  *out = gr;
+  return BLINK_OK;
+}
+
+blink_status blink_graph_launch(blink_graph graph, void* hip_stream) {
+  if (!graph || !graph->exec) return BLINK_ERR_ARG;
+  DeviceGuard g(graph->ctx->device);
+  hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(graph->ctx, e, "hipGraphLaunch");
+  return BLINK_OK;
+}
+
+blink_status blink_graph_destroy(blink_graph graph) {
+  if (!graph) return BLINK_OK;
+  {
+    DeviceGuard g(graph->ctx->device);
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  }
+  delete graph;
   return BLINK_OK;
 }
 

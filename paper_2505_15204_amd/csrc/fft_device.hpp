@@ -174,61 +174,73 @@ __device__ __forceinline__ void stage_load_lds(float2 (&v)[R], const float2* buf
 
 // Full inverse FFT of one transform per group of T threads.
 // On entry v[m] holds element tid + m*T (the first stage's input order); `buf` is this
-// transform's padded LDS buffer and `tw` the LDS twiddle table for N. Every thread of the
-// block must call this (it contains block barriers). On return the caller's `sink(e, value)`
-// has been called for every output element e this thread owns (natural order, each element
+// transform's padded LDS buffer and `tw` the twiddle table for N (LDS or global). Every thread
+// of the block must call this (it contains block barriers); threads with active == false take
+// part in the barriers only and touch no memory. On return the caller's `sink(e, value)` has
+// been called for every output element e this thread owns (natural order, each element
 // exactly once across the T threads); when the last stage writes back to LDS instead
 // (ToLds = true) the result is in buf at pad(e) and the block is synchronised.
 template <int LOGN, bool ToLds, class Sink>
 __device__ __forceinline__ void fft_inverse(float2 (&v)[FftPlan<LOGN>::R], float2* buf,
-                                            const float2* __restrict__ tw, int tid, Sink sink) {
+                                            const float2* __restrict__ tw, int tid, Sink sink,
+                                            bool active = true) {
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, R = P::R, T = P::T;
-  stage_compute<N, R, T, 1, P::R0>(v, tid, tw);
+  if (active) stage_compute<N, R, T, 1, P::R0>(v, tid, tw);
   if constexpr (P::NST == 1) {
     if constexpr (ToLds) {
       __syncthreads();
-      stage_store_lds<N, R, T, 1, P::R0>(v, buf, tid);
+      if (active) stage_store_lds<N, R, T, 1, P::R0>(v, buf, tid);
       __syncthreads();
     } else {
+      if (active) {
 #pragma unroll
-      for (int m = 0; m < P::R0; ++m) sink(stage_out_index<T, 1, P::R0>(tid, 0, m), v[m]);
+        for (int m = 0; m < P::R0; ++m) sink(stage_out_index<T, 1, P::R0>(tid, 0, m), v[m]);
+      }
     }
   } else {
     __syncthreads();                       // the caller's loads of buf are complete
-    stage_store_lds<N, R, T, 1, P::R0>(v, buf, tid);
+    if (active) stage_store_lds<N, R, T, 1, P::R0>(v, buf, tid);
     __syncthreads();
-    stage_load_lds<N, R, T, P::R1>(v, buf, tid);
-    stage_compute<N, R, T, P::R0, P::R1>(v, tid, tw);
+    if (active) {
+      stage_load_lds<N, R, T, P::R1>(v, buf, tid);
+      stage_compute<N, R, T, P::R0, P::R1>(v, tid, tw);
+    }
     constexpr int Q1 = R / P::R1;
     if constexpr (P::NST == 2) {
       if constexpr (ToLds) {
         __syncthreads();
-        stage_store_lds<N, R, T, P::R0, P::R1>(v, buf, tid);
+        if (active) stage_store_lds<N, R, T, P::R0, P::R1>(v, buf, tid);
         __syncthreads();
       } else {
+        if (active) {
 #pragma unroll
-        for (int q = 0; q < Q1; ++q)
+          for (int q = 0; q < Q1; ++q)
 #pragma unroll
-          for (int m = 0; m < P::R1; ++m) sink(stage_out_index<T, P::R0, P::R1>(tid, q, m), v[q * P::R1 + m]);
+            for (int m = 0; m < P::R1; ++m) sink(stage_out_index<T, P::R0, P::R1>(tid, q, m), v[q * P::R1 + m]);
+        }
       }
     } else {
       __syncthreads();
-      stage_store_lds<N, R, T, P::R0, P::R1>(v, buf, tid);
+      if (active) stage_store_lds<N, R, T, P::R0, P::R1>(v, buf, tid);
       __syncthreads();
-      stage_load_lds<N, R, T, P::R2>(v, buf, tid);
       constexpr int NS2 = P::R0 * P::R1;
-      stage_compute<N, R, T, NS2, P::R2>(v, tid, tw);
+      if (active) {
+        stage_load_lds<N, R, T, P::R2>(v, buf, tid);
+        stage_compute<N, R, T, NS2, P::R2>(v, tid, tw);
+      }
       constexpr int Q2 = R / P::R2;
       if constexpr (ToLds) {
         __syncthreads();
-        stage_store_lds<N, R, T, NS2, P::R2>(v, buf, tid);
+        if (active) stage_store_lds<N, R, T, NS2, P::R2>(v, buf, tid);
         __syncthreads();
       } else {
+        if (active) {
 #pragma unroll
-        for (int q = 0; q < Q2; ++q)
+          for (int q = 0; q < Q2; ++q)
 #pragma unroll
-          for (int m = 0; m < P::R2; ++m) sink(stage_out_index<T, NS2, P::R2>(tid, q, m), v[q * P::R2 + m]);
+            for (int m = 0; m < P::R2; ++m) sink(stage_out_index<T, NS2, P::R2>(tid, q, m), v[q * P::R2 + m]);
+        }
       }
     }
   }

@@ -1,0 +1,281 @@
+// imaging_device.hpp — device building blocks shared by the batched kernels (kernels.hip) and the
+// persistent uneven-batch kernel (persistent.hip): nearest-cell binning, LDS-private strip
+// gridding fused with the column FFT, and the Hermitian-extended row FFT.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_device.hpp"
+
+namespace blink {
+
+constexpr int kLdsBytes = 160 * 1024;
+constexpr double kSpeedOfLight = 299792458.0;
+constexpr int kBinThreads = 1024;
+constexpr int kMaxStrips = 4096;
+
+__host__ __device__ constexpr int pow2_floor(int x) {
+  int p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// ---------------------------------------------------------------- block scan
+// Exclusive scan of v[0..n) in place by the whole workgroup (blockDim a multiple of 64, at most
+// 1024; n <= 8 * blockDim); v[n] receives the total. s_wave holds at least 17 ints.
+__device__ inline void block_exclusive_scan(int* v, int n, int* s_wave) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, w = tid >> 6, nw = nt >> 6;
+  const int per = (n + nt - 1) / nt;
+  const int base = tid * per;
+  int tsum = 0;
+  for (int j = 0; j < per; ++j)
+    if (base + j < n) tsum += v[base + j];
+  int x = tsum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) s_wave[w] = x;
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int i = 0; i < nw; ++i) {
+      int t = s_wave[i];
+      s_wave[i] = run;
+      run += t;
+    }
+    s_wave[nw] = run;
+  }
+  __syncthreads();
+  int excl = s_wave[w] + x - tsum;
+  for (int j = 0; j < per; ++j) {
+    if (base + j < n) {
+      const int t = v[base + j];
+      v[base + j] = excl;
+      excl += t;
+    }
+  }
+  if (tid == 0) v[n] = s_wave[nw];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- binning
+// Nearest cell of one visibility (Section 6.2.4). Returns 1 when kept (and sets iu, iv), 0 when
+// out of grid. k = (f/c)(N dl) cells per metre; iu = rint(u k), ties to even.
+__device__ __forceinline__ int nearest_cell(double u, double v, double k, double half, int& iu, int& iv) {
+  const double ru = rint(u * k);      // one IEEE double product, round half to even
+  const double rv = rint(v * k);
+  if (!(fabs(ru) < half && fabs(rv) < half)) return 0;   // NaN lands here too
+  iu = (int)ru;
+  iv = (int)rv;
+  return 1;
+}
+
+struct BinShared {
+  int cnt[kMaxStrips + 1];
+  int wave[17];
+  int red[2];
+};
+
+// Cell indices and the counting sort of one visibility set's placements into column strips of
+// width 2^log_strip, keeping only columns ku < ku_limit. Writes the placement list plc (each
+// record {kv*N + ku, b | conj<<31}), the strip offsets off[0..ku_limit>>log_strip], the kept and
+// out-of-grid counts, and cell_idx[b] when non-null. One workgroup (a multiple of 64 threads,
+// at least 512 so that the strip count fits the scan).
+__device__ inline void bin_visibilities(const double* __restrict__ uvw, const uint8_t* __restrict__ fl, int B,
+                                        double k, int logn, int log_strip, int ku_limit, int2* __restrict__ plc,
+                                        int* __restrict__ off, int* kept_out, int* nout_out,
+                                        int32_t* __restrict__ cell_idx, BinShared& sh) {
+  const int N = 1 << logn, mask = N - 1;
+  const int nstrips = ku_limit >> log_strip;
+  const double half = (double)(N / 2);
+  for (int i = threadIdx.x; i <= nstrips; i += blockDim.x) sh.cnt[i] = 0;
+  if (threadIdx.x < 2) sh.red[threadIdx.x] = 0;
+  __syncthreads();
+  int kept = 0, outside = 0;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    int cell = -1;
+    if (!(fl && fl[b])) {
+      int iu, iv;
+      if (nearest_cell(uvw[3 * b], uvw[3 * b + 1], k, half, iu, iv)) {
+        const int ku1 = iu & mask, kv1 = iv & mask, ku2 = (-iu) & mask;
+        cell = kv1 * N + ku1;
+        ++kept;
+        if (ku1 < ku_limit) atomicAdd(&sh.cnt[ku1 >> log_strip], 1);
+        if (ku2 < ku_limit) atomicAdd(&sh.cnt[ku2 >> log_strip], 1);
+      } else {
+        cell = -2;
+        ++outside;
+      }
+    }
+    if (cell_idx) cell_idx[b] = cell;
+  }
+  if (kept) atomicAdd(&sh.red[0], kept);
+  if (outside) atomicAdd(&sh.red[1], outside);
+  __syncthreads();
+  block_exclusive_scan(sh.cnt, nstrips, sh.wave);
+  for (int i = threadIdx.x; i <= nstrips; i += blockDim.x) off[i] = sh.cnt[i];
+  if (threadIdx.x == 0) {
+    *kept_out = sh.red[0];
+    if (nout_out) *nout_out = sh.red[1];
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    if (fl && fl[b]) continue;
+    int iu, iv;
+    if (!nearest_cell(uvw[3 * b], uvw[3 * b + 1], k, half, iu, iv)) continue;
+    const int ku1 = iu & mask, kv1 = iv & mask;
+    const int ku2 = (-iu) & mask, kv2 = (-iv) & mask;
+    if (ku1 < ku_limit) {
+      int pos = atomicAdd(&sh.cnt[ku1 >> log_strip], 1);
+      plc[pos] = make_int2(kv1 * N + ku1, b);
+    }
+    if (ku2 < ku_limit) {
+      int pos = atomicAdd(&sh.cnt[ku2 >> log_strip], 1);
+      plc[pos] = make_int2(kv2 * N + ku2, (int)((unsigned)b | 0x80000000u));
+    }
+  }
+}
+
+// ---------------------------------------------------------------- scatter into an LDS strip
+// Accumulates the placements [o0, o1) of strip `strip` into the LDS strip buffer (column c at
+// sbuf[c*stride + pad(kv)] when PADDED, else sbuf[c*stride + kv]); V are the image's
+// visibilities; the mirrored placement takes the conjugate; `modulate` applies (-1)^(ku+kv).
+template <int LOGN, int S, bool PADDED, bool COUNT>
+__device__ __forceinline__ void scatter_strip(const int2* __restrict__ plc, int o0, int o1,
+                                              const float2* __restrict__ V, int strip, int stride,
+                                              bool modulate, float2* sbuf, unsigned* scnt) {
+  constexpr int N = 1 << LOGN;
+  for (int i = o0 + (int)threadIdx.x; i < o1; i += blockDim.x) {
+    const int2 r = plc[i];
+    const int kv = r.x >> LOGN, ku = r.x & (N - 1);
+    const int b = r.y & 0x7fffffff;
+    float2 val = V[b];
+    if (r.y < 0) val.y = -val.y;
+    if (modulate && ((kv + ku) & 1)) {
+      val.x = -val.x;
+      val.y = -val.y;
+    }
+    const int col = ku - strip * S;
+    float2* dst = sbuf + col * stride + (PADDED ? pad_index(kv) : kv);
+    atomicAdd(&dst->x, val.x);
+    atomicAdd(&dst->y, val.y);
+    if constexpr (COUNT) atomicAdd(&scnt[col * N + kv], 1u);
+  }
+}
+
+// Uniform weighting: cell mean; returns this thread's occupied-cell count (weighted).
+template <int LOGN, int S, bool PADDED>
+__device__ __forceinline__ int uniform_divide(float2* sbuf, const unsigned* scnt, int stride, int col_weight0,
+                                              int col_weight) {
+  constexpr int N = 1 << LOGN;
+  int occ = 0;
+  for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
+    const int col = i >> LOGN, kv = i & (N - 1);
+    const unsigned n = scnt[i];
+    if (n) {
+      float2* p = sbuf + col * stride + (PADDED ? pad_index(kv) : kv);
+      const float inv = 1.0f / (float)n;
+      p->x *= inv;
+      p->y *= inv;
+      occ += (col == 0) ? col_weight0 : col_weight;
+    }
+  }
+  return occ;
+}
+
+// Adds one value per thread into *dst with a single global atomic per workgroup.
+__device__ __forceinline__ void block_add_to_global(int val, int* s_tmp, int* dst) {
+  if (val) atomicAdd(s_tmp, val);
+  __syncthreads();
+  if (threadIdx.x == 0 && *s_tmp) atomicAdd(dst, *s_tmp);
+}
+
+// ---------------------------------------------------------------- fused grid + column FFT task
+// One strip of S half-spectrum columns of one image: zero the LDS strip, scatter the strip's
+// placements, (uniform) divide by counts and add the strip's occupied cells (column 0 once,
+// columns 1..N/2-1 twice for their mirrors) to *occ_img, inverse FFT every column along v, and
+// store the strip into Hi[y][strip*S + c]. Column 0 is stored as (Re of its transform, 0): the
+// real part is the transform of the column's Hermitian part, and the Nyquist column is empty.
+// Threads beyond S*T of the workgroup only join the barriers. `tw` is the twiddle table for N.
+template <int LOGN, int S, bool UNIFORM>
+__device__ __forceinline__ void grid_colfft_task(const float2* __restrict__ V, const int2* __restrict__ plc, int o0,
+                                                 int o1, int strip, bool shift, float2* __restrict__ Hi,
+                                                 int* occ_img, const float2* __restrict__ tw, float2* sbuf,
+                                                 unsigned* scnt, int* s_tmp) {
+  using P = FftPlan<LOGN>;
+  constexpr int N = P::N, T = P::T, NP = P::NP;
+  for (int i = threadIdx.x; i < S * NP; i += blockDim.x) sbuf[i] = make_float2(0.f, 0.f);
+  if constexpr (UNIFORM)
+    for (int i = threadIdx.x; i < S * N; i += blockDim.x) scnt[i] = 0u;
+  if (threadIdx.x == 0) *s_tmp = 0;
+  __syncthreads();
+  scatter_strip<LOGN, S, true, UNIFORM>(plc, o0, o1, V, strip, NP, shift, sbuf, scnt);
+  __syncthreads();
+  if constexpr (UNIFORM) {
+    int occ = uniform_divide<LOGN, S, true>(sbuf, scnt, NP, strip == 0 ? 1 : 2, 2);
+    block_add_to_global(occ, s_tmp, occ_img);
+    __syncthreads();
+  }
+  const bool active = (int)threadIdx.x < S * T;
+  const int col = active ? (int)threadIdx.x / T : 0, lt = (int)threadIdx.x % T;
+  float2* cb = sbuf + col * NP;
+  float2 v[P::R];
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < P::R; ++m) v[m] = cb[pad_index(lt + m * T)];
+  }
+  fft_inverse<LOGN, true>(v, cb, tw, lt, [](int, float2) {}, active);
+  for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
+    const int y = i / S, c = i % S;
+    float2 val = sbuf[c * NP + pad_index(y)];
+    if (strip == 0 && c == 0) val.y = 0.f;
+    Hi[(size_t)y * (N / 2) + strip * S + c] = val;
+  }
+}
+
+// ---------------------------------------------------------------- row task
+// Row-pair transforms j < TPB of row block `rowblk` of one image: rows y1 = 2r, y2 = 2r + 1 with
+// r = rowblk*TPB + j. Z[e] = Hf1[e] + i Hf2[e], where Hf is the Hermitian extension of a stored
+// half row: Hf[0] = Re H[0], Hf[N/2] = Im H[0], Hf[e] = H[e] (0 < e < N/2), Hf[e] = conj H[N-e].
+// The inverse FFT of Z is I1 + i I2 with both rows real; they are scaled by `scale` and stored.
+// The caller makes `tw` visible to the whole workgroup before the FFT's first barrier.
+template <int LOGN, int TPB>
+__device__ __forceinline__ void row_task(const float2* __restrict__ H, int rowblk, float scale, float* __restrict__ out,
+                                         const float2* __restrict__ tw, float2* sbuf) {
+  using P = FftPlan<LOGN>;
+  constexpr int N = P::N, T = P::T, NP = P::NP, HALF = N / 2;
+  const int j = (int)threadIdx.x / T, lt = (int)threadIdx.x % T;
+  const bool active = j < TPB;
+  const int r = rowblk * TPB + (active ? j : 0);
+  const float2* h1 = H + (size_t)(2 * r) * HALF;
+  const float2* h2 = h1 + HALF;
+  float2 v[P::R];
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < P::R; ++m) {
+      const int e = lt + m * T;
+      const int idx = (e < HALF) ? e : ((e == HALF) ? 0 : N - e);
+      const float2 a = h1[idx], b = h2[idx];
+      if (e == 0) v[m] = make_float2(a.x, b.x);
+      else if (e == HALF) v[m] = make_float2(a.y, b.y);
+      else if (e < HALF) v[m] = make_float2(a.x - b.y, a.y + b.x);
+      else v[m] = make_float2(a.x + b.y, b.x - a.y);
+    }
+  }
+  __syncthreads();   // the caller's twiddle table is visible
+  float* o1 = out + (size_t)(2 * r) * N;
+  float* o2 = o1 + N;
+  fft_inverse<LOGN, false>(v, sbuf + (active ? j : 0) * NP, tw, lt, [&](int e, float2 z) {
+    o1[e] = z.x * scale;
+    o2[e] = z.y * scale;
+  }, active);
+}
+
+__device__ __forceinline__ float inverse_weight(double W) {
+  return (W > 0.0 && isfinite(W)) ? (float)(1.0 / W) : 0.f;
+}
+
+}  // namespace blink

@@ -17,20 +17,10 @@
 // the two real-valued columns ku = 0 (real part) and ku = N/2 (imaginary part).
 #include <hip/hip_runtime.h>
 
-#include "fft_device.hpp"
+#include "imaging_device.hpp"
 #include "launch.hpp"
 
 namespace blink {
-
-constexpr int kLdsBytes = 160 * 1024;
-constexpr double kSpeedOfLight = 299792458.0;
-
-__host__ __device__ constexpr int pow2_floor(int x) {
-  int p = 1;
-  while (p * 2 <= x) p *= 2;
-  return p;
-}
-__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
 // ---------------------------------------------------------------- configuration
 // Largest strip width (columns per workgroup) of the fused column kernel that fits 1024 threads
@@ -82,193 +72,26 @@ hipError_t launch_twiddles(float2* tw, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- block scan
-// Exclusive scan of v[0..n) in place with 1024 threads (n <= 4096); v[n] receives the total.
-__device__ void block_exclusive_scan_1024(int* v, int n, int* s_wave) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int base = tid * 4;
-  int a[4];
-  int tsum = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    a[j] = (base + j < n) ? v[base + j] : 0;
-    tsum += a[j];
-  }
-  int x = tsum;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    int y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  if (lane == 63) s_wave[w] = x;
-  __syncthreads();
-  if (tid == 0) {
-    int run = 0;
-    for (int i = 0; i < 16; ++i) {
-      int t = s_wave[i];
-      s_wave[i] = run;
-      run += t;
-    }
-    s_wave[16] = run;
-  }
-  __syncthreads();
-  int excl = s_wave[w] + x - tsum;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    if (base + j < n) v[base + j] = excl;
-    excl += a[j];
-  }
-  if (tid == 0) v[n] = s_wave[16];
-  __syncthreads();
-}
-
 // ---------------------------------------------------------------- binning
-// Nearest cell of one visibility. Returns 1 when kept (and sets iu, iv), 0 when out of grid.
-__device__ __forceinline__ int nearest_cell(double u, double v, double k, double half, int& iu, int& iv) {
-  const double ru = rint(u * k);      // one IEEE double product, round half to even
-  const double rv = rint(v * k);
-  if (!(fabs(ru) < half && fabs(rv) < half)) return 0;   // NaN lands here too
-  iu = (int)ru;
-  iv = (int)rv;
-  return 1;
-}
-
-constexpr int kBinThreads = 1024;
-constexpr int kMaxStrips = 4096;
-
 __global__ __launch_bounds__(kBinThreads) void k_bin(BinArgs a) {
-  __shared__ int s_cnt[kMaxStrips + 1];
-  __shared__ int s_wave[17];
-  __shared__ int s_red[2];
+  __shared__ BinShared sh;
   const int tcl = blockIdx.x;
   const long tc = (long)a.tc0 + tcl;
   const int t = (int)(tc / a.C), c = (int)(tc % a.C);
-  const int N = 1 << a.logn, mask = N - 1;
+  const int N = 1 << a.logn;
   const int nstrips = a.ku_limit >> a.log_strip;
   const double k = (a.freq[c] / kSpeedOfLight) * ((double)N * a.pixel_scale);
-  const double half = (double)(N / 2);
-  const double* uvw = a.uvw + (size_t)t * a.B * 3;
-  const uint8_t* fl = a.flags ? a.flags + (size_t)tc * a.B : nullptr;
-
-  for (int i = threadIdx.x; i <= nstrips; i += blockDim.x) s_cnt[i] = 0;
-  if (threadIdx.x < 2) s_red[threadIdx.x] = 0;
-  __syncthreads();
-
-  int kept = 0, outside = 0;
-  for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
-    int cell = -1;
-    if (!(fl && fl[b])) {
-      int iu, iv;
-      if (nearest_cell(uvw[3 * b], uvw[3 * b + 1], k, half, iu, iv)) {
-        const int ku1 = iu & mask, kv1 = iv & mask, ku2 = (-iu) & mask;
-        cell = kv1 * N + ku1;
-        ++kept;
-        if (ku1 < a.ku_limit) atomicAdd(&s_cnt[ku1 >> a.log_strip], 1);
-        if (ku2 < a.ku_limit) atomicAdd(&s_cnt[ku2 >> a.log_strip], 1);
-      } else {
-        cell = -2;
-        ++outside;
-      }
-    }
-    if (a.cell_idx) a.cell_idx[(size_t)tc * a.B + b] = cell;
-  }
-  // block reduction of the two counters
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    kept += __shfl_down(kept, off, 64);
-    outside += __shfl_down(outside, off, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    atomicAdd(&s_red[0], kept);
-    atomicAdd(&s_red[1], outside);
-  }
-  __syncthreads();
-  block_exclusive_scan_1024(s_cnt, nstrips, s_wave);
-  int* off = a.strip_off + (size_t)tcl * (nstrips + 1);
-  for (int i = threadIdx.x; i <= nstrips; i += blockDim.x) off[i] = s_cnt[i];
-  if (threadIdx.x == 0) {
-    a.n_kept[tcl] = s_red[0];
-    if (a.n_out) a.n_out[tc] = s_red[1];
-  }
+  bin_visibilities(a.uvw + (size_t)t * a.B * 3, a.flags ? a.flags + (size_t)tc * a.B : nullptr, a.B, k, a.logn,
+                   a.log_strip, a.ku_limit, a.plc + (size_t)tcl * 2 * a.B, a.strip_off + (size_t)tcl * (nstrips + 1),
+                   a.n_kept + tcl, a.n_out ? a.n_out + tc : nullptr, a.cell_idx ? a.cell_idx + (size_t)tc * a.B : nullptr,
+                   sh);
   if (threadIdx.x < a.P) a.occ[(size_t)tcl * a.P + threadIdx.x] = 0;
-  __syncthreads();
-
-  int2* plc = a.plc + (size_t)tcl * 2 * a.B;
-  for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
-    if (fl && fl[b]) continue;
-    int iu, iv;
-    if (!nearest_cell(uvw[3 * b], uvw[3 * b + 1], k, half, iu, iv)) continue;
-    const int ku1 = iu & mask, kv1 = iv & mask;
-    const int ku2 = (-iu) & mask, kv2 = (-iv) & mask;
-    if (ku1 < a.ku_limit) {
-      int pos = atomicAdd(&s_cnt[ku1 >> a.log_strip], 1);
-      plc[pos] = make_int2(kv1 * N + ku1, b);
-    }
-    if (ku2 < a.ku_limit) {
-      int pos = atomicAdd(&s_cnt[ku2 >> a.log_strip], 1);
-      plc[pos] = make_int2(kv2 * N + ku2, (int)((unsigned)b | 0x80000000u));
-    }
-  }
 }
 
 hipError_t launch_bin(const BinArgs& a, hipStream_t s) {
   if (a.Q <= 0) return hipSuccess;
   k_bin<<<a.Q, kBinThreads, 0, s>>>(a);
   return hipGetLastError();
-}
-
-// ---------------------------------------------------------------- scatter into an LDS strip
-// Accumulates the placements of strip `strip` of one (t,c) pair into the LDS strip buffer
-// (column c at sbuf[c*stride + pad(kv)] when PADDED, else sbuf[c*stride + kv]).
-template <int LOGN, int S, bool PADDED, bool COUNT>
-__device__ __forceinline__ void scatter_strip(const int2* __restrict__ plc, int o0, int o1,
-                                              const float2* __restrict__ V, int strip, int stride,
-                                              bool modulate, float2* sbuf, unsigned* scnt) {
-  constexpr int N = 1 << LOGN;
-  for (int i = o0 + (int)threadIdx.x; i < o1; i += blockDim.x) {
-    const int2 r = plc[i];
-    const int kv = r.x >> LOGN, ku = r.x & (N - 1);
-    const int b = r.y & 0x7fffffff;
-    float2 val = V[b];
-    if (r.y < 0) val.y = -val.y;
-    if (modulate && ((kv + ku) & 1)) {
-      val.x = -val.x;
-      val.y = -val.y;
-    }
-    const int col = ku - strip * S;
-    float2* dst = sbuf + col * stride + (PADDED ? pad_index(kv) : kv);
-    atomicAdd(&dst->x, val.x);
-    atomicAdd(&dst->y, val.y);
-    if constexpr (COUNT) atomicAdd(&scnt[col * N + kv], 1u);
-  }
-}
-
-// Uniform weighting: cell mean; returns this thread's occupied-cell count (weighted).
-template <int LOGN, int S, bool PADDED>
-__device__ __forceinline__ int uniform_divide(float2* sbuf, const unsigned* scnt, int stride, int col_weight0,
-                                              int col_weight) {
-  constexpr int N = 1 << LOGN;
-  int occ = 0;
-  for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
-    const int col = i >> LOGN, kv = i & (N - 1);
-    const unsigned n = scnt[i];
-    if (n) {
-      float2* p = sbuf + col * stride + (PADDED ? pad_index(kv) : kv);
-      const float inv = 1.0f / (float)n;
-      p->x *= inv;
-      p->y *= inv;
-      occ += (col == 0) ? col_weight0 : col_weight;
-    }
-  }
-  return occ;
-}
-
-__device__ __forceinline__ void block_add_to_global(int val, int* s_tmp, int* dst) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) val += __shfl_down(val, off, 64);
-  if ((threadIdx.x & 63) == 0 && val) atomicAdd(s_tmp, val);
-  __syncthreads();
-  if (threadIdx.x == 0 && *s_tmp) atomicAdd(dst, *s_tmp);
 }
 
 // ---------------------------------------------------------------- full grid (blink_grid)
@@ -315,7 +138,7 @@ __global__ __launch_bounds__(256) void k_grid_full(GridArgs a) {
 template <int LOGN, int S, bool UNIFORM>
 __global__ __launch_bounds__(S * FftPlan<LOGN>::T) void k_grid_colfft(ColArgs a, const float2* __restrict__ twg) {
   using P = FftPlan<LOGN>;
-  constexpr int N = P::N, T = P::T, NP = P::NP;
+  constexpr int N = P::N, NP = P::NP;
   __shared__ float2 sbuf[S * NP];
   __shared__ float2 stw[N];
   __shared__ unsigned scnt[UNIFORM ? S * N : 1];
@@ -324,37 +147,11 @@ __global__ __launch_bounds__(S * FftPlan<LOGN>::T) void k_grid_colfft(ColArgs a,
   const int slot = blockIdx.x, img = a.img0 + slot, strip = blockIdx.y;
   const int tcl = img / a.P;
   const int nstrips = (N / 2) / S;
-  for (int i = threadIdx.x; i < S * NP; i += blockDim.x) sbuf[i] = make_float2(0.f, 0.f);
-  if constexpr (UNIFORM)
-    for (int i = threadIdx.x; i < S * N; i += blockDim.x) scnt[i] = 0u;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = twg[i];
-  if (threadIdx.x == 0) s_tmp = 0;
-  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = twg[i];   // visible after the task's first barrier
   const int* so = a.strip_off + (size_t)tcl * (nstrips + 1);
-  scatter_strip<LOGN, S, true, UNIFORM>(a.plc + (size_t)tcl * 2 * a.B, so[strip], so[strip + 1],
-                                        a.vis + (size_t)img * a.B, strip, NP, a.shift != 0, sbuf, scnt);
-  __syncthreads();
-  if constexpr (UNIFORM) {
-    // Column 0 of the grid is its own mirror; every other column ku < N/2 stands for itself
-    // and its mirror N - ku, so its occupied cells count twice.
-    int occ = uniform_divide<LOGN, S, true>(sbuf, scnt, NP, strip == 0 ? 1 : 2, 2);
-    block_add_to_global(occ, &s_tmp, a.occ + img);
-    __syncthreads();
-  }
-  const int col = threadIdx.x / T, lt = threadIdx.x % T;
-  float2* cb = sbuf + col * NP;
-  float2 v[P::R];
-#pragma unroll
-  for (int m = 0; m < P::R; ++m) v[m] = cb[pad_index(lt + m * T)];
-  fft_inverse<LOGN, true>(v, cb, stw, lt, [](int, float2) {});
-  // H[slot][y][strip*S + c]; column 0 carries (Re of the ku = 0 transform, ku = N/2 transform = 0).
-  float2* Hi = a.H + (size_t)slot * N * (N / 2);
-  for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
-    const int y = i / S, c = i % S;
-    float2 val = sbuf[c * NP + pad_index(y)];
-    if (strip == 0 && c == 0) val.y = 0.f;
-    Hi[(size_t)y * (N / 2) + strip * S + c] = val;
-  }
+  grid_colfft_task<LOGN, S, UNIFORM>(a.vis + (size_t)img * a.B, a.plc + (size_t)tcl * 2 * a.B, so[strip], so[strip + 1],
+                                     strip, a.shift != 0, a.H + (size_t)slot * N * (N / 2), a.occ + img, stw, sbuf, scnt,
+                                     &s_tmp);
 }
 
 // ---------------------------------------------------------------- dense grid column FFT
@@ -436,36 +233,15 @@ __device__ __forceinline__ double image_weight(const RowArgs& a, int img) {
 template <int LOGN, int TPB>
 __global__ __launch_bounds__(TPB * FftPlan<LOGN>::T) void k_row_c2r(RowArgs a, const float2* __restrict__ twg) {
   using P = FftPlan<LOGN>;
-  constexpr int N = P::N, T = P::T, NP = P::NP, HALF = N / 2;
+  constexpr int N = P::N, NP = P::NP;
   __shared__ float2 sbuf[TPB * NP];
   __shared__ float2 stw[N];
   const int slot = blockIdx.x, img = a.img0 + slot;
-  const int j = threadIdx.x / T, lt = threadIdx.x % T;
-  const int r = blockIdx.y * TPB + j;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = twg[i];
-  const float2* h1 = a.H + ((size_t)slot * N + 2 * r) * HALF;
-  const float2* h2 = h1 + HALF;
-  float2 v[P::R];
-#pragma unroll
-  for (int m = 0; m < P::R; ++m) {
-    const int e = lt + m * T;
-    const int idx = (e < HALF) ? e : ((e == HALF) ? 0 : N - e);
-    const float2 a = h1[idx], b = h2[idx];
-    if (e == 0) v[m] = make_float2(a.x, b.x);
-    else if (e == HALF) v[m] = make_float2(a.y, b.y);
-    else if (e < HALF) v[m] = make_float2(a.x - b.y, a.y + b.x);
-    else v[m] = make_float2(a.x + b.y, b.x - a.y);
-  }
-  __syncthreads();   // twiddles in LDS
+  for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = twg[i];   // visible after row_task's barrier
   const double W = image_weight(a, img);
-  const float s = (W > 0.0 && isfinite(W)) ? (float)(1.0 / W) : 0.f;
   if (a.weight_sum && blockIdx.y == 0 && threadIdx.x == 0) a.weight_sum[img] = W;
-  float* o1 = a.images + ((size_t)slot * N + 2 * r) * N;
-  float* o2 = o1 + N;
-  fft_inverse<LOGN, false>(v, sbuf + j * NP, stw, lt, [&](int e, float2 z) {
-    o1[e] = z.x * s;
-    o2[e] = z.y * s;
-  });
+  row_task<LOGN, TPB>(a.H + (size_t)slot * N * (N / 2), blockIdx.y, inverse_weight(W),
+                      a.images + (size_t)slot * N * N, stw, sbuf);
 }
 
 // ---------------------------------------------------------------- dispatch

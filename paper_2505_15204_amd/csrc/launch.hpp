@@ -5,6 +5,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "blink.h"
+
 namespace blink {
 
 // Compiled variants per grid size (largest first); each returns the number written to `out` (<= 4).
@@ -79,5 +81,36 @@ struct RowArgs {
   double* weight_sum;       // chunk base or null
 };
 hipError_t launch_row_c2r(const RowArgs& a, int n_img, int tpb, const float2* tw, hipStream_t s);
+
+// ---------------------------------------------------------------- uneven batches (persistent.hip)
+struct DescArgs {
+  const blink_image_desc* desc;
+  int n_img;
+  const float2* vis;
+  int64_t vis_len;
+  const double* uvw;
+  int64_t uvw_len;                 // baselines
+  const uint8_t* flags;
+  int64_t flags_len;
+  int max_b, max_logn, weighting, shift, block;
+  float* images;
+  int64_t images_len;
+  double* weight_sum;              // [n_img] or null
+  int32_t* n_out;                  // [n_img] or null
+  int32_t* status;                 // [1] (caller's or workspace)
+  // workspace
+  int* valid;                      // [n_img] 1 if the descriptor passed the checks
+  int* order;                      // [n_img] processing order (largest grids first)
+  int* counter;                    // [1] next position in `order`
+  int2* plc;                       // [workgroups][2 max_b]
+  int* strip_off;                  // [workgroups][strip_stride]
+  int strip_stride;
+  float2* H;                       // [workgroups][max_n * max_n / 2]
+  const float2* tw[13];            // twiddle tables per log2 N
+};
+hipError_t launch_desc_prep(const DescArgs& a, hipStream_t s);
+hipError_t launch_persistent(const DescArgs& a, int workgroups, hipStream_t s);
+// Resident workgroups of the persistent kernel per CU (0 if the configuration is not compiled).
+int persistent_blocks_per_cu(int block, bool uniform);
 
 }  // namespace blink

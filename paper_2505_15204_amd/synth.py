@@ -225,3 +225,100 @@ def make_problem_device(spec: Spec, device, seed: Optional[int] = None):
         flags[t] = (torch.rand((spec.C, spec.B), generator=gen, device=device)
                     < spec.flag_frac).to(torch.uint8)
     return {"uvw_m": uvw_d, "freq_hz": freq_d, "flags": flags, "vis": vis}
+
+
+# ---------------------------------------------------------------------------- uneven batches
+def uneven_layout(n_img: int = 4096, config: int = 5, n_tiles: int = 128, f_lo: float = 70.0e6,
+                  f_hi: float = 300.0e6, sizes=(512, 1024, 2048), thresholds=(120.0e6, 200.0e6),
+                  unflagged=(0.7, 1.0), n_src: int = 50, margin: float = 1.05):
+    """Layout of a batch of images with channel-dependent grid sizes and visibility counts.
+
+    Image i observes f_i = f_lo + (f_hi - f_lo)(i + 1/2)/n_img; its grid is sizes[0] below
+    thresholds[0], sizes[1] below thresholds[1], else sizes[2]; its pixel scale is
+    dl_i = 1 / (2 margin u_max f_i / c) so that every baseline falls on the grid; it keeps a
+    fraction U[unflagged] of the baselines: a cyclic window of a seeded permutation of the array's
+    baselines, stored once twice over so every window is contiguous. Returns a dict with the
+    per-image fields of the descriptors (vis, uvw and image offsets, B_i, N_i, f_i, dl_i), the
+    doubled baseline table uvw_ext [2B][3] and the sky.
+    """
+    g = rng(config, STREAM_IMAGES)
+    pos = tile_positions(n_tiles, rng(config, STREAM_TILES))
+    uvw = baseline_uvw(pos)
+    B = uvw.shape[0]
+    perm = g.permutation(B)
+    uvw_ext = np.concatenate([uvw[perm], uvw[perm]], axis=0)
+    u_max = float(np.abs(uvw[:, :2]).max())
+    freq = f_lo + (f_hi - f_lo) * (np.arange(n_img) + 0.5) / n_img
+    grid_n = np.where(freq < thresholds[0], sizes[0], np.where(freq < thresholds[1], sizes[1], sizes[2]))
+    dl = 1.0 / (2.0 * margin * u_max * freq / C_LIGHT)
+    frac = g.uniform(unflagged[0], unflagged[1], n_img)
+    nb = np.maximum(1, np.round(frac * B)).astype(np.int64)
+    start = g.integers(0, B, n_img)
+    vis_off = np.concatenate([[0], np.cumsum(nb)[:-1]])
+    img_off = np.concatenate([[0], np.cumsum(grid_n.astype(np.int64) ** 2)[:-1]])
+    sky = sky_model(n_src, rng(config, STREAM_SKY))
+    return {"n_img": n_img, "B": B, "uvw_ext": uvw_ext, "freq_hz": freq, "grid_n": grid_n.astype(np.int64),
+            "pixel_scale": dl, "n_baselines": nb, "uvw_offset": start, "vis_offset": vis_off,
+            "image_offset": img_off, "vis_len": int(nb.sum()),
+            "images_len": int((grid_n.astype(np.int64) ** 2).sum()), "max_b": int(nb.max()),
+            "max_n": int(grid_n.max()), "sky": sky, "config": config}
+
+
+def uneven_descriptors(lay, dtype):
+    """The layout's descriptors as a structured array of `dtype` (the library's blink_image_desc)."""
+    d = np.zeros(lay["n_img"], dtype=dtype)
+    d["vis_offset"] = lay["vis_offset"]
+    d["uvw_offset"] = lay["uvw_offset"]
+    d["flag_offset"] = 0
+    d["image_offset"] = lay["image_offset"]
+    d["freq_hz"] = lay["freq_hz"]
+    d["pixel_scale"] = lay["pixel_scale"]
+    d["n_baselines"] = lay["n_baselines"]
+    d["grid_n"] = lay["grid_n"]
+    return d
+
+
+def uneven_image_inputs(lay, i, noise_sigma: float = 0.1):
+    """Visibilities (complex64 [B_i]) and uvw ([B_i][3]) of image i on the host."""
+    o, n = int(lay["uvw_offset"][i]), int(lay["n_baselines"][i])
+    uvw = lay["uvw_ext"][o:o + n]
+    model = model_visibilities(uvw, np.array([lay["freq_hz"][i]]), lay["sky"])[0]
+    ng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(
+        entropy=ENTROPY, spawn_key=(lay["config"], STREAM_NOISE, i))))
+    noise = ng.normal(0.0, noise_sigma, size=(n, 2))
+    vis = np.empty(n, np.complex64)
+    vis.real = model.real + noise[:, 0]
+    vis.imag = model.imag + noise[:, 1]
+    return vis, uvw
+
+
+def uneven_vis_host(lay, noise_sigma: float = 0.1):
+    """All packed visibilities on the host (complex64 [sum B_i]); for small batches."""
+    out = np.empty(lay["vis_len"], np.complex64)
+    for i in range(lay["n_img"]):
+        v, _ = uneven_image_inputs(lay, i, noise_sigma)
+        o = int(lay["vis_offset"][i])
+        out[o:o + v.size] = v
+    return out
+
+
+def uneven_vis_device(lay, device, noise_sigma: float = 0.1, seed: Optional[int] = None):
+    """All packed visibilities generated on the device (same model; noise from a torch generator)."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(ENTROPY * 16 + lay["config"] if seed is None else seed)
+    s, l, m = (torch.from_numpy(x).to(device) for x in lay["sky"])
+    ext = torch.from_numpy(lay["uvw_ext"]).to(device)
+    out = torch.empty(lay["vis_len"], dtype=torch.complex64, device=device)
+    ov = torch.view_as_real(out)
+    for i in range(lay["n_img"]):
+        o, n, vo = int(lay["uvw_offset"][i]), int(lay["n_baselines"][i]), int(lay["vis_offset"][i])
+        uvw = ext[o:o + n]
+        ph = (-2.0 * math.pi * lay["freq_hz"][i] / C_LIGHT) * (uvw[:, 0:1] * l[None] + uvw[:, 1:2] * m[None])
+        re = torch.cos(ph) @ s
+        im = torch.sin(ph) @ s
+        noise = torch.randn((n, 2), generator=gen, device=device, dtype=torch.float32) * noise_sigma
+        ov[vo:vo + n, 0] = re.to(torch.float32) + noise[:, 0]
+        ov[vo:vo + n, 1] = im.to(torch.float32) + noise[:, 1]
+    return out

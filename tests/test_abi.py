@@ -89,3 +89,25 @@ def test_workspace_sizes(L):
         assert e.value.status == blink.BLINK_ERR_SIZE
     with pytest.raises(blink.BlinkError):
         blink.image_batch_workspace_size(1, 1, 1, 10, 64, precision=5)
+
+
+def test_desc_workspace_and_validation(L):
+    s = blink.desc_workspace_size(10, 100, 256, 4)
+    assert s >= 4 * 2 * 100 * 8 + 4 * 256 * 128 * 8
+    assert blink.desc_workspace_size(10, 100, 256, 8) > s
+    assert blink.desc_workspace_size(10, 100, 256, 64) == blink.desc_workspace_size(10, 100, 256, 10)
+    with pytest.raises(blink.BlinkError):
+        blink.desc_workspace_size(10, 100, 300, 4)
+    dummy = ctypes.c_void_p(0x1000)
+    # bad max_grid_n, negative n_img, unknown weighting, NULL context: rejected before any device work
+    args = lambda n_img=1, max_n=256, w=0, prec=0: [None, dummy, n_img, dummy, 10, dummy, 10, None, 0, 10, max_n, w,
+                                                  prec, 1, dummy, 1 << 20, None, None, None, ctypes.c_void_p(0x10000),
+                                                  1 << 24, None]
+    assert L.blink_image_batch_desc(*args(max_n=300)) == blink.BLINK_ERR_SIZE
+    assert L.blink_image_batch_desc(*args(n_img=-1)) == blink.BLINK_ERR_ARG
+    assert L.blink_image_batch_desc(*args(w=3)) == blink.BLINK_ERR_ARG
+    assert L.blink_image_batch_desc(*args(prec=4)) == blink.BLINK_ERR_ARG
+    assert L.blink_image_batch_desc(*args()) == blink.BLINK_ERR_ARG
+    assert L.blink_set_desc_plan(None, 512, 0) == blink.BLINK_ERR_ARG
+    assert L.blink_graph_launch(None, None) == blink.BLINK_ERR_ARG
+    assert L.blink_graph_destroy(None) == blink.BLINK_OK

@@ -1,0 +1,213 @@
+"""GPU parity of the uneven-batch path (blink_image_batch_desc: descriptor pass, per-image binning,
+persistent fused gridding + FFT with a work queue) and of its hipGraph capture, against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_15204_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+IMAGE_TOL = 1e-5
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2505_15204_amd as blink
+    c = blink.Context(0)
+    yield c
+    c.close()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+class Batch:
+    """A small uneven batch on the device plus its oracle images."""
+
+    def __init__(self, torch, n_img=24, sizes=(64, 128, 256), n_tiles=24, weighting=0, with_oracle=True):
+        import paper_2505_15204_amd as blink
+        self.lay = synth.uneven_layout(n_img, config=15, n_tiles=n_tiles, sizes=sizes, f_lo=70e6, f_hi=300e6)
+        lay = self.lay
+        self.desc_np = synth.uneven_descriptors(lay, blink.DESC_DTYPE)
+        self.vis_np = synth.uneven_vis_host(lay)
+        d = "cuda:0"
+        self.desc = torch.from_numpy(self.desc_np.view(np.uint8).copy()).to(d)
+        self.vis = torch.from_numpy(self.vis_np).to(d)
+        self.uvw = torch.from_numpy(lay["uvw_ext"]).to(d)
+        self.weighting = weighting
+        self.ref = []
+        if with_oracle:
+            for i in range(n_img):
+                o, n = int(lay["vis_offset"][i]), int(lay["n_baselines"][i])
+                uo = int(lay["uvw_offset"][i])
+                g = oracle.grid(self.vis_np[o:o + n], None, lay["uvw_ext"][uo:uo + n], lay["freq_hz"][i],
+                                int(lay["grid_n"][i]), lay["pixel_scale"][i], weighting)
+                img, _ = oracle.ifft2d(g["grid"][0], g["weight_sum"], shift=True)
+                self.ref.append((img, g["weight_sum"], g["n_out"]))
+
+    def run(self, torch, ctx, fill=np.nan, **kw):
+        lay = self.lay
+        d = "cuda:0"
+        images = torch.full((lay["images_len"],), fill, dtype=torch.float32, device=d)
+        wsum = torch.zeros(lay["n_img"], dtype=torch.float64, device=d)
+        nout = torch.zeros(lay["n_img"], dtype=torch.int32, device=d)
+        status = torch.full((1,), -1, dtype=torch.int32, device=d)
+        ctx.blink_image_batch_desc(self.desc, self.vis, self.uvw, None, images, lay["max_b"], lay["max_n"],
+                                   weighting=self.weighting, weight_sum=wsum, n_out=nout, status=status, **kw)
+        torch.cuda.synchronize()
+        return images, wsum, nout, status
+
+    def image(self, images_np, i):
+        o, n = int(self.lay["image_offset"][i]), int(self.lay["grid_n"][i])
+        return images_np[o:o + n * n].reshape(n, n)
+
+    def check(self, images, wsum, nout, status, skip=()):
+        assert int(status[0]) == 0
+        im = images.cpu().numpy()
+        for i, (ref, W, n_out) in enumerate(self.ref):
+            if i in skip:
+                continue
+            assert float(wsum[i]) == W and int(nout[i]) == n_out, i
+            e = rel_l2(self.image(im, i), ref)
+            assert e <= IMAGE_TOL, (i, int(self.lay["grid_n"][i]), e)
+
+
+@pytest.fixture(scope="module")
+def batch(torch):
+    return Batch(torch)
+
+
+def test_uneven_batch_matches_oracle(torch, ctx, batch):
+    say(f"blink_image_batch_desc {batch.lay['n_img']} images, sizes {sorted(set(batch.lay['grid_n']))}")
+    batch.check(*batch.run(torch, ctx))
+
+
+@pytest.mark.parametrize("block,wg", [(512, 0), (512, 1), (512, 5), (1024, 0), (1024, 3)])
+def test_every_desc_plan_matches_oracle(torch, ctx, batch, block, wg):
+    say(f"desc plan block={block} workgroups={wg}")
+    saved = ctx.get_desc_plan()
+    try:
+        ctx.set_desc_plan(block, wg)
+        batch.check(*batch.run(torch, ctx))
+    finally:
+        ctx.set_desc_plan(**saved)
+
+
+def test_uneven_uniform_weighting(torch, ctx):
+    b = Batch(torch, n_img=10, weighting=1)
+    say("blink_image_batch_desc uniform weighting")
+    b.check(*b.run(torch, ctx))
+
+
+def test_invalid_descriptors_are_skipped(torch, ctx):
+    import paper_2505_15204_amd as blink
+    b = Batch(torch, n_img=6)
+    bad = b.desc_np.copy()
+    bad["grid_n"][1] = 100                     # not a power of two
+    bad["image_offset"][3] = b.lay["images_len"]   # image would end past the array
+    bad["n_baselines"][4] = b.lay["max_b"] + 1     # above the stated maximum
+    good = b.desc
+    b.desc = torch.from_numpy(bad.view(np.uint8).copy()).to("cuda:0")
+    say("blink_image_batch_desc with three invalid descriptors")
+    try:
+        images, wsum, nout, status = b.run(torch, ctx, fill=-7.0)
+    finally:
+        b.desc = good
+    assert int(status[0]) == blink.DESC_BAD
+    im = images.cpu().numpy()
+    for i in (0, 2, 5):
+        assert rel_l2(b.image(im, i), b.ref[i][0]) <= IMAGE_TOL
+    for i in (1, 4):                           # skipped images keep the caller's contents
+        o, n = int(b.lay["image_offset"][i]), int(b.lay["grid_n"][i])
+        assert np.all(im[o:o + n * n] == -7.0)
+
+
+def test_graph_replays_match_eager(torch, ctx, batch):
+    """Capture once; replay several times with eager work and input changes in between."""
+    lay = batch.lay
+    d = "cuda:0"
+    images = torch.zeros(lay["images_len"], dtype=torch.float32, device=d)
+    wsum = torch.zeros(lay["n_img"], dtype=torch.float64, device=d)
+    status = torch.zeros(1, dtype=torch.int32, device=d)
+    vis = batch.vis.clone()
+    say("graph capture of the uneven batch")
+    g = ctx.graph_desc(batch.desc, vis, batch.uvw, None, images, lay["max_b"], lay["max_n"], weight_sum=wsum,
+                       status=status)
+    try:
+        for rep, scale in enumerate((1.0, 2.0, -0.5, 1.0)):
+            say(f"graph replay {rep} (visibilities x {scale})")
+            vis.copy_(batch.vis * scale)
+            junk = torch.randn(1 << 20, device=d).sum()      # eager work between replays
+            g.launch()
+            torch.cuda.synchronize()
+            eager = torch.empty_like(images)
+            ctx.blink_image_batch_desc(batch.desc, vis, batch.uvw, None, eager, lay["max_b"], lay["max_n"])
+            torch.cuda.synchronize()
+            assert int(status[0]) == 0 and float(junk) == float(junk)
+            a, e = images.cpu().numpy(), eager.cpu().numpy()
+            for i in range(lay["n_img"]):
+                ref = batch.image(e, i)
+                assert rel_l2(batch.image(a, i), ref) <= 1e-6, (rep, i)
+                assert rel_l2(batch.image(a, i), scale * batch.ref[i][0]) <= IMAGE_TOL, (rep, i)
+    finally:
+        g.close()
+
+
+def test_autotune_desc(torch, ctx, batch):
+    lay = batch.lay
+    images = torch.zeros(lay["images_len"], dtype=torch.float32, device="cuda:0")
+    saved = ctx.get_desc_plan()
+    say("autotune of the descriptor plan")
+    try:
+        plan, ms = ctx.autotune_desc(batch.desc, batch.vis, batch.uvw, None, images, lay["max_b"], lay["max_n"])
+        assert plan["block_threads"] in (512, 1024) and plan["workgroups"] >= 0 and ms > 0
+        torch.cuda.synchronize()
+        im = images.cpu().numpy()
+        for i in range(lay["n_img"]):
+            assert rel_l2(batch.image(im, i), batch.ref[i][0]) <= IMAGE_TOL
+    finally:
+        ctx.set_desc_plan(**saved)
+
+
+def test_uneven_full_size_sampled(torch, ctx):
+    """4096 images of 512^2, 1024^2 and 2048^2 over 70-300 MHz with 70-100% of 8128 baselines each,
+    one persistent launch; sampled images of every size checked against the oracle."""
+    import paper_2505_15204_amd as blink
+    lay = synth.uneven_layout()
+    say(f"uneven full size: {lay['n_img']} images, {lay['images_len'] * 4 / 1e9:.1f} GB of images")
+    d = "cuda:0"
+    desc = torch.from_numpy(synth.uneven_descriptors(lay, blink.DESC_DTYPE).view(np.uint8).copy()).to(d)
+    vis = synth.uneven_vis_device(lay, d)
+    uvw = torch.from_numpy(lay["uvw_ext"]).to(d)
+    images = torch.empty(lay["images_len"], dtype=torch.float32, device=d)
+    wsum = torch.empty(lay["n_img"], dtype=torch.float64, device=d)
+    status = torch.full((1,), -1, dtype=torch.int32, device=d)
+    ctx.blink_image_batch_desc(desc, vis, uvw, None, images, lay["max_b"], lay["max_n"], weight_sum=wsum,
+                               status=status)
+    torch.cuda.synchronize()
+    assert int(status[0]) == 0
+    for i in (0, 889, 890, 2314, 2315, 4095):
+        o, n, N = int(lay["vis_offset"][i]), int(lay["n_baselines"][i]), int(lay["grid_n"][i])
+        uo = int(lay["uvw_offset"][i])
+        v = vis[o:o + n].cpu().numpy()
+        g = oracle.grid(v, None, lay["uvw_ext"][uo:uo + n], lay["freq_hz"][i], N, lay["pixel_scale"][i])
+        ref, _ = oracle.ifft2d(g["grid"][0], g["weight_sum"], shift=True)
+        io = int(lay["image_offset"][i])
+        got = images[io:io + N * N].cpu().numpy().reshape(N, N)
+        assert float(wsum[i]) == g["weight_sum"] and g["n_out"] == 0
+        e = rel_l2(got, ref)
+        assert e <= IMAGE_TOL, (i, N, e)
