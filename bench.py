@@ -7,9 +7,12 @@ natural weighting, 50 point sources plus noise, 10% random flags. All inputs are
 the GPU and stay resident in HBM; a step images one time step (768 x 2 = 1536 images) into an
 HBM ring buffer; the default run times all 100 steps (153,600 images).
 
-Prints one JSON line with images/s, the roofline position of the dominant kernel (bytes from
-the algorithmic byte model / its hipEvent-measured launch time), per-kernel figures, and the
-FP64 CPU oracle timed on a bounded sample of the same workload on the host cores.
+Prints one JSON line with images/s (FP32 form), the roofline position of the dominant kernel
+(bytes from the algorithmic byte model / its hipEvent-measured launch time), per-kernel figures,
+the FP64 CPU oracle timed on a bounded sample of the same workload on the host cores, and the
+other forms measured beside it on the same GPU: the split-precision matrix-core FFT forms on
+this workload and on the 4096^2 precision workload (images/s ratio to FP32), and the uneven
+batch (4096 images of 512^2 .. 2048^2 in one persistent launch, eager and as a hipGraph).
 """
 import argparse
 import json
@@ -101,6 +104,119 @@ def cpu_baseline(d, spec, budget_s):
                       f"{spec.grid_n}^2 in {dt:.1f} s (FP64 C oracle, OpenMP over (t,c))"}
 
 
+FORMS = (("fp32", 0), ("split_f16", 1), ("split_bf16", 2))
+
+
+def timed(torch, fn, steps, warmup):
+    """GPU milliseconds of `steps` calls of fn(i) after `warmup` untimed ones (events on the current stream)."""
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        fn(i)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def kernel_table(prof, units, ub):
+    """Per-kernel launches, average duration and (with a byte model) achieved GB/s."""
+    kernels = {}
+    for name, (ms, launches) in prof.items():
+        if launches == 0:
+            continue
+        avg_s = ms / launches / 1e3
+        entry = {"launches": launches, "avg_ms": round(ms / launches, 5), "total_ms": round(ms, 3)}
+        if name in ub:
+            unit, per_unit = ub[name]
+            per_launch = per_unit * units[unit] / launches
+            gbs = per_launch / avg_s / 1e9
+            entry.update({"unit": unit, "bytes_per_unit": per_unit, "bytes_per_launch": round(per_launch),
+                          "achieved_GB_s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
+        kernels[name] = entry
+    return kernels
+
+
+def profiled(ctx, torch, fn, steps):
+    """The same calls again with hipEvents around every library launch; returns (per-kernel, ms)."""
+    ctx.profile_enable(True)
+    ms = timed(torch, fn, steps, 0)
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    return prof, ms
+
+
+def bench_precision_workload(ctx, torch, blink, synth, steps, warmup):
+    """The 4096^2 precision workload (10 time steps x 256 channels x 1 pol) in every FFT form;
+    a step images one time step (256 images) into a one-step ring buffer."""
+    spec = synth.spec_precision()
+    T, C, P, B, N = spec.T, spec.C, spec.P, spec.B, spec.grid_n
+    log(f"precision workload {spec.name}: T={T} C={C} P={P} N={N}")
+    d = synth.make_problem_device(spec, "cuda:0")
+    images = torch.empty((1, C, P, N, N), dtype=torch.float32, device="cuda:0")
+    ws = torch.empty(max(blink.image_batch_workspace_size(1, C, P, B, N, 0, p) for _, p in FORMS),
+                     dtype=torch.uint8, device="cuda:0")
+    out = {"workload": "precision-4096: 8128 baselines, 256 channels (every third VCS channel), 1 pol, "
+                       "10 time steps, 4096^2 grid, 1 arcmin, natural weighting", "images_per_step": C * P}
+    for name, prec in FORMS:
+        def step(i, prec=prec):
+            t = i % T
+            ctx.blink_image_batch(d["vis"][t:t + 1], d["flags"][t:t + 1], d["uvw_m"][t:t + 1], d["freq_hz"], N,
+                                  spec.pixel_scale, 0, precision=prec, out=images, workspace=ws)
+        ms = timed(torch, step, steps, warmup)
+        out[name] = {"images_per_s": round(steps * C * P / (ms / 1e3), 1), "ms_per_step": round(ms / steps, 3)}
+    for name, _ in FORMS[1:]:
+        out[name]["vs_fp32"] = round(out[name]["images_per_s"] / out["fp32"]["images_per_s"], 4)
+    del d, images, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_uneven(ctx, torch, blink, synth, reps):
+    """One persistent launch over 4096 images of 512^2, 1024^2 and 2048^2 (70-300 MHz, 70-100% of
+    8128 baselines each), FP32 and split forms, eager and replayed from a hipGraph."""
+    import numpy as np
+
+    lay = synth.uneven_layout()
+    dev = "cuda:0"
+    log(f"uneven batch: {lay['n_img']} images, {lay['images_len'] * 4 / 1e9:.1f} GB of images")
+    desc = torch.from_numpy(synth.uneven_descriptors(lay, blink.DESC_DTYPE).view(np.uint8).copy()).to(dev)
+    vis = synth.uneven_vis_device(lay, dev)
+    uvw = torch.from_numpy(lay["uvw_ext"]).to(dev)
+    images = torch.empty(lay["images_len"], dtype=torch.float32, device=dev)
+    n_img = lay["n_img"]
+    ws = torch.empty(blink.desc_workspace_size(n_img, lay["max_b"], lay["max_n"], 512), dtype=torch.uint8,
+                     device=dev)
+    model = int(sum(12 * int(n) ** 2 + 9 * int(b) for n, b in zip(lay["grid_n"], lay["n_baselines"])))
+    sizes = {int(n): int((lay["grid_n"] == n).sum()) for n in sorted(set(lay["grid_n"].tolist()))}
+    out = {"workload": "uneven: 4096 images, f = 70-300 MHz, N = 512 / 1024 / 2048 below 120 / 200 MHz / above, "
+                       "pixel scale per channel so every baseline fits, 70-100% of 8128 baselines per image",
+           "images": n_img, "images_per_size": sizes, "bytes_model_total": model,
+           "desc_plan": ctx.get_desc_plan()}
+    for name, prec in FORMS:
+        def run(i, prec=prec):
+            ctx.blink_image_batch_desc(desc, vis, uvw, None, images, lay["max_b"], lay["max_n"], precision=prec,
+                                       workspace=ws)
+        ms = timed(torch, run, reps, 1) / reps
+        g = ctx.graph_desc(desc, vis, uvw, None, images, lay["max_b"], lay["max_n"], precision=prec, workspace=ws)
+        try:
+            gms = timed(torch, lambda i: g.launch(), reps, 1) / reps
+        finally:
+            g.close()
+        gbs = model / (ms / 1e3) / 1e9
+        out[name] = {"images_per_s": round(n_img / (ms / 1e3), 1), "ms_per_batch": round(ms, 3),
+                     "graph_images_per_s": round(n_img / (gms / 1e3), 1), "graph_ms_per_batch": round(gms, 3),
+                     "model_GB_s": round(gbs, 1), "frac_hbm_model": round(gbs / HBM_PEAK_GBS, 4)}
+    for name, _ in FORMS[1:]:
+        out[name]["vs_fp32"] = round(out[name]["images_per_s"] / out["fp32"]["images_per_s"], 4)
+    del desc, vis, uvw, images, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +228,9 @@ def main():
                     help="tune the execution plan on time step 0 instead of loading the committed plan file")
     ap.add_argument("--save-plans", default="", help="write the context's plans (JSON) to this path")
     ap.add_argument("--plan", default="", help="force a plan col_strip,row_block,group")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the split-precision and uneven-batch measurements beside the headline")
+    ap.add_argument("--form-steps", type=int, default=20, help="steps per split-precision form measurement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy (read + write of this many MiB) --steps times; used "
                          "to scale the HBM byte counters")
@@ -174,22 +293,10 @@ def main():
     if args.save_plans:
         ctx.save_plans(args.save_plans)
     plan = ctx.get_plan(N, 0)
-    log(f"warmup {args.warmup} steps")
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} steps, timing {args.steps} steps")
     w0 = time.perf_counter()
-    ev0.record()
-    for i in range(args.steps):
-        step(i)
-    ev1.record()
-    torch.cuda.synchronize()
+    gpu_ms = timed(torch, step, args.steps, args.warmup)
     wall = time.perf_counter() - w0
-    gpu_ms = ev0.elapsed_time(ev1)
     n_images = args.steps * C * P
     value = n_images / (gpu_ms / 1e3)
     log(f"{n_images} images in {gpu_ms:.1f} ms (wall {wall * 1e3:.1f} ms): {value:.0f} images/s")
@@ -197,33 +304,10 @@ def main():
     # Per-kernel durations: the same steps again with hipEvents around every launch (the events
     # cost a little time per launch, so they are kept out of the headline pass).
     log(f"kernel timing pass: {args.steps} steps with per-launch events")
-    ctx.profile_enable(True)
-    pe0 = torch.cuda.Event(enable_timing=True)
-    pe1 = torch.cuda.Event(enable_timing=True)
-    pe0.record()
-    for i in range(args.steps):
-        step(i)
-    pe1.record()
-    torch.cuda.synchronize()
-    prof = ctx.profile_read()
-    ctx.profile_enable(False)
-    prof_ms = pe0.elapsed_time(pe1)
-
+    prof, prof_ms = profiled(ctx, torch, step, args.steps)
     units = {"image": n_images, "pair": args.steps * C}
     ub = kernel_unit_bytes(spec)
-    kernels = {}
-    for name, (ms, launches) in prof.items():
-        if launches == 0:
-            continue
-        avg_s = ms / launches / 1e3
-        entry = {"launches": launches, "avg_ms": round(ms / launches, 5), "total_ms": round(ms, 3)}
-        if name in ub:
-            unit, per_unit = ub[name]
-            per_launch = per_unit * units[unit] / launches
-            gbs = per_launch / avg_s / 1e9
-            entry.update({"unit": unit, "bytes_per_unit": per_unit, "bytes_per_launch": round(per_launch),
-                          "achieved_GB_s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
-        kernels[name] = entry
+    kernels = kernel_table(prof, units, ub)
     dom = max((k for k in kernels if k in ub), key=lambda k: kernels[k]["total_ms"])
     roof = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["achieved_GB_s"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": kernels[dom]["frac_hbm"],
@@ -233,6 +317,28 @@ def main():
             "achieved_GB_s": round(value * per_image / 1e9, 1),
             "frac_hbm": round(value * per_image / 1e9 / HBM_PEAK_GBS, 4),
             "kernel_timing_pass_ms": round(prof_ms, 3)}
+
+    forms = None
+    if not args.no_forms:
+        # The split-precision matrix-core forms on the same workload and buffers (MFMA vs FP32).
+        forms = {"vcs-1024": {"fp32": {"images_per_s": round(value, 1)}}}
+        fs = min(args.form_steps, T)
+        for name, prec in FORMS[1:]:
+            def fstep(i, prec=prec):
+                t = i % T
+                ctx.blink_image_batch(d["vis"][t:t + 1], d["flags"][t:t + 1], d["uvw_m"][t:t + 1], d["freq_hz"], N,
+                                      spec.pixel_scale, 0, precision=prec, out=images, weight_sum=wsum, n_out=nout,
+                                      workspace=ws)
+            ms = timed(torch, fstep, fs, 2)
+            fprof, _ = profiled(ctx, torch, fstep, fs)
+            fk = kernel_table(fprof, {"image": fs * C * P, "pair": fs * C}, ub)
+            v = fs * C * P / (ms / 1e3)
+            forms["vcs-1024"][name] = {"images_per_s": round(v, 1), "vs_fp32": round(v / value, 4),
+                                       "plan": ctx.get_plan(N, 0, prec),
+                                       "kernels": {k: fk[k] for k in ("grid_colfft", "row_fft") if k in fk}}
+            log(f"{name}: {v:.0f} images/s ({v / value:.3f} x FP32)")
+        forms["precision-4096"] = bench_precision_workload(ctx, torch, blink, synth, 3, 1)
+        forms["uneven"] = bench_uneven(ctx, torch, blink, synth, 3)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -269,6 +375,7 @@ def main():
         "kernels": kernels,
         "wall_s": round(wall, 4),
         "cpu_baseline": cpu,
+        "forms": forms,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

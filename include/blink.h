@@ -72,7 +72,16 @@ typedef enum {
 } blink_status;
 
 enum { BLINK_WEIGHT_NATURAL = 0, BLINK_WEIGHT_UNIFORM = 1 };
-enum { BLINK_PREC_FP32 = 0 };
+/* FFT precision forms (the `precision` argument). The paper computes in 32-bit floating point
+ * (Section 6.1) and names reduced precision as future work (Section 10):
+ *   BLINK_PREC_FP32        radix-16 butterflies in FP32 on the vector ALUs;
+ *   BLINK_PREC_SPLIT_F16   radix-16 stages as matrix-core (MFMA) products of FP16 operands split
+ *                          into hi + lo (3 products, FP32 accumulation; a power-of-two scale per
+ *                          strip or row block keeps FP16 in range);
+ *   BLINK_PREC_SPLIT_BF16  the same with BF16 operands (no scaling needed).
+ * Gridding, weights, twiddle multiplications and any radix-2/4/8 stage stay in FP32 in every
+ * form; for N = 8 (no radix-16 stage) the split forms equal FP32. */
+enum { BLINK_PREC_FP32 = 0, BLINK_PREC_SPLIT_F16 = 1, BLINK_PREC_SPLIT_BF16 = 2 };
 
 #define BLINK_MIN_GRID 8
 #define BLINK_MAX_GRID 4096
@@ -171,7 +180,7 @@ blink_status blink_desc_workspace_size(int n_img, int max_baselines, int max_gri
 /* Images described by desc[0..n_img) (device array). vis_len, uvw_len (baselines), flags_len and
  * images_len give the element counts of the caller's arrays; every descriptor is checked against
  * them on the device and an invalid one only sets BLINK_DESC_BAD (its image is left untouched).
- * weighting and shift apply to the whole batch. Outputs: images at each image_offset; weight_sum
+ * weighting, precision (any BLINK_PREC_* form) and shift apply to the whole batch. Outputs: images at each image_offset; weight_sum
  * double [n_img] and n_out int32 [n_img] (either may be NULL); status int32 [1] (may be NULL)
  * receives the BLINK_DESC_* bits. Uses the context's descriptor plan (blink_set_desc_plan); the
  * number of workgroups is reduced to the slots the workspace holds. Capturable into a hipGraph
@@ -215,30 +224,34 @@ blink_status blink_graph_launch(blink_graph graph, void *hip_stream);
 blink_status blink_graph_destroy(blink_graph graph);
 
 /* ---------------------------------------------------------------- execution plans and autotuning
- * Not part of the method: how blink_image_batch schedules its kernels for one grid size and
- * weighting. A plan never changes results beyond FP32 rounding order. Fields:
+ * Not part of the method: how blink_image_batch schedules its kernels for one grid size,
+ * weighting and precision form (each has its own plan; blink_ifft2d uses the row_block of the
+ * natural-weighting plan of its precision). A plan never changes results beyond rounding order.
+ * Fields:
  *   col_strip  columns of the half spectrum per workgroup of the fused gridding + column FFT kernel
  *   row_block  row-pair transforms per workgroup of the row FFT kernel
  *   group      images per column/row launch pair (0 = as many as the workspace holds, at most 256
  *              with the queried workspace); small groups keep the intermediates in the last-level
  *              cache between the two passes. */
 
-/* Compiled options for grid_n and weighting: up to 4 strip widths and 4 row blocks each. */
+/* Compiled options for grid_n and weighting (the same for every precision form): up to 4 strip
+ * widths and 4 row blocks each. */
 blink_status blink_plan_options(int grid_n, int weighting, int *col_strips, int *n_col,
                                 int *row_blocks, int *n_row);
 
 /* Current plan of a context (a default until set or tuned). */
-blink_status blink_get_plan(blink_ctx ctx, int grid_n, int weighting, int *col_strip,
-                            int *row_block, int *group);
+blink_status blink_get_plan(blink_ctx ctx, int grid_n, int weighting, int precision,
+                            int *col_strip, int *row_block, int *group);
 
 /* Set a plan; col_strip and row_block must be compiled options, group >= 0. */
-blink_status blink_set_plan(blink_ctx ctx, int grid_n, int weighting, int col_strip,
-                            int row_block, int group);
+blink_status blink_set_plan(blink_ctx ctx, int grid_n, int weighting, int precision,
+                            int col_strip, int row_block, int group);
 
 /* Autotuner: runs blink_image_batch on the caller's problem (same arguments) for every compiled
  * (col_strip, row_block) pair and group sizes 16 .. 256, times each with hipEvents on hip_stream,
- * and keeps the fastest in the context. Synchronises with the host. On return `images` etc. hold
- * a valid result, and col_strip, row_block, group, best_ms (any may be NULL) describe the choice. */
+ * and keeps the fastest as the context's plan for (grid_n, weighting, precision). Synchronises
+ * with the host. On return `images` etc. hold a valid result, and col_strip, row_block, group and
+ * best_ms (any may be NULL) describe the choice. */
 blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32 *vis, const uint8_t *flags,
                                         const double *uvw_m, const double *freq_hz, int T, int C,
                                         int P, int B, int grid_n, double pixel_scale, int weighting,

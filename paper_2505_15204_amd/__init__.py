@@ -31,7 +31,10 @@ DESC_DTYPE = _np.dtype([("vis_offset", "<i8"), ("uvw_offset", "<i8"), ("flag_off
                         ("image_offset", "<i8"), ("freq_hz", "<f8"), ("pixel_scale", "<f8"),
                         ("n_baselines", "<i4"), ("grid_n", "<i4"), ("reserved", "<i4", (2,))])
 assert DESC_DTYPE.itemsize == 64
-PREC_FP32 = 0
+PREC_FP32 = 0            # BLINK_PREC_FP32: FP32 radix-16 butterflies
+PREC_SPLIT_F16 = 1       # BLINK_PREC_SPLIT_F16: matrix-core radix-16 stages, FP16 hi + lo operands
+PREC_SPLIT_BF16 = 2      # BLINK_PREC_SPLIT_BF16: the same with BF16 operands
+PRECISIONS = (PREC_FP32, PREC_SPLIT_F16, PREC_SPLIT_BF16)
 
 _lib = None
 
@@ -83,9 +86,9 @@ def lib() -> ctypes.CDLL:
     L.blink_plan_options.restype = i32
     L.blink_plan_options.argtypes = [i32, i32, P, P, P, P]
     L.blink_get_plan.restype = i32
-    L.blink_get_plan.argtypes = [P, i32, i32, P, P, P]
+    L.blink_get_plan.argtypes = [P, i32, i32, i32, P, P, P]
     L.blink_set_plan.restype = i32
-    L.blink_set_plan.argtypes = [P, i32, i32, i32, i32, i32]
+    L.blink_set_plan.argtypes = [P, i32, i32, i32, i32, i32, i32]
     L.blink_autotune_image_batch.restype = i32
     L.blink_autotune_image_batch.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32, P, P,
                                              P, P, sz, P, P, P, P, P]
@@ -211,34 +214,41 @@ class Context:
             out[name] = (ms.value, n.value)
         return out
 
-    # -- execution plans (scheduling only; results are the same up to FP32 rounding order)
-    def get_plan(self, grid_n: int, weighting: int = 0) -> dict:
+    # -- execution plans (scheduling only; results are the same up to rounding order)
+    def get_plan(self, grid_n: int, weighting: int = 0, precision: int = PREC_FP32) -> dict:
         c, r, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(lib().blink_get_plan(self.handle, grid_n, weighting, ctypes.byref(c), ctypes.byref(r), ctypes.byref(g)),
-               self.handle, "blink_get_plan")
+        _check(lib().blink_get_plan(self.handle, grid_n, weighting, precision, ctypes.byref(c), ctypes.byref(r),
+                                    ctypes.byref(g)), self.handle, "blink_get_plan")
         return {"col_strip": c.value, "row_block": r.value, "group": g.value}
 
-    def set_plan(self, grid_n: int, weighting: int = 0, col_strip: int = 0, row_block: int = 0, group: int = 0):
-        _check(lib().blink_set_plan(self.handle, grid_n, weighting, col_strip, row_block, group), self.handle,
-               "blink_set_plan")
+    def set_plan(self, grid_n: int, weighting: int = 0, col_strip: int = 0, row_block: int = 0, group: int = 0,
+                 precision: int = PREC_FP32):
+        _check(lib().blink_set_plan(self.handle, grid_n, weighting, precision, col_strip, row_block, group),
+               self.handle, "blink_set_plan")
 
-    def save_plans(self, path: str, sizes=(256, 512, 1024, 2048, 4096)):
-        """Write the context's plans as JSON keyed by device name, grid size and weighting."""
+    def save_plans(self, path: str, sizes=(256, 512, 1024, 2048, 4096), precisions=PRECISIONS):
+        """Write the context's plans as JSON keyed by device name, grid size, weighting and precision."""
         import json
         torch = self._torch()
         name = torch.cuda.get_device_properties(self.device).gcnArchName
-        rec = {f"{name}/{n}/{w}": self.get_plan(n, w) for n in sizes for w in (0, 1)}
+        rec = {f"{name}/{n}/{w}/{p}": self.get_plan(n, w, p) for n in sizes for w in (0, 1) for p in precisions}
         with open(path, "w") as fh:
             json.dump(rec, fh, indent=1, sort_keys=True)
 
     def load_plans(self, path: str):
+        """Apply the plans of this device from a file written by save_plans (keys without a
+        precision field are FP32 plans)."""
         import json
         torch = self._torch()
         name = torch.cuda.get_device_properties(self.device).gcnArchName
         for key, p in json.load(open(path)).items():
-            dev, n, w = key.rsplit("/", 2)
+            parts = key.split("/")
+            if parts[-1].isdigit() and parts[-2].isdigit() and parts[-3].isdigit():
+                dev, n, w, prec = "/".join(parts[:-3]), parts[-3], parts[-2], parts[-1]
+            else:
+                dev, n, w, prec = "/".join(parts[:-2]), parts[-2], parts[-1], str(PREC_FP32)
             if dev == name:
-                self.set_plan(int(n), int(w), p["col_strip"], p["row_block"], p["group"])
+                self.set_plan(int(n), int(w), p["col_strip"], p["row_block"], p["group"], precision=int(prec))
 
     def autotune_image_batch(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float, weighting: int = 0,
                              precision: int = PREC_FP32, shift: bool = True, out=None, workspace=None, stream=None):

@@ -4,13 +4,18 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libblink.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "persistent.hip", "api.hip")]
+# (source, extra defines): split.hip is built once per split precision (1 = FP16, 2 = BF16).
+UNITS = [("kernels.hip", []), ("persistent.hip", []), ("api.hip", []),
+         ("split.hip", ["-DBLINK_SPLIT_PREC=1"]), ("split.hip", ["-DBLINK_SPLIT_PREC=2"])]
+SOURCES = sorted({os.path.join(CSRC, f) for f, _ in UNITS})
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -26,17 +31,37 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source for gfx950 into paper_2505_15204_amd/libblink.so."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-shared", "-I", INCLUDE, "-I", CSRC, *SOURCES, "-o", tmp]
+def _run(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     msgs = [ln for ln in (res.stdout + res.stderr).splitlines() if noise not in ln]
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
-    if verbose and msgs:
-        print("\n".join(msgs), file=sys.stderr)
+    return res.returncode, msgs
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every unit for gfx950 (in parallel) and link paper_2505_15204_amd/libblink.so."""
+    jobs = jobs or min(len(UNITS), max(1, os.cpu_count() or 1))
+    with tempfile.TemporaryDirectory(prefix="blink_build_") as tmpdir:
+        objs, cmds = [], []
+        for k, (src, defs) in enumerate(UNITS):
+            obj = os.path.join(tmpdir, f"{k}_{os.path.splitext(src)[0]}.o")
+            objs.append(obj)
+            cmds.append([hipcc(), *HIPCC_FLAGS, *defs, "-I", INCLUDE, "-I", CSRC, "-c",
+                         os.path.join(CSRC, src), "-o", obj])
+        with ThreadPoolExecutor(jobs) as ex:
+            results = list(ex.map(_run, cmds))
+        all_msgs = []
+        for (rc, msgs), cmd in zip(results, cmds):
+            if rc != 0:
+                raise RuntimeError(f"hipcc failed: {' '.join(cmd)}\n" + "\n".join(msgs))
+            all_msgs += msgs
+        tmp = LIB + ".tmp"
+        rc, msgs = _run([hipcc(), "--offload-arch=gfx950", "-fPIC", "-shared", *objs, "-o", tmp])
+        if rc != 0:
+            raise RuntimeError("link failed:\n" + "\n".join(msgs))
+        all_msgs += msgs
+    if verbose and all_msgs:
+        print("\n".join(all_msgs), file=sys.stderr)
     os.replace(tmp, LIB)
     return LIB
 

@@ -14,17 +14,19 @@
 #include "blink.h"
 #include "launch.hpp"
 
+constexpr int kPrecForms = 3;   // BLINK_PREC_FP32, BLINK_PREC_SPLIT_F16, BLINK_PREC_SPLIT_BF16
+
 struct blink_ctx_s {
   int device = 0;
   float2* tw_base = nullptr;      // twiddle tables for N = 8 .. 4096, concatenated
   float2* tw[13] = {};
   bool broken = false;
   std::string err;
-  // execution plan per (log2 N, weighting): fused-kernel strip width, row transforms per
-  // workgroup, images per column/row launch pair (0 = as many as the workspace holds)
+  // execution plan per (log2 N, weighting, precision form): fused-kernel strip width, row
+  // transforms per workgroup, images per column/row launch pair (0 = as many as the workspace holds)
   struct Plan {
     int col_strip = 0, row_tpb = 0, group = 0;
-  } plan[13][2];
+  } plan[13][2][kPrecForms];
   // descriptor-path plan (blink_set_desc_plan) and device facts
   int desc_block = 512, desc_workgroups = 0;
   int cu_count = 0;
@@ -38,6 +40,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool valid_precision(int p) { return p >= 0 && p < kPrecForms; }
 
 int log2_exact(int n) {
   if (n < BLINK_MIN_GRID || n > BLINK_MAX_GRID || (n & (n - 1))) return -1;
@@ -309,13 +313,15 @@ blink_status blink_create(blink_ctx* out, int hip_device) {
       blink::col_strip_options(l, u != 0, col);
       int nr = blink::row_block_options(l, row);
       // default: the widest strip, and the row block closest to 256 threads
-      ctx->plan[l][u].col_strip = col[0];
       int t = (1 << l) / 16 > 0 ? (1 << l) / 16 : 1;
       int best = row[0];
       for (int i = 0; i < nr; ++i)
         if (row[i] * t <= 256) { best = row[i]; break; }
-      ctx->plan[l][u].row_tpb = best;
-      ctx->plan[l][u].group = 0;
+      for (int pf = 0; pf < kPrecForms; ++pf) {
+        ctx->plan[l][u][pf].col_strip = col[0];
+        ctx->plan[l][u][pf].row_tpb = best;
+        ctx->plan[l][u][pf].group = 0;
+      }
     }
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -353,7 +359,7 @@ blink_status blink_grid_workspace_size(int T, int C, int B, int grid_n, size_t* 
 
 blink_status blink_ifft2d_workspace_size(int n_img, int grid_n, int precision, size_t* bytes) {
   if (!bytes || n_img < 0) return BLINK_ERR_ARG;
-  if (precision != BLINK_PREC_FP32) return BLINK_ERR_ARG;
+  if (!valid_precision(precision)) return BLINK_ERR_ARG;
   const int logn = log2_exact(grid_n);
   if (logn < 0) return BLINK_ERR_SIZE;
   FftLayout L = fft_layout((size_t)n_img, logn);
@@ -366,7 +372,7 @@ blink_status blink_image_batch_workspace_size(int T, int C, int P, int B, int gr
                                               int precision, size_t* bytes) {
   if (!bytes || T < 0 || C < 0 || P < 1 || B < 0) return BLINK_ERR_ARG;
   if (weighting != BLINK_WEIGHT_NATURAL && weighting != BLINK_WEIGHT_UNIFORM) return BLINK_ERR_ARG;
-  if (precision != BLINK_PREC_FP32) return BLINK_ERR_ARG;
+  if (!valid_precision(precision)) return BLINK_ERR_ARG;
   const int logn = log2_exact(grid_n);
   if (logn < 0) return BLINK_ERR_SIZE;
   const size_t n_img = (size_t)T * C * P;
@@ -465,7 +471,7 @@ blink_status blink_ifft2d(blink_ctx ctx, const blink_cf32* grids, const double* 
   if (n_img < 0) return fail(ctx, BLINK_ERR_ARG, "n_img < 0");
   const int logn = log2_exact(grid_n);
   if (logn < 0) return fail(ctx, BLINK_ERR_SIZE, "grid_n=%d is not a power of two in [8, 4096]", grid_n);
-  if (precision != BLINK_PREC_FP32) return fail(ctx, BLINK_ERR_ARG, "unsupported precision %d", precision);
+  if (!valid_precision(precision)) return fail(ctx, BLINK_ERR_ARG, "unsupported precision %d", precision);
   if (!ctx) return BLINK_ERR_ARG;
   if (ctx->broken) return fail(ctx, BLINK_ERR_STATE, "context unusable after an earlier HIP error");
   if (n_img == 0) return BLINK_OK;
@@ -488,7 +494,8 @@ blink_status blink_ifft2d(blink_ctx ctx, const blink_cf32* grids, const double* 
     hipError_t e;
     {
       KernelTimer kt(ctx, BLINK_KERNEL_DENSE_COLFFT, s);
-      e = blink::launch_dense_colfft((const float2*)grids + i0 * N * N, q, logn, shift != 0, H, ctx->tw[logn], s);
+      e = blink::launch_dense_colfft((const float2*)grids + i0 * N * N, q, logn, shift != 0, precision, H,
+                                     ctx->tw[logn], s);
     }
     if (e == hipSuccess) {
       blink::RowArgs ra{};
@@ -500,7 +507,7 @@ blink_status blink_ifft2d(blink_ctx ctx, const blink_cf32* grids, const double* 
       ra.wmode = blink::kWeightUser;
       ra.w_user = weight_sum;
       KernelTimer kt(ctx, BLINK_KERNEL_ROW_FFT, s);
-      e = blink::launch_row_c2r(ra, q, ctx->plan[logn][0].row_tpb, ctx->tw[logn], s);
+      e = blink::launch_row_c2r(ra, q, ctx->plan[logn][0][precision].row_tpb, precision, ctx->tw[logn], s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "ifft2d kernels");
   }
@@ -515,10 +522,10 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
   blink_status st = check_problem(ctx, vis, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting,
                                   images, workspace, &logn);
   if (st != BLINK_OK) return st;
-  if (precision != BLINK_PREC_FP32) return fail(ctx, BLINK_ERR_ARG, "unsupported precision %d", precision);
+  if (!valid_precision(precision)) return fail(ctx, BLINK_ERR_ARG, "unsupported precision %d", precision);
   const size_t n_tc = (size_t)T * C;
   if (n_tc == 0) return BLINK_OK;
-  const auto& plan = ctx->plan[logn][weighting];
+  const auto& plan = ctx->plan[logn][weighting][precision];
   const size_t want = plan.group > 0 ? (size_t)plan.group : kMaxGroupImages;
   size_t Q = largest_fitting_chunk(n_tc, workspace_bytes, [&](size_t q) {
     return image_layout(q, P, B, logn, weighting, q * P < want ? q * P : want).total;
@@ -597,14 +604,14 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
       ca.img0 = i0;
       {
         KernelTimer kt(ctx, BLINK_KERNEL_GRID_COLFFT, s);
-        e = blink::launch_grid_colfft(ca, gi, S, ctx->tw[logn], s);
+        e = blink::launch_grid_colfft(ca, gi, S, precision, ctx->tw[logn], s);
       }
       if (e != hipSuccess) return hip_fail(ctx, e, "grid+column FFT kernel");
       ra.img0 = i0;
       ra.images = images + (tc0 * P + i0) * N * N;
       {
         KernelTimer kt(ctx, BLINK_KERNEL_ROW_FFT, s);
-        e = blink::launch_row_c2r(ra, gi, plan.row_tpb, ctx->tw[logn], s);
+        e = blink::launch_row_c2r(ra, gi, plan.row_tpb, precision, ctx->tw[logn], s);
       }
       if (e != hipSuccess) return hip_fail(ctx, e, "row FFT kernel");
     }
@@ -664,7 +671,7 @@ blink_status check_desc(blink_ctx ctx, const DescCall& c, int* max_logn) {
   if (*max_logn < 0) return fail(ctx, BLINK_ERR_SIZE, "max_grid_n=%d is not a power of two in [8, 4096]", c.max_n);
   if (c.weighting != BLINK_WEIGHT_NATURAL && c.weighting != BLINK_WEIGHT_UNIFORM)
     return fail(ctx, BLINK_ERR_ARG, "unknown weighting %d", c.weighting);
-  if (c.precision != BLINK_PREC_FP32) return fail(ctx, BLINK_ERR_ARG, "unsupported precision %d", c.precision);
+  if (!valid_precision(c.precision)) return fail(ctx, BLINK_ERR_ARG, "unsupported precision %d", c.precision);
   if (!ctx) return BLINK_ERR_ARG;
   if (ctx->broken) return fail(ctx, BLINK_ERR_STATE, "context unusable after an earlier HIP error");
   if (c.n_img == 0) return BLINK_OK;
@@ -682,7 +689,7 @@ blink_status run_desc(blink_ctx ctx, const DescCall& c, hipStream_t s) {
   blink_status st = check_desc(ctx, c, &max_logn);
   if (st != BLINK_OK || c.n_img == 0) return st;
   const int block = desc_block_for(ctx, c.weighting);
-  const int per_cu = blink::persistent_blocks_per_cu(block, c.weighting != 0);
+  const int per_cu = blink::persistent_blocks_per_cu(block, c.weighting != 0, c.precision);
   if (per_cu <= 0) return fail(ctx, BLINK_ERR_ARG, "persistent kernel with %d threads is not available", block);
   size_t wg = ctx->desc_workgroups > 0 ? (size_t)ctx->desc_workgroups : (size_t)per_cu * ctx->cu_count;
   if (wg > (size_t)c.n_img) wg = (size_t)c.n_img;
@@ -731,7 +738,7 @@ blink_status run_desc(blink_ctx ctx, const DescCall& c, hipStream_t s) {
   }
   if (e == hipSuccess) {
     KernelTimer kt(ctx, BLINK_KERNEL_PERSISTENT, s);
-    e = blink::launch_persistent(a, (int)wg, s);
+    e = blink::launch_persistent(a, (int)wg, c.precision, s);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "uneven-batch kernels");
   return BLINK_OK;
@@ -811,7 +818,7 @@ blink_status blink_autotune_desc(blink_ctx ctx, const blink_image_desc* desc, in
   blink_status result = BLINK_OK;
   for (int bi = 0; bi < 2 && result == BLINK_OK; ++bi) {
     if (weighting && blocks[bi] != 512) continue;
-    const int resident = blink::persistent_blocks_per_cu(blocks[bi], weighting != 0) * ctx->cu_count;
+    const int resident = blink::persistent_blocks_per_cu(blocks[bi], weighting != 0, precision) * ctx->cu_count;
     const int counts[] = {0, resident / 2, resident / 4};
     for (int wi = 0; wi < 3 && result == BLINK_OK; ++wi) {
       if (wi > 0 && counts[wi] < 1) continue;
@@ -928,21 +935,23 @@ blink_status blink_plan_options(int grid_n, int weighting, int* col_strips, int*
   return BLINK_OK;
 }
 
-blink_status blink_get_plan(blink_ctx ctx, int grid_n, int weighting, int* col_strip, int* row_block, int* group) {
+blink_status blink_get_plan(blink_ctx ctx, int grid_n, int weighting, int precision, int* col_strip, int* row_block,
+                            int* group) {
   const int logn = log2_exact(grid_n);
   if (logn < 0) return fail(ctx, BLINK_ERR_SIZE, "grid_n=%d unsupported", grid_n);
-  if (!ctx || (weighting != 0 && weighting != 1)) return BLINK_ERR_ARG;
-  const auto& p = ctx->plan[logn][weighting];
+  if (!ctx || (weighting != 0 && weighting != 1) || !valid_precision(precision)) return BLINK_ERR_ARG;
+  const auto& p = ctx->plan[logn][weighting][precision];
   if (col_strip) *col_strip = p.col_strip;
   if (row_block) *row_block = p.row_tpb;
   if (group) *group = p.group;
   return BLINK_OK;
 }
 
-blink_status blink_set_plan(blink_ctx ctx, int grid_n, int weighting, int col_strip, int row_block, int group) {
+blink_status blink_set_plan(blink_ctx ctx, int grid_n, int weighting, int precision, int col_strip, int row_block,
+                            int group) {
   const int logn = log2_exact(grid_n);
   if (logn < 0) return fail(ctx, BLINK_ERR_SIZE, "grid_n=%d unsupported", grid_n);
-  if (!ctx || (weighting != 0 && weighting != 1) || group < 0) return BLINK_ERR_ARG;
+  if (!ctx || (weighting != 0 && weighting != 1) || group < 0 || !valid_precision(precision)) return BLINK_ERR_ARG;
   int col[4], row[4];
   const int nc = blink::col_strip_options(logn, weighting != 0, col);
   const int nr = blink::row_block_options(logn, row);
@@ -952,7 +961,7 @@ blink_status blink_set_plan(blink_ctx ctx, int grid_n, int weighting, int col_st
   if (!okc || !okr)
     return fail(ctx, BLINK_ERR_ARG, "plan (col_strip=%d, row_block=%d) is not a compiled option for N=%d", col_strip,
                 row_block, grid_n);
-  auto& p = ctx->plan[logn][weighting];
+  auto& p = ctx->plan[logn][weighting][precision];
   p.col_strip = col_strip;
   p.row_tpb = row_block;
   p.group = group;
@@ -969,7 +978,8 @@ blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32* vis, co
   blink_status st = check_problem(ctx, vis, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting, images,
                                   workspace, &logn);
   if (st != BLINK_OK) return st;
-  const auto saved = ctx->plan[logn][weighting];
+  if (!valid_precision(precision)) return fail(ctx, BLINK_ERR_ARG, "unsupported precision %d", precision);
+  const auto saved = ctx->plan[logn][weighting][precision];
   const bool was_profiling = ctx->profiling;
   ctx->profiling = false;
   DeviceGuard g(ctx->device);
@@ -990,7 +1000,7 @@ blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32* vis, co
   for (int gi = 0; gi < 5 && result == BLINK_OK; ++gi) {
     for (int ci = 0; ci < nc && result == BLINK_OK; ++ci) {
       for (int ri = 0; ri < nr && result == BLINK_OK; ++ri) {
-        auto& p = ctx->plan[logn][weighting];
+        auto& p = ctx->plan[logn][weighting][precision];
         p.col_strip = col[ci];
         p.row_tpb = row[ri];
         p.group = groups[gi];
@@ -1017,7 +1027,7 @@ blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32* vis, co
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   ctx->profiling = was_profiling;
-  ctx->plan[logn][weighting] = result == BLINK_OK ? best_plan : saved;
+  ctx->plan[logn][weighting][precision] = result == BLINK_OK ? best_plan : saved;
   if (result != BLINK_OK) return result;
   // leave a result computed with the chosen plan in the outputs
   result = blink_image_batch(ctx, vis, flags, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting, precision,

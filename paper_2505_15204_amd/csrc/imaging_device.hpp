@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fft_device.hpp"
+#include "split_fft.hpp"
 
 namespace blink {
 
@@ -200,17 +201,23 @@ __device__ __forceinline__ void block_add_to_global(int val, int* s_tmp, int* ds
 // store the strip into Hi[y][strip*S + c]. Column 0 is stored as (Re of its transform, 0): the
 // real part is the transform of the column's Hermitian part, and the Nyquist column is empty.
 // Threads beyond S*T of the workgroup only join the barriers. `tw` is the twiddle table for N.
-template <int LOGN, int S, bool UNIFORM>
+// PREC selects the FP32 butterflies or the split matrix-core form (split_fft.hpp), which needs a
+// workgroup of whole waves; `s_max` is that form's LDS word for the strip's largest magnitude.
+template <int LOGN, int S, bool UNIFORM, int PREC = kPrecFp32>
 __device__ __forceinline__ void grid_colfft_task(const float2* __restrict__ V, const int2* __restrict__ plc, int o0,
                                                  int o1, int strip, bool shift, float2* __restrict__ Hi,
                                                  int* occ_img, const float2* __restrict__ tw, float2* sbuf,
-                                                 unsigned* scnt, int* s_tmp) {
+                                                 unsigned* scnt, int* s_tmp, unsigned* s_max = nullptr) {
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, T = P::T, NP = P::NP;
+  constexpr bool SPLIT = PREC != kPrecFp32 && LOGN >= 4;
   for (int i = threadIdx.x; i < S * NP; i += blockDim.x) sbuf[i] = make_float2(0.f, 0.f);
   if constexpr (UNIFORM)
     for (int i = threadIdx.x; i < S * N; i += blockDim.x) scnt[i] = 0u;
-  if (threadIdx.x == 0) *s_tmp = 0;
+  if (threadIdx.x == 0) {
+    *s_tmp = 0;
+    if constexpr (SPLIT) *s_max = 0u;
+  }
   __syncthreads();
   scatter_strip<LOGN, S, true, UNIFORM>(plc, o0, o1, V, strip, NP, shift, sbuf, scnt);
   __syncthreads();
@@ -219,15 +226,20 @@ __device__ __forceinline__ void grid_colfft_task(const float2* __restrict__ V, c
     block_add_to_global(occ, s_tmp, occ_img);
     __syncthreads();
   }
-  const bool active = (int)threadIdx.x < S * T;
-  const int col = active ? (int)threadIdx.x / T : 0, lt = (int)threadIdx.x % T;
-  float2* cb = sbuf + col * NP;
-  float2 v[P::R];
-  if (active) {
+  if constexpr (SPLIT) {
+    fft_inverse_split<LOGN, PREC, true>(
+        sbuf, S, tw, [&](int c, int e) { return sbuf[c * NP + pad_index(e)]; }, [](int, int, float2) {}, s_max);
+  } else {
+    const bool active = (int)threadIdx.x < S * T;
+    const int col = active ? (int)threadIdx.x / T : 0, lt = (int)threadIdx.x % T;
+    float2* cb = sbuf + col * NP;
+    float2 v[P::R];
+    if (active) {
 #pragma unroll
-    for (int m = 0; m < P::R; ++m) v[m] = cb[pad_index(lt + m * T)];
+      for (int m = 0; m < P::R; ++m) v[m] = cb[pad_index(lt + m * T)];
+    }
+    fft_inverse<LOGN, true>(v, cb, tw, lt, [](int, float2) {}, active);
   }
-  fft_inverse<LOGN, true>(v, cb, tw, lt, [](int, float2) {}, active);
   for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
     const int y = i / S, c = i % S;
     float2 val = sbuf[c * NP + pad_index(y)];
@@ -241,37 +253,57 @@ __device__ __forceinline__ void grid_colfft_task(const float2* __restrict__ V, c
 // r = rowblk*TPB + j. Z[e] = Hf1[e] + i Hf2[e], where Hf is the Hermitian extension of a stored
 // half row: Hf[0] = Re H[0], Hf[N/2] = Im H[0], Hf[e] = H[e] (0 < e < N/2), Hf[e] = conj H[N-e].
 // The inverse FFT of Z is I1 + i I2 with both rows real; they are scaled by `scale` and stored.
-// The caller makes `tw` visible to the whole workgroup before the FFT's first barrier.
-template <int LOGN, int TPB>
+// The caller makes `tw` visible to the whole workgroup before the FFT's first barrier. With a
+// split PREC the workgroup is whole waves and `s_max` is that form's LDS word (as for the column
+// task, consecutive calls are separated by a workgroup barrier).
+__device__ __forceinline__ float2 hermitian_pair(const float2* __restrict__ h1, const float2* __restrict__ h2, int e,
+                                                 int N) {
+  const int HALF = N / 2;
+  const int idx = (e < HALF) ? e : ((e == HALF) ? 0 : N - e);
+  const float2 a = h1[idx], b = h2[idx];
+  if (e == 0) return make_float2(a.x, b.x);
+  if (e == HALF) return make_float2(a.y, b.y);
+  if (e < HALF) return make_float2(a.x - b.y, a.y + b.x);
+  return make_float2(a.x + b.y, b.x - a.y);
+}
+
+template <int LOGN, int TPB, int PREC = kPrecFp32>
 __device__ __forceinline__ void row_task(const float2* __restrict__ H, int rowblk, float scale, float* __restrict__ out,
-                                         const float2* __restrict__ tw, float2* sbuf) {
+                                         const float2* __restrict__ tw, float2* sbuf, unsigned* s_max = nullptr) {
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, T = P::T, NP = P::NP, HALF = N / 2;
-  const int j = (int)threadIdx.x / T, lt = (int)threadIdx.x % T;
-  const bool active = j < TPB;
-  const int r = rowblk * TPB + (active ? j : 0);
-  const float2* h1 = H + (size_t)(2 * r) * HALF;
-  const float2* h2 = h1 + HALF;
-  float2 v[P::R];
-  if (active) {
+  if constexpr (PREC != kPrecFp32 && LOGN >= 4) {
+    if (threadIdx.x == 0) *s_max = 0u;
+    __syncthreads();   // the caller's twiddle table is visible
+    const float2* hb = H + (size_t)(2 * rowblk * TPB) * HALF;
+    float* ob = out + (size_t)(2 * rowblk * TPB) * N;
+    fft_inverse_split<LOGN, PREC, false>(
+        sbuf, TPB, tw, [&](int c, int e) { return hermitian_pair(hb + (size_t)(2 * c) * HALF, hb + (size_t)(2 * c + 1) * HALF, e, N); },
+        [&](int c, int e, float2 z) {
+          float* o1 = ob + (size_t)(2 * c) * N;
+          o1[e] = z.x * scale;
+          o1[N + e] = z.y * scale;
+        },
+        s_max);
+  } else {
+    const int j = (int)threadIdx.x / T, lt = (int)threadIdx.x % T;
+    const bool active = j < TPB;
+    const int r = rowblk * TPB + (active ? j : 0);
+    const float2* h1 = H + (size_t)(2 * r) * HALF;
+    const float2* h2 = h1 + HALF;
+    float2 v[P::R];
+    if (active) {
 #pragma unroll
-    for (int m = 0; m < P::R; ++m) {
-      const int e = lt + m * T;
-      const int idx = (e < HALF) ? e : ((e == HALF) ? 0 : N - e);
-      const float2 a = h1[idx], b = h2[idx];
-      if (e == 0) v[m] = make_float2(a.x, b.x);
-      else if (e == HALF) v[m] = make_float2(a.y, b.y);
-      else if (e < HALF) v[m] = make_float2(a.x - b.y, a.y + b.x);
-      else v[m] = make_float2(a.x + b.y, b.x - a.y);
+      for (int m = 0; m < P::R; ++m) v[m] = hermitian_pair(h1, h2, lt + m * T, N);
     }
+    __syncthreads();   // the caller's twiddle table is visible
+    float* o1 = out + (size_t)(2 * r) * N;
+    float* o2 = o1 + N;
+    fft_inverse<LOGN, false>(v, sbuf + (active ? j : 0) * NP, tw, lt, [&](int e, float2 z) {
+      o1[e] = z.x * scale;
+      o2[e] = z.y * scale;
+    }, active);
   }
-  __syncthreads();   // the caller's twiddle table is visible
-  float* o1 = out + (size_t)(2 * r) * N;
-  float* o2 = o1 + N;
-  fft_inverse<LOGN, false>(v, sbuf + (active ? j : 0) * NP, tw, lt, [&](int e, float2 z) {
-    o1[e] = z.x * scale;
-    o2[e] = z.y * scale;
-  }, active);
 }
 
 __device__ __forceinline__ float inverse_weight(double W) {

@@ -57,10 +57,11 @@ struct ColArgs {
   float2* H;                // [n_img][N][N/2]
   int* occ;                 // [Q][P]
 };
-hipError_t launch_grid_colfft(const ColArgs& a, int n_img, int strip, const float2* tw, hipStream_t s);
+// `prec` selects the FFT form: BLINK_PREC_FP32 or a split matrix-core precision.
+hipError_t launch_grid_colfft(const ColArgs& a, int n_img, int strip, int prec, const float2* tw, hipStream_t s);
 
 // Column FFT of the Hermitian part of dense grids into H (blink_ifft2d).
-hipError_t launch_dense_colfft(const float2* grids, int n_img, int logn, int shift, float2* H,
+hipError_t launch_dense_colfft(const float2* grids, int n_img, int logn, int shift, int prec, float2* H,
                                const float2* tw, hipStream_t s);
 
 // Per-image 1/W (and W as double) from kept counts (natural) or occupancy (uniform).
@@ -80,7 +81,20 @@ struct RowArgs {
   const int* occ;           // [Q][P]
   double* weight_sum;       // chunk base or null
 };
-hipError_t launch_row_c2r(const RowArgs& a, int n_img, int tpb, const float2* tw, hipStream_t s);
+hipError_t launch_row_c2r(const RowArgs& a, int n_img, int tpb, int prec, const float2* tw, hipStream_t s);
+
+// The same three launchers for one precision form; FP32 is built in kernels.hip, each split
+// precision in its own object from split.hip.
+template <int PREC>
+struct PrecLaunch {
+  static hipError_t grid_colfft(const ColArgs& a, int n_img, int strip, const float2* tw, hipStream_t s);
+  static hipError_t dense_colfft(const float2* grids, int n_img, int logn, int shift, float2* H, const float2* tw,
+                                 hipStream_t s);
+  static hipError_t row_c2r(const RowArgs& a, int n_img, int tpb, const float2* tw, hipStream_t s);
+};
+extern template struct PrecLaunch<BLINK_PREC_FP32>;
+extern template struct PrecLaunch<BLINK_PREC_SPLIT_F16>;
+extern template struct PrecLaunch<BLINK_PREC_SPLIT_BF16>;
 
 // ---------------------------------------------------------------- uneven batches (persistent.hip)
 struct DescArgs {
@@ -109,8 +123,18 @@ struct DescArgs {
   const float2* tw[13];            // twiddle tables per log2 N
 };
 hipError_t launch_desc_prep(const DescArgs& a, hipStream_t s);
-hipError_t launch_persistent(const DescArgs& a, int workgroups, hipStream_t s);
+hipError_t launch_persistent(const DescArgs& a, int workgroups, int prec, hipStream_t s);
 // Resident workgroups of the persistent kernel per CU (0 if the configuration is not compiled).
-int persistent_blocks_per_cu(int block, bool uniform);
+int persistent_blocks_per_cu(int block, bool uniform, int prec);
+
+// The persistent kernel of one precision form (FP32 in persistent.hip, split forms in split.hip).
+template <int PREC>
+struct PersistLaunch {
+  static hipError_t launch(const DescArgs& a, int workgroups, hipStream_t s);
+  static int blocks_per_cu(int block, bool uniform);
+};
+extern template struct PersistLaunch<BLINK_PREC_FP32>;
+extern template struct PersistLaunch<BLINK_PREC_SPLIT_F16>;
+extern template struct PersistLaunch<BLINK_PREC_SPLIT_BF16>;
 
 }  // namespace blink

@@ -1,0 +1,178 @@
+// persistent.hpp — uneven batches: the persistent fused gridding + FFT kernel as a template over
+// the precision form (Section 6.2.4: many channels and intervals gridded in parallel on one GPU
+// and transformed all at once; here the images may differ in grid size and visibility count).
+// persistent.hip builds the descriptor pass and the FP32 form; split.hip builds the split forms.
+//
+//   k_persistent     every workgroup repeatedly claims the next image of the order prepared by the
+//                    descriptor pass and images it alone: nearest-cell binning into column strips,
+//                    the fused gridding + column FFT strip by strip into the workgroup's own
+//                    intermediate slot, then the row FFTs into the image
+//
+// Workgroups never wait for one another: the only shared state is the queue counter, so every
+// workgroup finishes once the queue is empty, whatever the number of resident workgroups. The
+// intermediate slot is written and read by the same workgroup, ordered by workgroup barriers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "imaging_device.hpp"
+#include "launch.hpp"
+
+namespace blink {
+
+// Strip width and row block of the persistent kernel for one grid size and block size: one
+// transform per T = N/16 threads, as many as the block holds (at most N/2).
+__host__ __device__ constexpr int fft_threads(int logn) { return logn >= 4 ? (1 << logn) / 16 : 1; }
+__host__ __device__ constexpr int desc_cols(int logn, int block) {
+  return cmin(block / fft_threads(logn), (1 << logn) / 2);
+}
+
+template <int BLOCK>
+struct PersistLds {
+  // float2 elements of the largest strip or row block over all grid sizes
+  static constexpr int f2(int logn) { return desc_cols(logn, BLOCK) * padded_len(1 << logn); }
+  static constexpr int max_f2() {
+    int m = 0;
+    for (int l = 3; l <= 12; ++l) m = f2(l) > m ? f2(l) : m;
+    return m;
+  }
+  static constexpr int max_counts() {
+    int m = 0;
+    for (int l = 3; l <= 12; ++l) {
+      int c = desc_cols(l, BLOCK) * (1 << l);
+      m = c > m ? c : m;
+    }
+    return m;
+  }
+};
+static_assert(sizeof(BinShared) <= sizeof(float2) * PersistLds<512>::max_f2(), "binning scratch aliases the strip");
+
+// ---------------------------------------------------------------- one image in one workgroup
+struct ImageJob {
+  const float2* V;          // visibilities of the image
+  const double* uvw;        // its baselines' uvw
+  const uint8_t* flags;     // its flags or null
+  int B;
+  double k;                 // cells per metre
+  int2* plc;                // this workgroup's placement list
+  int* off;                 // this workgroup's strip offsets
+  float2* H;                // this workgroup's intermediate slot
+  float* out;               // the image
+  int32_t* n_out;           // its out-of-grid count or null
+  double* wsum;             // its weight sum or null
+  int shift;
+};
+
+template <int S>
+struct Log2 {
+  static constexpr int value = S <= 1 ? 0 : 1 + Log2<S / 2>::value;
+};
+template <>
+struct Log2<1> {
+  static constexpr int value = 0;
+};
+
+template <int LOGN, int BLOCK, bool UNIFORM, int PREC>
+__device__ __noinline__ void image_job(ImageJob j, const float2* __restrict__ tw, float2* sbuf, unsigned* scnt,
+                                       int* s_int, unsigned* s_max) {
+  constexpr int N = 1 << LOGN;
+  constexpr int S = desc_cols(LOGN, BLOCK);
+  constexpr int NBLK = (N / 2) / S;         // column strips, and row blocks of S row pairs
+  constexpr int LOGS = Log2<S>::value;
+  static_assert((1 << LOGS) == S, "strip width is a power of two");
+  int* s_tmp = s_int;
+  int* s_kept = s_int + 1;
+  int* s_occ = s_int + 2;
+  BinShared& bsh = *reinterpret_cast<BinShared*>(sbuf);
+  bin_visibilities(j.uvw, j.flags, j.B, j.k, LOGN, LOGS, N / 2, j.plc, j.off, s_kept, j.n_out, nullptr, bsh);
+  if (threadIdx.x == 0) *s_occ = 0;
+  __syncthreads();                          // placement list and offsets complete; binning scratch free
+  for (int strip = 0; strip < NBLK; ++strip) {
+    grid_colfft_task<LOGN, S, UNIFORM, PREC>(j.V, j.plc, j.off[strip], j.off[strip + 1], strip, j.shift != 0, j.H,
+                                             s_occ, tw, sbuf, scnt, s_tmp, s_max);
+    __syncthreads();                        // the next strip reuses the strip buffer
+  }
+  const double W = UNIFORM ? (double)*s_occ : 2.0 * (double)*s_kept;
+  if (j.wsum && threadIdx.x == 0) *j.wsum = W;
+  const float scale = inverse_weight(W);
+  for (int rb = 0; rb < NBLK; ++rb) {
+    row_task<LOGN, S, PREC>(j.H, rb, scale, j.out, tw, sbuf, s_max);
+    __syncthreads();
+  }
+}
+
+template <int BLOCK, bool UNIFORM, int PREC>
+__global__ __launch_bounds__(BLOCK) void k_persistent(DescArgs a) {
+  using L = PersistLds<BLOCK>;
+  __shared__ float2 sbuf[L::max_f2()];
+  __shared__ unsigned scnt[UNIFORM ? L::max_counts() : 1];
+  __shared__ int s_int[4];
+  __shared__ int s_next;
+  __shared__ unsigned s_max;
+  const size_t slot_elems = (size_t)1 << (2 * a.max_logn - 1);
+  float2* H = a.H + (size_t)blockIdx.x * slot_elems;
+  int2* plc = a.plc + (size_t)blockIdx.x * 2 * a.max_b;
+  int* off = a.strip_off + (size_t)blockIdx.x * a.strip_stride;
+  for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int q = s_next;
+    __syncthreads();
+    if (q >= a.n_img) break;
+    const int img = a.order[q];
+    if (!a.valid[img]) continue;
+    const blink_image_desc d = a.desc[img];
+    const int logn = 31 - __clz(d.grid_n);
+    ImageJob j;
+    j.V = a.vis + d.vis_offset;
+    j.uvw = a.uvw + 3 * d.uvw_offset;
+    j.flags = a.flags ? a.flags + d.flag_offset : nullptr;
+    j.B = d.n_baselines;
+    j.k = (d.freq_hz / kSpeedOfLight) * ((double)d.grid_n * d.pixel_scale);
+    j.plc = plc;
+    j.off = off;
+    j.H = H;
+    j.out = a.images + d.image_offset;
+    j.n_out = a.n_out ? a.n_out + img : nullptr;
+    j.wsum = a.weight_sum ? a.weight_sum + img : nullptr;
+    j.shift = a.shift;
+    switch (logn) {
+      case 3: image_job<3, BLOCK, UNIFORM, PREC>(j, a.tw[3], sbuf, scnt, s_int, &s_max); break;
+      case 4: image_job<4, BLOCK, UNIFORM, PREC>(j, a.tw[4], sbuf, scnt, s_int, &s_max); break;
+      case 5: image_job<5, BLOCK, UNIFORM, PREC>(j, a.tw[5], sbuf, scnt, s_int, &s_max); break;
+      case 6: image_job<6, BLOCK, UNIFORM, PREC>(j, a.tw[6], sbuf, scnt, s_int, &s_max); break;
+      case 7: image_job<7, BLOCK, UNIFORM, PREC>(j, a.tw[7], sbuf, scnt, s_int, &s_max); break;
+      case 8: image_job<8, BLOCK, UNIFORM, PREC>(j, a.tw[8], sbuf, scnt, s_int, &s_max); break;
+      case 9: image_job<9, BLOCK, UNIFORM, PREC>(j, a.tw[9], sbuf, scnt, s_int, &s_max); break;
+      case 10: image_job<10, BLOCK, UNIFORM, PREC>(j, a.tw[10], sbuf, scnt, s_int, &s_max); break;
+      case 11: image_job<11, BLOCK, UNIFORM, PREC>(j, a.tw[11], sbuf, scnt, s_int, &s_max); break;
+      case 12: image_job<12, BLOCK, UNIFORM, PREC>(j, a.tw[12], sbuf, scnt, s_int, &s_max); break;
+      default: break;
+    }
+  }
+}
+
+template <int PREC>
+int PersistLaunch<PREC>::blocks_per_cu(int block, bool uniform) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (block == 512 && !uniform)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<512, false, PREC>, 512, 0);
+  if (block == 1024 && !uniform)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<1024, false, PREC>, 1024, 0);
+  if (block == 512 && uniform)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<512, true, PREC>, 512, 0);
+  return e == hipSuccess ? n : 0;
+}
+
+template <int PREC>
+hipError_t PersistLaunch<PREC>::launch(const DescArgs& a, int workgroups, hipStream_t s) {
+  if (a.n_img <= 0) return hipSuccess;
+  if (a.block == 512 && !a.weighting) k_persistent<512, false, PREC><<<workgroups, 512, 0, s>>>(a);
+  else if (a.block == 1024 && !a.weighting) k_persistent<1024, false, PREC><<<workgroups, 1024, 0, s>>>(a);
+  else if (a.block == 512 && a.weighting) k_persistent<512, true, PREC><<<workgroups, 512, 0, s>>>(a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace blink

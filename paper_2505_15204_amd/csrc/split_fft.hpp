@@ -1,0 +1,316 @@
+// split_fft.hpp — the precision form of the inverse FFT: radix-16 stages as gfx950 matrix-core
+// (MFMA) products in FP16 or BF16 with hi + lo split operands and FP32 accumulation.
+//
+// Same transform as fft_device.hpp (X[j] = sum_k x[k] exp(+2 pi i j k / N), Section 4, Eq. 5) and
+// the same self-sorting radix-16 stage order, so the LDS layout between stages is unchanged.
+// What differs is how one radix-16 butterfly is evaluated: the 16-point inverse DFT is the real
+// 32 x 32 matrix M that maps interleaved (re, im) inputs to interleaved outputs,
+//     M[2j][2q] = cos a,  M[2j][2q+1] = -sin a,  M[2j+1][2q] = sin a,  M[2j+1][2q+1] = cos a,
+// a = 2 pi (j q mod 16) / 16, and 32 butterflies at a time form the 32 x 32 right-hand side of
+// two v_mfma_f32_32x32x16 products (K = 16 reals each). Every FP32 operand x is split into
+// hi = round(x) and lo = round(x - hi) in the 16-bit type, and the product is
+//     M x ~ M_lo x_hi + M_hi x_lo + M_hi x_hi        (the lo * lo term is dropped)
+// accumulated in FP32: about 21 significant bits for FP16 (11 + 11), 16 for BF16 (8 + 8).
+// Twiddle multiplications between stages, and a final radix-2/4/8 stage where N is not a power
+// of 16, stay in FP32 on the vector ALUs. The reduced-precision study is left open by the paper
+// (Section 10, future work); this is one design for it.
+//
+// FP16 range: the inputs of a task (the columns of a strip, or the row pairs of a row block) are
+// scaled by one power of two so that their largest real or imaginary part lies in [32, 64). A
+// radix-16 stage with unit-modulus twiddles grows that bound by at most 16 sqrt(2) = 2^4.5, so
+// the inputs of the third radix-16 stage stay below 2^15 and no 16-bit operand overflows; the
+// outputs are multiplied back by the exact inverse power of two. BF16 has the FP32 exponent
+// range and needs no scaling.
+//
+// Wave layout of the MFMA products (v_mfma_f32_32x32x16_{f16,bf16}, wave64): with n = lane % 32
+// and g = lane / 32, lane (n, g) holds row n of A and column n of B for k = 8 g .. 8 g + 7, and
+// rows 8 (v / 4) + 4 g + v % 4 (v < 16) of column n of the FP32 result. Butterfly 64 w + 32 h + n
+// of a stage (wave w, batch h < 2) is column n of batch h; lane (n, g) loads its complex inputs
+// 4 g .. 4 g + 3 and 8 + 4 g .. 8 + 4 g + 3 and receives its outputs 4 t' + 2 g + {0, 1}, t' < 4.
+// A block of W waves covers 64 W butterflies per stage, one per thread as in the FP32 form;
+// the block size must be a multiple of 64 because the matrix operand A is spread over the
+// whole wave.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "fft_device.hpp"
+
+namespace blink {
+
+enum : int { kPrecFp32 = 0, kPrecSplitF16 = 1, kPrecSplitBf16 = 2 };
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int PREC>
+struct Split;
+
+template <>
+struct Split<kPrecSplitF16> {
+  using elem = _Float16;
+  using vec = f16x8;
+  static __device__ __forceinline__ f32x16 mma(vec a, vec b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Split<kPrecSplitBf16> {
+  using elem = __bf16;
+  using vec = bf16x8;
+  static __device__ __forceinline__ f32x16 mma(vec a, vec b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// hi = x rounded to nearest even in the 16-bit type, lo = (x - hi) rounded the same way.
+template <int PREC>
+__device__ __forceinline__ void split_value(float x, typename Split<PREC>::elem& hi, typename Split<PREC>::elem& lo) {
+  using E = typename Split<PREC>::elem;
+  hi = (E)x;
+  lo = (E)(x - (float)hi);
+}
+
+// The A operands (hi and lo, for K blocks 0 and 1) of this lane: row n of M, columns 16 kb + 8 g + e.
+// `tw` holds exp(+2 pi i j / N) for j < N; entry t N/16 is exp(+2 pi i t / 16).
+template <int PREC>
+struct DftOperands {
+  typename Split<PREC>::vec hi[2], lo[2];
+};
+
+template <int PREC, int N>
+__device__ __forceinline__ DftOperands<PREC> dft16_operands(const float2* __restrict__ tw) {
+  DftOperands<PREC> F;
+  const int lane = threadIdx.x & 63, n = lane & 31, g = lane >> 5;
+  const int j = n >> 1, p = n & 1;
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int q = 8 * kb + 4 * g + (e >> 1), r = e & 1;
+      const float2 w = tw[((j * q) & 15) * (N / 16)];
+      const float f = (p == 0) ? (r == 0 ? w.x : -w.y) : (r == 0 ? w.y : w.x);
+      typename Split<PREC>::elem h, l;
+      split_value<PREC>(f, h, l);
+      F.hi[kb][e] = h;
+      F.lo[kb][e] = l;
+    }
+  }
+  return F;
+}
+
+// One batch of 32 radix-16 butterflies: x[4 kb + i] is this lane's complex input 8 kb + 4 g + i.
+// Returns the FP32 result; output t (< 8) of this lane is complex 4 (t / 2) + 2 g + t % 2,
+// at (r[2 t], r[2 t + 1]).
+template <int PREC>
+__device__ __forceinline__ f32x16 dft16_mfma(const float2 (&x)[8], const DftOperands<PREC>& F) {
+  using S = Split<PREC>;
+  typename S::vec bhi[2], blo[2];
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      typename S::elem h, l;
+      split_value<PREC>(x[4 * kb + i].x, h, l);
+      bhi[kb][2 * i] = h;
+      blo[kb][2 * i] = l;
+      split_value<PREC>(x[4 * kb + i].y, h, l);
+      bhi[kb][2 * i + 1] = h;
+      blo[kb][2 * i + 1] = l;
+    }
+  }
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  // small terms first
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb) {
+    acc = S::mma(F.lo[kb], bhi[kb], acc);
+    acc = S::mma(F.hi[kb], blo[kb], acc);
+  }
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb) acc = S::mma(F.hi[kb], bhi[kb], acc);
+  return acc;
+}
+
+__device__ __forceinline__ int split_in_q(int g, int i) { return (i < 4) ? 4 * g + i : 8 + 4 * g + (i - 4); }
+__device__ __forceinline__ int split_out_j(int g, int t) { return 4 * (t >> 1) + 2 * g + (t & 1); }
+
+// Largest |re| or |im| over the block. *s_max must be 0 and visible to every thread on entry
+// (set before an earlier barrier); it keeps the maximum afterwards. Contains a block barrier.
+__device__ __forceinline__ float block_max_abs(float m, unsigned* s_max) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(s_max, __float_as_uint(m));
+  __syncthreads();
+  return __uint_as_float(*s_max);
+}
+
+// Power of two that brings a maximum magnitude mx into [32, 64).
+__device__ __forceinline__ int f16_scale_exponent(float mx) {
+  if (!(mx > 0.f) || !isfinite(mx)) return 0;
+  int e;
+  (void)frexpf(mx, &e);                 // mx = f 2^e, f in [0.5, 1)
+  e = 6 - e;
+  return e < -126 ? -126 : (e > 126 ? 126 : e);
+}
+
+// Complete inverse FFT of `ntrans` transforms of length N = 2^LOGN (LOGN >= 4) held by one block.
+// Transform c lives at buf + c * NP (padded, natural order) between stages. The first stage's
+// inputs come from load(c, e); the outputs go to sink(c, e, value), or, with ToLds, back into buf
+// at pad(e) with the block synchronised on return. Every thread of the block calls this; the
+// block size is a multiple of 64 and at least ntrans * N / 16. `tw` is the twiddle table for N
+// (visible to the block on entry); `s_max` as for block_max_abs (FP16 only).
+template <int LOGN, int PREC, bool ToLds, class Load, class Sink>
+__device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const float2* __restrict__ tw, Load load,
+                                                  Sink sink, unsigned* s_max) {
+  using P = FftPlan<LOGN>;
+  static_assert(LOGN >= 4, "the split form needs at least one radix-16 stage");
+  static_assert(PREC == kPrecSplitF16 || PREC == kPrecSplitBf16, "split precision");
+  constexpr int N = P::N, T = P::T, NP = P::NP, NB = N / 16;
+  const DftOperands<PREC> F = dft16_operands<PREC, N>(tw);
+  const int lane = threadIdx.x & 63, n = lane & 31, g = lane >> 5, w = threadIdx.x >> 6;
+  const int total = ntrans * NB;
+
+  // The butterfly of batch h of this lane, and whether it exists.
+  auto bfly = [&](int h, int& c, int& b) {
+    const int beta = 64 * w + 32 * h + n;
+    c = beta / NB;
+    b = beta % NB;
+    return beta < total;
+  };
+  // Emits the outputs of one MFMA stage with span NS; `last` stages go to the sink (or LDS).
+  auto emit = [&](const f32x16& r, int c, int b, bool act, auto ns_tag, auto last_tag, float u) {
+    constexpr int NS = decltype(ns_tag)::value;
+    constexpr bool LAST = decltype(last_tag)::value;
+    if (!act) return;
+    const int k = b & (NS - 1);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = (b - k) * 16 + k + split_out_j(g, t) * NS;
+      float2 val = make_float2(r[2 * t], r[2 * t + 1]);
+      if constexpr (LAST) {
+        val = cscale(val, u);
+        if constexpr (ToLds) buf[c * NP + pad_index(e)] = val;
+        else sink(c, e, val);
+      } else {
+        buf[c * NP + pad_index(e)] = val;
+      }
+    }
+  };
+
+  // ---- stage 0: radix 16, span 1, inputs from load()
+  float2 x[2][8];
+  bool act[2];
+  int cc[2], bb[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    act[h] = bfly(h, cc[h], bb[h]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[h][i] = act[h] ? load(cc[h], bb[h] + split_in_q(g, i) * NB) : make_float2(0.f, 0.f);
+  }
+  float u = 1.f;
+  if constexpr (PREC == kPrecSplitF16) {
+    float m = 0.f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) m = fmaxf(m, fmaxf(fabsf(x[h][i].x), fabsf(x[h][i].y)));
+    const int e = f16_scale_exponent(block_max_abs(m, s_max));   // also: every load of buf is done
+    const float s = ldexpf(1.f, e);
+    u = ldexpf(1.f, -e);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) x[h][i] = cscale(x[h][i], s);
+  } else {
+    __syncthreads();                     // every load of buf is done before the in-place stores
+  }
+  using One = std::integral_constant<int, 1>;
+  constexpr bool ONE_STAGE = (P::NST == 1);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const f32x16 r = dft16_mfma<PREC>(x[h], F);
+    emit(r, cc[h], bb[h], act[h], One{}, std::integral_constant<bool, ONE_STAGE>{}, u);
+  }
+  if constexpr (ONE_STAGE) {
+    if constexpr (ToLds) __syncthreads();
+    return;
+  } else {
+    __syncthreads();
+    // ---- later stages
+    auto mfma_stage = [&](auto ns_tag, auto last_tag) {
+      constexpr int NS = decltype(ns_tag)::value;
+      constexpr int STRIDE = N / (NS * 16);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        act[h] = bfly(h, cc[h], bb[h]);
+        const int k = bb[h] & (NS - 1);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int q = split_in_q(g, i);
+          const float2 v = act[h] ? buf[cc[h] * NP + pad_index(bb[h] + q * NB)] : make_float2(0.f, 0.f);
+          x[h][i] = cmul(v, tw[k * q * STRIDE]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const f32x16 r = dft16_mfma<PREC>(x[h], F);
+        emit(r, cc[h], bb[h], act[h], ns_tag, last_tag, u);
+      }
+    };
+    auto valu_stage = [&](auto ns_tag, auto rad_tag) {
+      // final small-radix stage in FP32, one thread per group of 16 elements as in fft_inverse
+      constexpr int NS = decltype(ns_tag)::value, RAD = decltype(rad_tag)::value;
+      const int c = threadIdx.x / T, lt = threadIdx.x % T;
+      const bool active = c < ntrans;
+      float2 v[16];
+      if (active) {
+        stage_load_lds<N, 16, T, RAD>(v, buf + c * NP, lt);
+        stage_compute<N, 16, T, NS, RAD>(v, lt, tw);
+      }
+      if constexpr (ToLds) __syncthreads();
+      if (active) {
+        constexpr int Q = 16 / RAD;
+#pragma unroll
+        for (int qq = 0; qq < Q; ++qq)
+#pragma unroll
+          for (int m = 0; m < RAD; ++m) {
+            const int e = stage_out_index<T, NS, RAD>(lt, qq, m);
+            const float2 val = cscale(v[qq * RAD + m], u);
+            if constexpr (ToLds) buf[c * NP + pad_index(e)] = val;
+            else sink(c, e, val);
+          }
+      }
+      if constexpr (ToLds) __syncthreads();
+    };
+    using B0 = std::integral_constant<bool, false>;
+    using B1 = std::integral_constant<bool, true>;
+    using S16 = std::integral_constant<int, 16>;
+    if constexpr (P::NST == 2) {
+      if constexpr (P::R1 == 16) {
+        mfma_stage(S16{}, B1{});
+        if constexpr (ToLds) __syncthreads();
+      } else {
+        valu_stage(S16{}, std::integral_constant<int, P::R1>{});
+      }
+    } else {
+      mfma_stage(S16{}, B0{});
+      __syncthreads();
+      using S256 = std::integral_constant<int, 256>;
+      if constexpr (P::R2 == 16) {
+        mfma_stage(S256{}, B1{});
+        if constexpr (ToLds) __syncthreads();
+      } else {
+        valu_stage(S256{}, std::integral_constant<int, P::R2>{});
+      }
+    }
+  }
+}
+
+}  // namespace blink
