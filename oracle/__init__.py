@@ -55,6 +55,17 @@ def load(path: str):
                                         P, P, P, P, P, i32]
     L.blink_ref_max_threads.restype = i32
     L.blink_ref_max_threads.argtypes = []
+    L.blink_ref_es_kernel.restype = f64
+    L.blink_ref_es_kernel.argtypes = [f64, f64]
+    L.blink_ref_es_transform.restype = f64
+    L.blink_ref_es_transform.argtypes = [f64, i32, f64]
+    L.blink_ref_grid_conv.restype = i32
+    L.blink_ref_grid_conv.argtypes = [P, P, P, i32, i32, f64, i32, f64, i32, f64, P, P, P]
+    L.blink_ref_conv_correction.restype = i32
+    L.blink_ref_conv_correction.argtypes = [i32, i32, f64, i32, P]
+    L.blink_ref_image_batch_conv.restype = i32
+    L.blink_ref_image_batch_conv.argtypes = [P, P, P, P, i32, i32, i32, i32, i32, f64, i32, f64, i32, P, P, P,
+                                             i32]
     return L
 
 
@@ -155,6 +166,59 @@ class Oracle:
     def max_threads(self) -> int:
         return int(self.L.blink_ref_max_threads())
 
+    # -- convolutional gridding (exponential-of-semicircle kernel, grid correction)
+    def es_kernel(self, z: float, beta: float) -> float:
+        return self.L.blink_ref_es_kernel(float(z), float(beta))
+
+    def es_transform(self, nu: float, width: int, beta: float) -> float:
+        return self.L.blink_ref_es_transform(float(nu), int(width), float(beta))
+
+    def grid_conv(self, vis, flags, uvw, freq_hz, grid_n, pixel_scale, width, beta):
+        """Convolutional gridding of one (t,c): vis complex [P][B] (or [B]). Returns dict(grid
+        complex128 [P][N][N], weight_sum, n_out)."""
+        vis = np.asarray(vis)
+        if vis.ndim == 1:
+            vis = vis[None]
+        P, B = vis.shape
+        v = _c(vis, np.complex64)
+        f = None if flags is None else _c(flags, np.uint8)
+        u = _c(uvw, np.float64)
+        N = int(grid_n)
+        g = np.empty((P, N, N), dtype=np.complex128)
+        W = ctypes.c_double()
+        nout = ctypes.c_int32()
+        rc = self.L.blink_ref_grid_conv(_ptr(v), _ptr(f), _ptr(u), P, B, float(freq_hz), N, float(pixel_scale),
+                                       int(width), float(beta), _ptr(g), ctypes.byref(W), ctypes.byref(nout))
+        if rc != 0:
+            raise ValueError(f"blink_ref_grid_conv failed with code {rc}")
+        return {"grid": g, "weight_sum": W.value, "n_out": nout.value}
+
+    def conv_correction(self, grid_n, width, beta, shift=True):
+        corr = np.empty(int(grid_n), dtype=np.float64)
+        rc = self.L.blink_ref_conv_correction(int(grid_n), int(width), float(beta), int(bool(shift)), _ptr(corr))
+        if rc != 0:
+            raise ValueError(f"blink_ref_conv_correction failed with code {rc}")
+        return corr
+
+    def image_batch_conv(self, vis, flags, uvw, freq_hz, grid_n, pixel_scale, width, beta, shift=True,
+                         n_threads=0):
+        """Convolutional path over vis [T][C][P][B]: dict(images, weight_sum, n_out)."""
+        v = _c(vis, np.complex64)
+        T, C, P, B = v.shape
+        f = None if flags is None else _c(flags, np.uint8)
+        u = _c(uvw, np.float64)
+        fr = _c(freq_hz, np.float64)
+        N = int(grid_n)
+        images = np.empty((T, C, P, N, N), dtype=np.float64)
+        W = np.empty((T, C, P), dtype=np.float64)
+        nout = np.empty((T, C), dtype=np.int32)
+        rc = self.L.blink_ref_image_batch_conv(_ptr(v), _ptr(f), _ptr(u), _ptr(fr), T, C, P, B, N,
+                                              float(pixel_scale), int(width), float(beta), int(bool(shift)),
+                                              _ptr(images), _ptr(W), _ptr(nout), int(n_threads))
+        if rc != 0:
+            raise ValueError(f"blink_ref_image_batch_conv failed with code {rc}")
+        return {"images": images, "weight_sum": W, "n_out": nout}
+
 
 def default() -> Oracle:
     return Oracle(lib())
@@ -182,3 +246,23 @@ def image_batch(*a, **k):
 
 def max_threads() -> int:
     return default().max_threads()
+
+
+def es_kernel(*a, **k):
+    return default().es_kernel(*a, **k)
+
+
+def es_transform(*a, **k):
+    return default().es_transform(*a, **k)
+
+
+def grid_conv(*a, **k):
+    return default().grid_conv(*a, **k)
+
+
+def conv_correction(*a, **k):
+    return default().conv_correction(*a, **k)
+
+
+def image_batch_conv(*a, **k):
+    return default().image_batch_conv(*a, **k)

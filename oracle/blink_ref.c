@@ -238,3 +238,146 @@ int blink_ref_image_batch(const float *vis, const uint8_t *flags, const double *
     }
     return err;
 }
+
+/* ------------------------------------------------------------------------------------------
+ * Convolutional gridding (a step beyond the paper: Section 6.2.4 places visibilities with no
+ * convolution kernel and names one as a planned improvement against aliasing; Section 10 lists
+ * it as work in progress). The kernel is the "exponential of semicircle" of Barnett, Magland and
+ * af Klinteberg (2019): phi(z) = exp(beta (sqrt(1 - z^2) - 1)) for |z| < 1, else 0, applied
+ * separably in u and v with z = 2 d / W for a cell offset d and a support of W cells. The
+ * image is divided by the kernel's continuous Fourier transform at each pixel (grid correction).
+ * ------------------------------------------------------------------------------------------ */
+
+double blink_ref_es_kernel(double z, double beta)
+{
+    if (!(fabs(z) < 1.0)) return 0.0;
+    return exp(beta * (sqrt(1.0 - z * z) - 1.0));
+}
+
+/* c(nu) = integral over |d| < W/2 of phi(2d/W) cos(2 pi nu d) dd. With d = (W/2) sin(theta)
+ * the integrand is smooth: c(nu) = W * integral_0^{pi/2} exp(beta (cos t - 1)) cos(pi nu W sin t)
+ * cos t dt, evaluated by composite Simpson's rule on 4096 intervals. */
+double blink_ref_es_transform(double nu, int width, double beta)
+{
+    const int M = 4096;
+    const double h = (M_PI / 2.0) / M;
+    double s = 0.0;
+    for (int i = 0; i <= M; ++i) {
+        double t = i * h;
+        double f = exp(beta * (cos(t) - 1.0)) * cos(M_PI * nu * width * sin(t)) * cos(t);
+        double w = (i == 0 || i == M) ? 1.0 : ((i % 2) ? 4.0 : 2.0);
+        s += w * f;
+    }
+    return (double)width * s * h / 3.0;
+}
+
+/* One visibility value spread over the cells j (integers with |j - x| < W/2) of each axis with
+ * weights phi(2 (j - x) / W); cells wrap modulo N. */
+static void spread(double *g, int N, double xu, double xv, int width, double beta, double re, double im)
+{
+    const double h = 0.5 * width;
+    int ju0 = (int)ceil(xu - h), jv0 = (int)ceil(xv - h);
+    for (int jv = jv0; jv < xv + h; ++jv) {
+        if (!(fabs(jv - xv) < h)) continue;
+        double wv = blink_ref_es_kernel(2.0 * (jv - xv) / width, beta);
+        for (int ju = ju0; ju < xu + h; ++ju) {
+            if (!(fabs(ju - xu) < h)) continue;
+            double w = wv * blink_ref_es_kernel(2.0 * (ju - xu) / width, beta);
+            size_t c = (size_t)mod_n(jv, N) * N + mod_n(ju, N);
+            g[2 * c] += w * re;
+            g[2 * c + 1] += w * im;
+        }
+    }
+}
+
+int blink_ref_grid_conv(const float *vis, const uint8_t *flags, const double *uvw, int P, int B,
+                        double freq_hz, int grid_n, double pixel_scale, int width, double beta,
+                        double *grid, double *weight_sum, int32_t *n_out)
+{
+    if (!is_pow2(grid_n) || P < 1 || B < 0 || !vis || !uvw || !grid || !weight_sum || !n_out)
+        return 1;
+    if (width < 1 || width > 16 || !(beta >= 0.0) || !isfinite(beta) || width >= grid_n) return 1;
+    const int N = grid_n;
+    const size_t NN = (size_t)N * N;
+    memset(grid, 0, sizeof(double) * 2 * NN * (size_t)P);
+    const double k = blink_ref_cells_per_metre(freq_hz, N, pixel_scale);
+    const double half = (double)(N / 2);
+    int32_t outside = 0;
+    int64_t kept = 0;
+    for (int b = 0; b < B; ++b) {
+        if (flags && flags[b]) continue;
+        double xu = uvw[3 * (size_t)b + 0] * k;
+        double xv = uvw[3 * (size_t)b + 1] * k;
+        double ru = nearbyint(xu), rv = nearbyint(xv);
+        if (!(fabs(rv) < half && fabs(ru) < half)) {   /* the nearest-cell keep rule */
+            ++outside;
+            continue;
+        }
+        ++kept;
+        for (int p = 0; p < P; ++p) {
+            const float *v = vis + 2 * ((size_t)p * B + b);
+            double re = (double)v[0], im = (double)v[1];
+            double *g = grid + 2 * NN * (size_t)p;
+            spread(g, N, xu, xv, width, beta, re, im);      /* V at (u, v) */
+            spread(g, N, -xu, -xv, width, beta, re, -im);   /* conj V at (-u, -v) */
+        }
+    }
+    *weight_sum = 2.0 * (double)kept;
+    *n_out = outside;
+    return 0;
+}
+
+/* Grid correction of one axis: corr[x] = c(X / N) for pixel x, X its signed offset from the phase
+ * centre (x - N/2 when shifted, else x for x < N/2 and x - N above). */
+int blink_ref_conv_correction(int grid_n, int width, double beta, int shift, double *corr)
+{
+    if (!is_pow2(grid_n) || !corr || width < 1 || width > 16 || !(beta >= 0.0)) return 1;
+    const int N = grid_n;
+    for (int x = 0; x < N; ++x) {
+        int X = shift ? x - N / 2 : (x < N / 2 ? x : x - N);
+        corr[x] = blink_ref_es_transform((double)X / N, width, beta);
+    }
+    return 0;
+}
+
+int blink_ref_image_batch_conv(const float *vis, const uint8_t *flags, const double *uvw,
+                               const double *freq_hz, int T, int C, int P, int B, int grid_n,
+                               double pixel_scale, int width, double beta, int shift, double *images,
+                               double *weight_sum, int32_t *n_out, int n_threads)
+{
+    if (!is_pow2(grid_n) || T < 0 || C < 0 || P < 1 || B < 0) return 1;
+    if (!vis || !uvw || !freq_hz || !images) return 1;
+    const int N = grid_n;
+    const size_t NN = (size_t)N * N;
+    double *corr = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!corr) return 2;
+    if (blink_ref_conv_correction(N, width, beta, shift, corr)) { free(corr); return 1; }
+    const long n_tc = (long)T * C;
+    int err = 0;
+#ifdef _OPENMP
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads) reduction(max : err)
+#endif
+    for (long tc = 0; tc < n_tc; ++tc) {
+        const long t = tc / C, c = tc % C;
+        double *grid = (double *)malloc(sizeof(double) * 2 * NN * (size_t)P);
+        if (!grid) { err = 2; continue; }
+        double W = 0.0;
+        int32_t nout = 0;
+        int rc = blink_ref_grid_conv(vis + 2 * (size_t)tc * P * B, flags ? flags + (size_t)tc * B : NULL,
+                                     uvw + 3 * (size_t)t * B, P, B, freq_hz[c], N, pixel_scale, width, beta,
+                                     grid, &W, &nout);
+        for (int p = 0; rc == 0 && p < P; ++p) {
+            double *img = images + ((size_t)tc * P + p) * NN;
+            rc = blink_ref_ifft2d(grid + 2 * NN * (size_t)p, N, W, shift, img, NULL);
+            for (int y = 0; rc == 0 && y < N; ++y)
+                for (int x = 0; x < N; ++x) img[(size_t)y * N + x] /= corr[x] * corr[y];
+            if (weight_sum) weight_sum[(size_t)tc * P + p] = W;
+        }
+        if (n_out) n_out[tc] = nout;
+        if (rc > err) err = rc;
+        free(grid);
+    }
+    free(corr);
+    return err;
+}

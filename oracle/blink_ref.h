@@ -75,6 +75,29 @@ int blink_ref_image_batch(const float *vis, const uint8_t *flags, const double *
                           double *weight_sum, int32_t *n_out, int32_t *cell_idx,
                           int32_t *counts, int n_threads);
 
+/* Convolutional gridding (beyond the paper's nearest-cell placement, Section 6.2.4; the paper plans
+ * a gridding kernel against aliasing, Section 10). Kernel: phi(z) = exp(beta (sqrt(1 - z^2) - 1))
+ * for |z| < 1 ("exponential of semicircle", Barnett, Magland & af Klinteberg 2019), z = 2 d / W for
+ * a cell offset d, support W cells, applied separably; a kept visibility V at cell position
+ * (x, y) = (u k, v k) adds phi(2 (ju - x)/W) phi(2 (jv - y)/W) V to every cell (ju, jv) with
+ * |ju - x| < W/2 and |jv - y| < W/2 (cells wrap modulo N), and conj(V) likewise around (-x, -y).
+ * The keep rule is the nearest-cell one; natural weighting only (W_sum = 2 x kept). The image
+ * is Re(IDFT2(G)) / W_sum / (c(X/N) c(Y/N)), c the kernel's continuous Fourier transform. */
+double blink_ref_es_kernel(double z, double beta);
+/* c(nu) = integral_{|d| < W/2} phi(2 d / W) cos(2 pi nu d) dd (composite Simpson, 4096 intervals). */
+double blink_ref_es_transform(double nu, int width, double beta);
+/* grid: out complex double [P][N][N]; width 1..16 (< N), beta >= 0. */
+int blink_ref_grid_conv(const float *vis, const uint8_t *flags, const double *uvw, int P, int B,
+                        double freq_hz, int grid_n, double pixel_scale, int width, double beta,
+                        double *grid, double *weight_sum, int32_t *n_out);
+/* corr[x] = c(X/N), X the signed offset of pixel x from the phase centre. */
+int blink_ref_conv_correction(int grid_n, int width, double beta, int shift, double *corr);
+/* Whole convolutional path over a batch (layouts as blink_ref_image_batch). */
+int blink_ref_image_batch_conv(const float *vis, const uint8_t *flags, const double *uvw,
+                               const double *freq_hz, int T, int C, int P, int B, int grid_n,
+                               double pixel_scale, int width, double beta, int shift, double *images,
+                               double *weight_sum, int32_t *n_out, int n_threads);
+
 /* Number of threads blink_ref_image_batch would use for n_threads <= 0. */
 int blink_ref_max_threads(void);
 

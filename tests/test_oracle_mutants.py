@@ -31,6 +31,19 @@ MUTANTS = {
     "mirror_cell_wrong": ("size_t c2 = (size_t)mod_n(-iv, N) * N + mod_n(-iu, N);",
                           "size_t c2 = (size_t)mod_n(-iv, N) * N + mod_n(iu, N);"),
     "butterfly_sign": ("y[0] = x[0] - tr; y[1] = x[1] - ti;", "y[0] = x[0] + tr; y[1] = x[1] - ti;"),
+    # convolutional gridding
+    "conv_mirror_not_conjugated": ("spread(g, N, -xu, -xv, width, beta, re, -im);",
+                                   "spread(g, N, -xu, -xv, width, beta, re, im);"),
+    "conv_mirror_not_mirrored": ("spread(g, N, -xu, -xv, width, beta, re, -im);",
+                                 "spread(g, N, -xu, xv, width, beta, re, -im);"),
+    "conv_support_halved": ("const double h = 0.5 * width;", "const double h = 0.25 * width;"),
+    "conv_kernel_no_sqrt": ("return exp(beta * (sqrt(1.0 - z * z) - 1.0));", "return exp(beta * ((1.0 - z * z) - 1.0));"),
+    "conv_correction_not_centred": ("int X = shift ? x - N / 2 : (x < N / 2 ? x : x - N);",
+                                    "int X = shift ? x : (x < N / 2 ? x : x - N);"),
+    "conv_correction_one_axis": ("img[(size_t)y * N + x] /= corr[x] * corr[y];", "img[(size_t)y * N + x] /= corr[x] * corr[x];"),
+    "conv_transform_frequency": ("cos(M_PI * nu * width * sin(t))", "cos(2.0 * M_PI * nu * width * sin(t))"),
+    "conv_edge_not_strict": ("fabs(rv) < half && fabs(ru) < half", "fabs(rv) <= half && fabs(ru) <= half"),
+    "conv_weight_halved": ("*weight_sum = 2.0 * (double)kept;", "*weight_sum = (double)kept;"),
 }
 
 
@@ -44,7 +57,7 @@ def test_pins_catch_planted_mistake(tmp_path, name):
     lib = oracle.compile_library(str(path), str(tmp_path / f"libmut_{name}.so"))
     O = oracle.Oracle(oracle.load(lib))
     caught = []
-    for pin in oracle_pins.PINS:
+    for pin in oracle_pins.PINS + oracle_pins.CONV_PINS:
         try:
             pin(O)
         except Exception:  # any failure of a pin counts as caught
