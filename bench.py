@@ -11,8 +11,9 @@ Prints one JSON line with images/s (FP32 form), the roofline position of the dom
 (bytes from the algorithmic byte model / its hipEvent-measured launch time), per-kernel figures,
 the FP64 CPU oracle timed on a bounded sample of the same workload on the host cores, and the
 other forms measured beside it on the same GPU: the split-precision matrix-core FFT forms on
-this workload and on the 4096^2 precision workload (images/s ratio to FP32), and the uneven
-batch (4096 images of 512^2 .. 2048^2 in one persistent launch, eager and as a hipGraph).
+this workload and on the 4096^2 precision workload (images/s ratio to FP32), convolutional
+gridding (W = 8) on this workload, and the uneven batch (4096 images of 512^2 .. 2048^2 in one
+persistent launch, eager and as a hipGraph).
 """
 import argparse
 import json
@@ -337,6 +338,23 @@ def main():
                                        "plan": ctx.get_plan(N, 0, prec),
                                        "kernels": {k: fk[k] for k in ("grid_colfft", "row_fft") if k in fk}}
             log(f"{name}: {v:.0f} images/s ({v / value:.3f} x FP32)")
+        # Convolutional gridding (W = 8, beta = 18.4) on the same workload, FP32.
+        cws = torch.empty(blink.image_batch_conv_workspace_size(1, C, P, B, N, 8), dtype=torch.uint8, device="cuda:0")
+
+        def cstep(i):
+            t = i % T
+            ctx.blink_image_batch_conv(d["vis"][t:t + 1], d["flags"][t:t + 1], d["uvw_m"][t:t + 1], d["freq_hz"], N,
+                                       spec.pixel_scale, 8, 18.4, out=images, weight_sum=wsum, n_out=nout,
+                                       workspace=cws)
+        ms = timed(torch, cstep, fs, 2)
+        cprof, _ = profiled(ctx, torch, cstep, fs)
+        ck = kernel_table(cprof, {"image": fs * C * P, "pair": fs * C}, ub)
+        v = fs * C * P / (ms / 1e3)
+        forms["vcs-1024"]["conv_w8_fp32"] = {"images_per_s": round(v, 1), "vs_fp32": round(v / value, 4),
+                                             "kernel": "exponential of semicircle, W = 8, beta = 18.4",
+                                             "kernels": {k: ck[k] for k in ("bin", "grid_colfft", "row_fft") if k in ck}}
+        log(f"conv W=8: {v:.0f} images/s ({v / value:.3f} x nearest-cell FP32)")
+        del cws
         forms["precision-4096"] = bench_precision_workload(ctx, torch, blink, synth, 3, 1)
         forms["uneven"] = bench_uneven(ctx, torch, blink, synth, 3)
 

@@ -148,6 +148,27 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32 *vis, const uint8
                                int32_t *n_out, void *workspace, size_t workspace_bytes,
                                void *hip_stream);
 
+/* ---------------------------------------------------------------- convolutional gridding
+ * A step beyond the paper, which places visibilities on their nearest cell with no convolution
+ * kernel (Section 6.2.4) and names a gridding kernel against aliasing as planned work (Sections 7
+ * and 10). Here each kept visibility (same keep rule, natural weighting) is spread over the cells
+ * within W/2 of its exact position (x, y) = (u k, v k) with the separable weights
+ * phi(2 (ju - x)/W) phi(2 (jv - y)/W), phi(z) = exp(beta (sqrt(1 - z^2) - 1)) for |z| < 1 (the
+ * "exponential of semicircle" kernel of Barnett, Magland & af Klinteberg, 2019); conj(V) spreads
+ * around (-x, -y); cells wrap modulo N. The image is Re(IDFT2(G)) / W_sum divided by
+ * c(X/N) c(Y/N), c(nu) = integral of phi(2d/W) cos(2 pi nu d) dd (the kernel's Fourier transform),
+ * X, Y the pixel offsets from the phase centre. kernel_width is 1..16 and below N/2, kernel_beta
+ * 0..100 (e.g. W = 8, beta = 2.3 W). Same layouts, workspace rules and outputs as
+ * blink_image_batch; plans: the natural-weighting plan's row block and group. */
+blink_status blink_image_batch_conv_workspace_size(int T, int C, int P, int B, int grid_n,
+                                                   int kernel_width, int precision, size_t *bytes);
+blink_status blink_image_batch_conv(blink_ctx ctx, const blink_cf32 *vis, const uint8_t *flags,
+                                    const double *uvw_m, const double *freq_hz, int T, int C,
+                                    int P, int B, int grid_n, double pixel_scale, int kernel_width,
+                                    double kernel_beta, int precision, int shift, float *images,
+                                    double *weight_sum, int32_t *n_out, void *workspace,
+                                    size_t workspace_bytes, void *hip_stream);
+
 /* ---------------------------------------------------------------- uneven batches
  * Section 6.2.4 grids many fine channels and integration intervals in parallel on one GPU and
  * transforms all grids at once. blink_image_batch_desc does this for images that differ in grid
@@ -273,7 +294,8 @@ enum {
     BLINK_KERNEL_ROW_FFT = 5,      /* row FFT, real part, 1/W, image store */
     BLINK_KERNEL_DESC_PREP = 6,    /* descriptor checks and image order (uneven batches) */
     BLINK_KERNEL_PERSISTENT = 7,   /* persistent fused binning + gridding + FFT (uneven batches) */
-    BLINK_KERNEL_COUNT = 8
+    BLINK_KERNEL_CONV_CORRECTION = 8, /* grid-correction table of the convolutional path */
+    BLINK_KERNEL_COUNT = 9
 };
 
 /* Enable (nonzero) or disable timing; either way the recorded launches are discarded. */

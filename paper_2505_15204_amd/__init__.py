@@ -20,8 +20,8 @@ PLANS_PATH = os.path.join(PKG, "plans_gfx950.json")     # autotuned execution pl
 
 BLINK_OK, BLINK_ERR_ARG, BLINK_ERR_SIZE, BLINK_ERR_NOMEM, BLINK_ERR_HIP, BLINK_ERR_STATE = range(6)
 WEIGHT_NATURAL, WEIGHT_UNIFORM = 0, 1
-KERNELS = ("bin", "grid", "grid_colfft", "dense_colfft", "weights", "row_fft", "desc_prep",
-           "persistent")   # BLINK_KERNEL_* ids
+KERNELS = ("bin", "grid", "grid_colfft", "dense_colfft", "weights", "row_fft", "desc_prep", "persistent",
+           "conv_correction")   # BLINK_KERNEL_* ids
 DESC_BAD = 1
 
 # blink_image_desc as a NumPy structured dtype (64 bytes, C layout)
@@ -89,6 +89,11 @@ def lib() -> ctypes.CDLL:
     L.blink_get_plan.argtypes = [P, i32, i32, i32, P, P, P]
     L.blink_set_plan.restype = i32
     L.blink_set_plan.argtypes = [P, i32, i32, i32, i32, i32, i32]
+    L.blink_image_batch_conv_workspace_size.restype = i32
+    L.blink_image_batch_conv_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
+    L.blink_image_batch_conv.restype = i32
+    L.blink_image_batch_conv.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, f64, i32, i32, P, P, P,
+                                         P, sz, P]
     L.blink_autotune_image_batch.restype = i32
     L.blink_autotune_image_batch.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32, P, P,
                                              P, P, sz, P, P, P, P, P]
@@ -146,6 +151,14 @@ def image_batch_workspace_size(T: int, C: int, P: int, B: int, grid_n: int, weig
     n = ctypes.c_size_t()
     _check(lib().blink_image_batch_workspace_size(T, C, P, B, grid_n, weighting, precision, ctypes.byref(n)),
            what="blink_image_batch_workspace_size")
+    return n.value
+
+
+def image_batch_conv_workspace_size(T: int, C: int, P: int, B: int, grid_n: int, kernel_width: int,
+                                    precision: int = PREC_FP32) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().blink_image_batch_conv_workspace_size(T, C, P, B, grid_n, kernel_width, precision, ctypes.byref(n)),
+           what="blink_image_batch_conv_workspace_size")
     return n.value
 
 
@@ -449,6 +462,36 @@ class Context:
                                      _ptr(out), _ptr(weight_sum), _ptr(n_out), _ptr(ws), ws.numel(),
                                      self._stream(stream))
         _check(st, self.handle, "blink_image_batch")
+        return {"images": out, "weight_sum": weight_sum, "n_out": n_out}
+
+    def blink_image_batch_conv(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float,
+                               kernel_width: int = 8, kernel_beta: float = 18.4, precision: int = PREC_FP32,
+                               shift: bool = True, out=None, weight_sum=None, n_out=None, workspace=None,
+                               stream=None):
+        """Convolutional gridding (exponential-of-semicircle kernel of kernel_width cells) + inverse
+        2D FFT + grid correction, natural weighting. Same arguments and outputs as blink_image_batch."""
+        torch = self._torch()
+        T, C, P, B = vis.shape
+        N = int(grid_n)
+        self._require("vis", vis, torch.complex64)
+        if flags is not None:
+            self._require("flags", flags, torch.uint8, (T, C, B))
+        self._require("uvw_m", uvw_m, torch.float64, (T, B, 3))
+        self._require("freq_hz", freq_hz, torch.float64, (C,))
+        dev = vis.device
+        if out is None:
+            out = torch.empty((T, C, P, N, N), dtype=torch.float32, device=dev)
+        self._require("out", out, torch.float32, (T, C, P, N, N))
+        if weight_sum is None:
+            weight_sum = torch.empty((T, C, P), dtype=torch.float64, device=dev)
+        if n_out is None:
+            n_out = torch.empty((T, C), dtype=torch.int32, device=dev)
+        ws = self._workspace(image_batch_conv_workspace_size(T, C, P, B, N, kernel_width, precision), workspace)
+        st = lib().blink_image_batch_conv(self.handle, _ptr(vis), _ptr(flags), _ptr(uvw_m), _ptr(freq_hz), T, C, P,
+                                          B, N, float(pixel_scale), int(kernel_width), float(kernel_beta),
+                                          int(precision), int(bool(shift)), _ptr(out), _ptr(weight_sum),
+                                          _ptr(n_out), _ptr(ws), ws.numel(), self._stream(stream))
+        _check(st, self.handle, "blink_image_batch_conv")
         return {"images": out, "weight_sum": weight_sum, "n_out": n_out}
 
 

@@ -18,8 +18,10 @@ constexpr int kPrecForms = 3;   // BLINK_PREC_FP32, BLINK_PREC_SPLIT_F16, BLINK_
 
 struct blink_ctx_s {
   int device = 0;
-  float2* tw_base = nullptr;      // twiddle tables for N = 8 .. 4096, concatenated
+  float2* tw_base = nullptr;      // stage-ordered twiddle tables for N = 8 .. 4096, concatenated,
+                                  // then the split forms' DFT operand table
   float2* tw[13] = {};
+  const uint4* dft_ops = nullptr;
   bool broken = false;
   std::string err;
   // execution plan per (log2 N, weighting, precision form): fused-kernel strip width, row
@@ -181,6 +183,37 @@ ImageLayout image_layout(size_t Q, int P, int B, int logn, int uniform, size_t h
   return L;
 }
 
+// Convolutional path: records of the strips each placement reaches, the grid-correction table and
+// the intermediates.
+struct ConvLayout {
+  BinLayout bins;
+  size_t corr, H, total;
+  int rec_stride;
+  bool ok;
+};
+
+ConvLayout conv_layout(size_t Q, int P, int B, int logn, int width, size_t h_images) {
+  const size_t N = size_t(1) << logn;
+  const int S = blink::conv_strip_width(logn);
+  const size_t nstrips = (N / 2) / (size_t)S;
+  ConvLayout L;
+  L.rec_stride = blink::conv_records_per_pair(B, width, S);
+  Carve c;
+  L.bins.plc = c.take(Q, (size_t)L.rec_stride * 16);
+  L.bins.off = c.take(Q, (nstrips + 1) * sizeof(int));
+  L.bins.kept = c.take(Q, sizeof(int));
+  L.bins.occ = c.take(Q, (size_t)P * sizeof(int));
+  L.corr = c.take(N, sizeof(float));
+  L.H = c.take(h_images, N * (N / 2) * sizeof(float2));
+  L.total = c.off;
+  L.ok = c.ok;
+  return L;
+}
+
+bool conv_args_ok(int width, double beta, int logn) {
+  return width >= 1 && width <= 16 && 2 * width < (1 << logn) && beta >= 0.0 && std::isfinite(beta) && beta <= 100.0;
+}
+
 struct GridLayout {
   BinLayout bins;
   size_t total;
@@ -295,7 +328,9 @@ blink_status blink_create(blink_ctx* out, int hip_device) {
     return BLINK_ERR_HIP;
   }
   size_t total = 0;
-  for (int l = 3; l <= 12; ++l) total += size_t(1) << l;
+  for (int l = 3; l <= 12; ++l) total += (size_t)blink::twiddle_table_size(l);
+  const size_t ops_off = (total + 1) / 2 * 2;     // 16-byte aligned (float2 units)
+  total = ops_off + (size_t)blink::kDftOpsCount * 2;
   if (hipMalloc(&ctx->tw_base, total * sizeof(float2)) != hipSuccess) {
     delete ctx;
     return BLINK_ERR_NOMEM;
@@ -304,9 +339,11 @@ blink_status blink_create(blink_ctx* out, int hip_device) {
   hipError_t e = hipSuccess;
   for (int l = 3; l <= 12 && e == hipSuccess; ++l) {
     ctx->tw[l] = ctx->tw_base + off;
-    e = blink::launch_twiddles(ctx->tw[l], 1 << l, nullptr);
-    off += size_t(1) << l;
+    e = blink::launch_twiddles(ctx->tw[l], l, nullptr);
+    off += (size_t)blink::twiddle_table_size(l);
   }
+  ctx->dft_ops = (const uint4*)(ctx->tw_base + ops_off);
+  if (e == hipSuccess) e = blink::launch_dft_operands(ctx->tw[4], (uint4*)(ctx->tw_base + ops_off), nullptr);
   for (int l = 3; l <= 12; ++l) {
     for (int u = 0; u < 2; ++u) {
       int col[4], row[4];
@@ -495,7 +532,7 @@ blink_status blink_ifft2d(blink_ctx ctx, const blink_cf32* grids, const double* 
     {
       KernelTimer kt(ctx, BLINK_KERNEL_DENSE_COLFFT, s);
       e = blink::launch_dense_colfft((const float2*)grids + i0 * N * N, q, logn, shift != 0, precision, H,
-                                     ctx->tw[logn], s);
+                                     ctx->tw[logn], ctx->dft_ops, s);
     }
     if (e == hipSuccess) {
       blink::RowArgs ra{};
@@ -506,6 +543,7 @@ blink_status blink_ifft2d(blink_ctx ctx, const blink_cf32* grids, const double* 
       ra.img0 = (int)i0;
       ra.wmode = blink::kWeightUser;
       ra.w_user = weight_sum;
+      ra.dft_ops = ctx->dft_ops;
       KernelTimer kt(ctx, BLINK_KERNEL_ROW_FFT, s);
       e = blink::launch_row_c2r(ra, q, ctx->plan[logn][0][precision].row_tpb, precision, ctx->tw[logn], s);
     }
@@ -588,6 +626,7 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
     ca.shift = shift != 0;
     ca.H = (float2*)(ws + L.H);
     ca.occ = ba.occ;
+    ca.dft_ops = ctx->dft_ops;
     const int n_img = q * P;
     blink::RowArgs ra{};
     ra.H = ca.H;
@@ -597,6 +636,7 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
     ra.n_kept = ba.n_kept;
     ra.occ = ba.occ;
     ra.weight_sum = weight_sum ? weight_sum + tc0 * P : nullptr;
+    ra.dft_ops = ctx->dft_ops;
     // Images go through the two passes G at a time so that their intermediates can stay in the
     // last-level cache between the column and the row launch.
     for (int i0 = 0; i0 < n_img; i0 += G) {
@@ -607,6 +647,139 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
         e = blink::launch_grid_colfft(ca, gi, S, precision, ctx->tw[logn], s);
       }
       if (e != hipSuccess) return hip_fail(ctx, e, "grid+column FFT kernel");
+      ra.img0 = i0;
+      ra.images = images + (tc0 * P + i0) * N * N;
+      {
+        KernelTimer kt(ctx, BLINK_KERNEL_ROW_FFT, s);
+        e = blink::launch_row_c2r(ra, gi, plan.row_tpb, precision, ctx->tw[logn], s);
+      }
+      if (e != hipSuccess) return hip_fail(ctx, e, "row FFT kernel");
+    }
+  }
+  return BLINK_OK;
+}
+
+blink_status blink_image_batch_conv_workspace_size(int T, int C, int P, int B, int grid_n, int kernel_width,
+                                                   int precision, size_t* bytes) {
+  if (!bytes || T < 0 || C < 0 || P < 1 || B < 0) return BLINK_ERR_ARG;
+  if (!valid_precision(precision)) return BLINK_ERR_ARG;
+  const int logn = log2_exact(grid_n);
+  if (logn < 0) return BLINK_ERR_SIZE;
+  if (!conv_args_ok(kernel_width, 0.0, logn)) return BLINK_ERR_ARG;
+  const size_t n_img = (size_t)T * C * P;
+  ConvLayout L = conv_layout((size_t)T * C, P, B, logn, kernel_width,
+                             n_img < kMaxGroupImages ? n_img : kMaxGroupImages);
+  if (!L.ok) return BLINK_ERR_SIZE;
+  *bytes = L.total;
+  return BLINK_OK;
+}
+
+blink_status blink_image_batch_conv(blink_ctx ctx, const blink_cf32* vis, const uint8_t* flags, const double* uvw_m,
+                                    const double* freq_hz, int T, int C, int P, int B, int grid_n, double pixel_scale,
+                                    int kernel_width, double kernel_beta, int precision, int shift, float* images,
+                                    double* weight_sum, int32_t* n_out, void* workspace, size_t workspace_bytes,
+                                    void* hip_stream) {
+  int logn = 0;
+  blink_status st = check_problem(ctx, vis, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, BLINK_WEIGHT_NATURAL,
+                                  images, workspace, &logn);
+  if (st != BLINK_OK) return st;
+  if (!valid_precision(precision)) return fail(ctx, BLINK_ERR_ARG, "unsupported precision %d", precision);
+  if (!conv_args_ok(kernel_width, kernel_beta, logn))
+    return fail(ctx, BLINK_ERR_ARG, "kernel width %d (1..16, < N/2) or beta %g (0..100) out of range", kernel_width,
+                kernel_beta);
+  const size_t n_tc = (size_t)T * C;
+  if (n_tc == 0) return BLINK_OK;
+  const auto& plan = ctx->plan[logn][BLINK_WEIGHT_NATURAL][precision];
+  const size_t want = plan.group > 0 ? (size_t)plan.group : kMaxGroupImages;
+  size_t Q = largest_fitting_chunk(n_tc, workspace_bytes, [&](size_t q) {
+    return conv_layout(q, P, B, logn, kernel_width, q * P < want ? q * P : want).total;
+  });
+  size_t h_images = Q * P < want ? Q * P : want;
+  if (Q == 0 && conv_layout(1, P, B, logn, kernel_width, 1).total <= workspace_bytes) {
+    Q = 1;
+    h_images = 1;
+  }
+  if (Q == 0)
+    return fail(ctx, BLINK_ERR_SIZE, "workspace of %zu bytes is smaller than one (t,c) pair needs (%zu)",
+                workspace_bytes, conv_layout(1, P, B, logn, kernel_width, 1).total);
+  if (Q * P > (size_t)INT32_MAX) return fail(ctx, BLINK_ERR_SIZE, "batch too large");
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t N = size_t(1) << logn;
+  const int S = blink::conv_strip_width(logn);
+  int log_s = 0;
+  while ((1 << log_s) < S) ++log_s;
+  char* ws = (char*)workspace;
+  ConvLayout L = conv_layout(Q, P, B, logn, kernel_width, h_images);
+  const blink::ConvParams cp{kernel_width, kernel_beta};
+  float* corr = (float*)(ws + L.corr);
+  hipError_t e;
+  {
+    KernelTimer kt(ctx, BLINK_KERNEL_CONV_CORRECTION, s);
+    e = blink::launch_conv_correction(corr, logn, cp, shift != 0, s);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "grid-correction kernel");
+  const int G = (int)h_images;
+  for (size_t tc0 = 0; tc0 < n_tc; tc0 += Q) {
+    const int q = (int)((n_tc - tc0) < Q ? (n_tc - tc0) : Q);
+    blink::BinArgs ba{};
+    ba.uvw = uvw_m;
+    ba.freq = freq_hz;
+    ba.flags = flags;
+    ba.tc0 = (int)tc0;
+    ba.Q = q;
+    ba.C = C;
+    ba.B = B;
+    ba.logn = logn;
+    ba.log_strip = log_s;
+    ba.ku_limit = (int)(N / 2);
+    ba.P = P;
+    ba.pixel_scale = pixel_scale;
+    ba.plc = (int2*)(ws + L.bins.plc);
+    ba.strip_off = (int*)(ws + L.bins.off);
+    ba.n_kept = (int*)(ws + L.bins.kept);
+    ba.occ = (int*)(ws + L.bins.occ);
+    ba.cell_idx = nullptr;
+    ba.n_out = n_out;
+    {
+      KernelTimer kt(ctx, BLINK_KERNEL_BIN, s);
+      e = blink::launch_bin_conv(ba, cp, L.rec_stride, s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "convolutional bin kernel");
+    blink::ColArgs ca{};
+    ca.vis = (const float2*)vis + tc0 * P * B;
+    ca.plc = ba.plc;
+    ca.strip_off = ba.strip_off;
+    ca.Q = q;
+    ca.P = P;
+    ca.B = B;
+    ca.logn = logn;
+    ca.uniform = 0;
+    ca.shift = shift != 0;
+    ca.H = (float2*)(ws + L.H);
+    ca.occ = ba.occ;
+    ca.dft_ops = ctx->dft_ops;
+    ca.rec_stride = L.rec_stride;
+    const int n_img = q * P;
+    blink::RowArgs ra{};
+    ra.H = ca.H;
+    ra.logn = logn;
+    ra.P = P;
+    ra.wmode = blink::kWeightNatural;
+    ra.n_kept = ba.n_kept;
+    ra.occ = ba.occ;
+    ra.weight_sum = weight_sum ? weight_sum + tc0 * P : nullptr;
+    ra.dft_ops = ctx->dft_ops;
+    ra.corr = corr;
+    for (int i0 = 0; i0 < n_img; i0 += G) {
+      const int gi = (n_img - i0) < G ? (n_img - i0) : G;
+      ca.img0 = i0;
+      {
+        KernelTimer kt(ctx, BLINK_KERNEL_GRID_COLFFT, s);
+        e = blink::launch_grid_colfft_conv(ca, gi, cp, precision, ctx->tw[logn], s);
+      }
+      if (e != hipSuccess) return hip_fail(ctx, e, "convolutional grid + column FFT kernel");
       ra.img0 = i0;
       ra.images = images + (tc0 * P + i0) * N * N;
       {
@@ -731,6 +904,7 @@ blink_status run_desc(blink_ctx ctx, const DescCall& c, hipStream_t s) {
   a.strip_stride = c.max_n / 2 + 1;
   a.H = (float2*)(ws + L.H);
   for (int l = 3; l <= 12; ++l) a.tw[l] = ctx->tw[l];
+  a.dft_ops = ctx->dft_ops;
   hipError_t e;
   {
     KernelTimer kt(ctx, BLINK_KERNEL_DESC_PREP, s);

@@ -9,8 +9,9 @@
 // one pass through LDS. Stage s with radix r and span Ns (product of earlier radices) reads
 // element b + m*N/r (b = butterfly, m < r), multiplies by w^(k m) with w = exp(2 pi i/(Ns r)),
 // k = b mod Ns, does an r-point DFT and writes element (b - k) r + k + m Ns. The output is in
-// natural order. Twiddles come from a table tw[j] = exp(+2 pi i j/N) rounded to FP32 from
-// values generated in FP64.
+// natural order. Twiddles are FP32 values rounded from FP64 ones, stored per stage (the
+// twiddle table layout below) so that the lanes of a wave, which differ in k, read different
+// LDS banks.
 //
 // LDS layout of one transform: element e lives at pad(e) = e + e/16, so the stride-16 writes
 // of the first stage spread over the banks; a transform occupies padded_len(N) float2.
@@ -115,6 +116,25 @@ __device__ __forceinline__ void dft(float2* v) {
   else static_assert(RAD == 2 || RAD == 4 || RAD == 8 || RAD == 16, "unsupported radix");
 }
 
+// ---------------------------------------------------------------- twiddle table layout
+// Twiddle table of one size N, by stage (generated in FP64 and rounded to FP32 on the device):
+//   A[17 k + m]      = exp(+2 pi i k m / (16 R1)),  k < 16, m < R1   second stage (span 16)
+//   A[17 k + 16]     = exp(+2 pi i k / 16),         k < 16           16-point DFT entries
+//   B[256 m + k]     = exp(+2 pi i k m / N),        k < 256, m < R2  third stage (span 256), N >= 512
+// with B = A + 272. A row holds 17 values, so the 16 values of k a wave reads for one m fall in
+// distinct banks; a B row is contiguous in k.
+constexpr int kTwRow = 17;
+constexpr int kTwA = 16 * kTwRow;
+__host__ __device__ constexpr int tw_size(int logn) { return kTwA + (logn >= 9 ? (1 << logn) : 0); }
+
+template <int NS>
+__device__ __forceinline__ float2 stage_twiddle(const float2* __restrict__ tw, int k, int m) {
+  static_assert(NS == 16 || NS == 256, "twiddled stages have span 16 or 256");
+  if constexpr (NS == 16) return tw[k * kTwRow + m];
+  else return tw[kTwA + m * 256 + k];
+}
+__device__ __forceinline__ float2 dft16_entry(const float2* __restrict__ tw, int t) { return tw[t * kTwRow + 16]; }
+
 // ---------------------------------------------------------------- plan
 template <int LOGN>
 struct FftPlan {
@@ -139,9 +159,8 @@ __device__ __forceinline__ void stage_compute(float2 (&v)[R], int tid, const flo
     if constexpr (NS > 1) {
       const int b = tid + q * T;
       const int k = b & (NS - 1);
-      constexpr int STRIDE = N / (NS * RAD);
 #pragma unroll
-      for (int m = 1; m < RAD; ++m) v[q * RAD + m] = cmul(v[q * RAD + m], tw[k * m * STRIDE]);
+      for (int m = 1; m < RAD; ++m) v[q * RAD + m] = cmul(v[q * RAD + m], stage_twiddle<NS>(tw, k, m));
     }
     dft<RAD>(&v[q * RAD]);
   }
@@ -154,32 +173,60 @@ __device__ __forceinline__ int stage_out_index(int tid, int q, int m) {
   return (b - k) * RAD + k + m * NS;
 }
 
+// pad(e + c) = pad(e) + c + c/16 whenever c is a multiple of 16, so the addresses of one
+// thread's loads and stores are one computed base plus compile-time offsets where the strides
+// allow it.
+__host__ __device__ constexpr int pad_offset(int c) { return c + c / 16; }
+
 template <int N, int R, int T, int NS, int RAD>
 __device__ __forceinline__ void stage_store_lds(const float2 (&v)[R], float2* buf, int tid) {
   constexpr int Q = R / RAD;
 #pragma unroll
-  for (int q = 0; q < Q; ++q)
+  for (int q = 0; q < Q; ++q) {
+    const int b = tid + q * T;
+    const int k = b & (NS - 1);
+    const int base = (b - k) * RAD + k;
+    if constexpr (NS % 16 == 0) {
+      const int pb = pad_index(base);
 #pragma unroll
-    for (int m = 0; m < RAD; ++m) buf[pad_index(stage_out_index<T, NS, RAD>(tid, q, m))] = v[q * RAD + m];
+      for (int m = 0; m < RAD; ++m) buf[pb + pad_offset(m * NS)] = v[q * RAD + m];
+    } else if constexpr (NS == 1 && RAD == 16) {
+      const int pb = 17 * b;                         // pad(16 b + m) = 17 b + m for m < 16
+#pragma unroll
+      for (int m = 0; m < RAD; ++m) buf[pb + m] = v[q * RAD + m];
+    } else {
+#pragma unroll
+      for (int m = 0; m < RAD; ++m) buf[pad_index(base + m * NS)] = v[q * RAD + m];
+    }
+  }
 }
 
 template <int N, int R, int T, int RAD>
 __device__ __forceinline__ void stage_load_lds(float2 (&v)[R], const float2* buf, int tid) {
   constexpr int Q = R / RAD;
+  constexpr int STEP = N / RAD;
+  if constexpr (STEP % 16 == 0 && T % 16 == 0) {
+    const int pb = pad_index(tid);
 #pragma unroll
-  for (int q = 0; q < Q; ++q)
+    for (int q = 0; q < Q; ++q)
 #pragma unroll
-    for (int m = 0; m < RAD; ++m) v[q * RAD + m] = buf[pad_index(tid + q * T + m * (N / RAD))];
+      for (int m = 0; m < RAD; ++m) v[q * RAD + m] = buf[pb + pad_offset(q * T + m * STEP)];
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int m = 0; m < RAD; ++m) v[q * RAD + m] = buf[pad_index(tid + q * T + m * STEP)];
+  }
 }
 
 // Full inverse FFT of one transform per group of T threads.
 // On entry v[m] holds element tid + m*T (the first stage's input order); `buf` is this
-// transform's padded LDS buffer and `tw` the twiddle table for N (LDS or global). Every thread
-// of the block must call this (it contains block barriers); threads with active == false take
-// part in the barriers only and touch no memory. On return the caller's `sink(e, value)` has
-// been called for every output element e this thread owns (natural order, each element
-// exactly once across the T threads); when the last stage writes back to LDS instead
-// (ToLds = true) the result is in buf at pad(e) and the block is synchronised.
+// transform's padded LDS buffer and `tw` the twiddle table of N in the layout above (LDS or
+// global). Every thread of the block must call this (it contains block barriers); threads with
+// active == false take part in the barriers only and touch no memory. On return the caller's
+// `sink(e, value)` has been called for every output element e this thread owns (natural order,
+// each element exactly once across the T threads); when the last stage writes back to LDS
+// instead (ToLds = true) the result is in buf at pad(e) and the block is synchronised.
 template <int LOGN, bool ToLds, class Sink>
 __device__ __forceinline__ void fft_inverse(float2 (&v)[FftPlan<LOGN>::R], float2* buf,
                                             const float2* __restrict__ tw, int tid, Sink sink,

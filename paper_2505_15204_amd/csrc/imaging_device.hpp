@@ -167,13 +167,15 @@ __device__ __forceinline__ void scatter_strip(const int2* __restrict__ plc, int 
   }
 }
 
-// Uniform weighting: cell mean; returns this thread's occupied-cell count (weighted).
-template <int LOGN, int S, bool PADDED>
+// Uniform weighting: cell mean; returns this thread's occupied-cell count (weighted). NT is the
+// workgroup size (0: read blockDim).
+template <int LOGN, int S, bool PADDED, int NT = 0>
 __device__ __forceinline__ int uniform_divide(float2* sbuf, const unsigned* scnt, int stride, int col_weight0,
                                               int col_weight) {
   constexpr int N = 1 << LOGN;
+  const int nt = NT > 0 ? NT : (int)blockDim.x;
   int occ = 0;
-  for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
+  for (int i = threadIdx.x; i < S * N; i += nt) {
     const int col = i >> LOGN, kv = i & (N - 1);
     const unsigned n = scnt[i];
     if (n) {
@@ -194,6 +196,62 @@ __device__ __forceinline__ void block_add_to_global(int val, int* s_tmp, int* ds
   if (threadIdx.x == 0 && *s_tmp) atomicAdd(dst, *s_tmp);
 }
 
+// ---------------------------------------------------------------- strip store
+// The S transformed columns of a strip (column c at sbuf + c*NP, padded) into rows of the half
+// spectrum: Hi[y][strip*S + c]. With REAL0, column 0 of strip 0 keeps only its real part (the
+// transform of the Hermitian part of column 0; the imaginary slot is the Nyquist column's, empty).
+// Thread t handles column t % S of rows t / S + j * NT / S, so when NT / S is a multiple of 16
+// every address is one base plus compile-time steps.
+template <int LOGN, int S, int NT, bool REAL0 = true>
+__device__ __forceinline__ void store_strip(const float2* sbuf, int strip, float2* __restrict__ Hi) {
+  constexpr int N = 1 << LOGN, NP = padded_len(N), HALF = N / 2;
+  if constexpr (NT % S == 0 && (NT / S) % 16 == 0 && (S * N) % NT == 0) {
+    constexpr int RPI = NT / S, ITER = (S * N) / NT;
+    const int c = (int)threadIdx.x % S, y0 = (int)threadIdx.x / S;
+    const float2* src = sbuf + c * NP + pad_index(y0);
+    float2* dst = Hi + (size_t)y0 * HALF + strip * S + c;
+    const bool real_only = REAL0 && strip == 0 && c == 0;
+#pragma unroll 4
+    for (int j = 0; j < ITER; ++j) {
+      float2 val = src[pad_offset(j * RPI)];
+      if (real_only) val.y = 0.f;
+      dst[(size_t)j * RPI * HALF] = val;
+    }
+  } else {
+    for (int i = threadIdx.x; i < S * N; i += NT) {
+      const int y = i / S, c = i % S;
+      float2 val = sbuf[c * NP + pad_index(y)];
+      if (REAL0 && strip == 0 && c == 0) val.y = 0.f;
+      Hi[(size_t)y * HALF + strip * S + c] = val;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- strip FFT + store
+// The column transforms of a gridded LDS strip (S columns, padded) and their store into Hi; the
+// block is synchronised before the store. REAL0 keeps only the real part of column 0 of strip 0
+// (nearest-cell gridding leaves the Nyquist column empty); without it column 0 carries
+// (column 0) + i (column N/2) as packed by the gridding.
+template <int LOGN, int S, int PREC, int NT, bool REAL0>
+__device__ __forceinline__ void strip_fft_store(float2* sbuf, int strip, float2* __restrict__ Hi,
+                                                const float2* __restrict__ tw, SplitCtx sp) {
+  using P = FftPlan<LOGN>;
+  constexpr int T = P::T, NP = P::NP;
+  constexpr bool SPLIT = PREC != kPrecFp32 && LOGN >= 4;
+  if constexpr (SPLIT) {
+    fft_inverse_split<LOGN, PREC, true, true>(
+        sbuf, S, tw, [&](int c, int e) { return sbuf[c * NP + pad_index(e)]; }, [](int, int, float2) {}, sp);
+  } else {
+    const bool active = (int)threadIdx.x < S * T;
+    const int col = active ? (int)threadIdx.x / T : 0, lt = (int)threadIdx.x % T;
+    float2* cb = sbuf + col * NP;
+    float2 v[P::R];
+    if (active) stage_load_lds<P::N, P::R, T, P::R0>(v, cb, lt);
+    fft_inverse<LOGN, true>(v, cb, tw, lt, [](int, float2) {}, active);
+  }
+  store_strip<LOGN, S, NT, REAL0>(sbuf, strip, Hi);
+}
+
 // ---------------------------------------------------------------- fused grid + column FFT task
 // One strip of S half-spectrum columns of one image: zero the LDS strip, scatter the strip's
 // placements, (uniform) divide by counts and add the strip's occupied cells (column 0 once,
@@ -202,50 +260,35 @@ __device__ __forceinline__ void block_add_to_global(int val, int* s_tmp, int* ds
 // real part is the transform of the column's Hermitian part, and the Nyquist column is empty.
 // Threads beyond S*T of the workgroup only join the barriers. `tw` is the twiddle table for N.
 // PREC selects the FP32 butterflies or the split matrix-core form (split_fft.hpp), which needs a
-// workgroup of whole waves; `s_max` is that form's LDS word for the strip's largest magnitude.
-template <int LOGN, int S, bool UNIFORM, int PREC = kPrecFp32>
+// workgroup of whole waves; `sp` holds that form's LDS word for the strip's largest magnitude and
+// the DFT operand table.
+// NT is the workgroup size (a compile-time loop stride).
+template <int LOGN, int S, bool UNIFORM, int PREC, int NT>
 __device__ __forceinline__ void grid_colfft_task(const float2* __restrict__ V, const int2* __restrict__ plc, int o0,
                                                  int o1, int strip, bool shift, float2* __restrict__ Hi,
                                                  int* occ_img, const float2* __restrict__ tw, float2* sbuf,
-                                                 unsigned* scnt, int* s_tmp, unsigned* s_max = nullptr) {
+                                                 unsigned* scnt, int* s_tmp, SplitCtx sp = {}) {
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, T = P::T, NP = P::NP;
   constexpr bool SPLIT = PREC != kPrecFp32 && LOGN >= 4;
-  for (int i = threadIdx.x; i < S * NP; i += blockDim.x) sbuf[i] = make_float2(0.f, 0.f);
+  static_assert(NT >= S * T, "one thread per FFT thread at least");
+#pragma unroll 4
+  for (int i = threadIdx.x; i < S * NP; i += NT) sbuf[i] = make_float2(0.f, 0.f);
   if constexpr (UNIFORM)
-    for (int i = threadIdx.x; i < S * N; i += blockDim.x) scnt[i] = 0u;
+    for (int i = threadIdx.x; i < S * N; i += NT) scnt[i] = 0u;
   if (threadIdx.x == 0) {
     *s_tmp = 0;
-    if constexpr (SPLIT) *s_max = 0u;
+    if constexpr (SPLIT) *sp.s_max = 0u;
   }
   __syncthreads();
   scatter_strip<LOGN, S, true, UNIFORM>(plc, o0, o1, V, strip, NP, shift, sbuf, scnt);
   __syncthreads();
   if constexpr (UNIFORM) {
-    int occ = uniform_divide<LOGN, S, true>(sbuf, scnt, NP, strip == 0 ? 1 : 2, 2);
+    int occ = uniform_divide<LOGN, S, true, NT>(sbuf, scnt, NP, strip == 0 ? 1 : 2, 2);
     block_add_to_global(occ, s_tmp, occ_img);
     __syncthreads();
   }
-  if constexpr (SPLIT) {
-    fft_inverse_split<LOGN, PREC, true>(
-        sbuf, S, tw, [&](int c, int e) { return sbuf[c * NP + pad_index(e)]; }, [](int, int, float2) {}, s_max);
-  } else {
-    const bool active = (int)threadIdx.x < S * T;
-    const int col = active ? (int)threadIdx.x / T : 0, lt = (int)threadIdx.x % T;
-    float2* cb = sbuf + col * NP;
-    float2 v[P::R];
-    if (active) {
-#pragma unroll
-      for (int m = 0; m < P::R; ++m) v[m] = cb[pad_index(lt + m * T)];
-    }
-    fft_inverse<LOGN, true>(v, cb, tw, lt, [](int, float2) {}, active);
-  }
-  for (int i = threadIdx.x; i < S * N; i += blockDim.x) {
-    const int y = i / S, c = i % S;
-    float2 val = sbuf[c * NP + pad_index(y)];
-    if (strip == 0 && c == 0) val.y = 0.f;
-    Hi[(size_t)y * (N / 2) + strip * S + c] = val;
-  }
+  strip_fft_store<LOGN, S, PREC, NT, true>(sbuf, strip, Hi, tw, sp);
 }
 
 // ---------------------------------------------------------------- row task
@@ -254,8 +297,9 @@ __device__ __forceinline__ void grid_colfft_task(const float2* __restrict__ V, c
 // half row: Hf[0] = Re H[0], Hf[N/2] = Im H[0], Hf[e] = H[e] (0 < e < N/2), Hf[e] = conj H[N-e].
 // The inverse FFT of Z is I1 + i I2 with both rows real; they are scaled by `scale` and stored.
 // The caller makes `tw` visible to the whole workgroup before the FFT's first barrier. With a
-// split PREC the workgroup is whole waves and `s_max` is that form's LDS word (as for the column
-// task, consecutive calls are separated by a workgroup barrier).
+// split PREC the workgroup is whole waves and `sp` is that form's context (as for the column
+// task, consecutive calls are separated by a workgroup barrier). A non-null `corr` (N values)
+// multiplies pixel (y, x) by corr[y] corr[x] (the convolutional path's grid correction).
 __device__ __forceinline__ float2 hermitian_pair(const float2* __restrict__ h1, const float2* __restrict__ h2, int e,
                                                  int N) {
   const int HALF = N / 2;
@@ -269,22 +313,33 @@ __device__ __forceinline__ float2 hermitian_pair(const float2* __restrict__ h1, 
 
 template <int LOGN, int TPB, int PREC = kPrecFp32>
 __device__ __forceinline__ void row_task(const float2* __restrict__ H, int rowblk, float scale, float* __restrict__ out,
-                                         const float2* __restrict__ tw, float2* sbuf, unsigned* s_max = nullptr) {
+                                         const float2* __restrict__ tw, float2* sbuf, SplitCtx sp = {},
+                                         const float* __restrict__ corr = nullptr) {
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, T = P::T, NP = P::NP, HALF = N / 2;
   if constexpr (PREC != kPrecFp32 && LOGN >= 4) {
-    if (threadIdx.x == 0) *s_max = 0u;
+    if (threadIdx.x == 0) *sp.s_max = 0u;
     __syncthreads();   // the caller's twiddle table is visible
     const float2* hb = H + (size_t)(2 * rowblk * TPB) * HALF;
     float* ob = out + (size_t)(2 * rowblk * TPB) * N;
-    fft_inverse_split<LOGN, PREC, false>(
-        sbuf, TPB, tw, [&](int c, int e) { return hermitian_pair(hb + (size_t)(2 * c) * HALF, hb + (size_t)(2 * c + 1) * HALF, e, N); },
-        [&](int c, int e, float2 z) {
-          float* o1 = ob + (size_t)(2 * c) * N;
-          o1[e] = z.x * scale;
-          o1[N + e] = z.y * scale;
-        },
-        s_max);
+    auto load = [&](int c, int e) {
+      return hermitian_pair(hb + (size_t)(2 * c) * HALF, hb + (size_t)(2 * c + 1) * HALF, e, N);
+    };
+    if (corr) {
+      fft_inverse_split<LOGN, PREC, false, false>(sbuf, TPB, tw, load, [&](int c, int e, float2 z) {
+        const int y1 = 2 * (rowblk * TPB + c);
+        float* o1 = ob + (size_t)(2 * c) * N;
+        const float cx = corr[e] * scale;
+        o1[e] = z.x * cx * corr[y1];
+        o1[N + e] = z.y * cx * corr[y1 + 1];
+      }, sp);
+    } else {
+      fft_inverse_split<LOGN, PREC, false, false>(sbuf, TPB, tw, load, [&](int c, int e, float2 z) {
+        float* o1 = ob + (size_t)(2 * c) * N;
+        o1[e] = z.x * scale;
+        o1[N + e] = z.y * scale;
+      }, sp);
+    }
   } else {
     const int j = (int)threadIdx.x / T, lt = (int)threadIdx.x % T;
     const bool active = j < TPB;
@@ -299,10 +354,20 @@ __device__ __forceinline__ void row_task(const float2* __restrict__ H, int rowbl
     __syncthreads();   // the caller's twiddle table is visible
     float* o1 = out + (size_t)(2 * r) * N;
     float* o2 = o1 + N;
-    fft_inverse<LOGN, false>(v, sbuf + (active ? j : 0) * NP, tw, lt, [&](int e, float2 z) {
-      o1[e] = z.x * scale;
-      o2[e] = z.y * scale;
-    }, active);
+    float2* buf = sbuf + (active ? j : 0) * NP;
+    if (corr) {
+      const float s1 = scale * corr[2 * r], s2 = scale * corr[2 * r + 1];
+      fft_inverse<LOGN, false>(v, buf, tw, lt, [&](int e, float2 z) {
+        const float cx = corr[e];
+        o1[e] = z.x * s1 * cx;
+        o2[e] = z.y * s2 * cx;
+      }, active);
+    } else {
+      fft_inverse<LOGN, false>(v, buf, tw, lt, [&](int e, float2 z) {
+        o1[e] = z.x * scale;
+        o2[e] = z.y * scale;
+      }, active);
+    }
   }
 }
 

@@ -1,6 +1,6 @@
 // kernels.hip — gfx950 kernels of the batched dirty-imaging path.
 //
-//   k_twiddles       FP64 sincospi -> FP32 twiddle table
+//   k_twiddles       FP64 sincospi -> FP32 stage-ordered twiddle table
 //   k_bin            cell indices (FP64 product + rint), flags, out-of-grid drop, counting sort
 //                    of the placements into column strips (Section 6.2.4 gridding, one
 //                    workgroup per (time, channel), shared by the polarisations)
@@ -9,6 +9,8 @@
 //   k_dense_colfft   Hermitian part of a dense grid -> inverse FFT along v -> H
 //   k_row_c2r        two H rows -> Hermitian-extended inverse FFT along u -> two image rows,
 //                    scaled by 1/W of the image (computed from the kept count or occupancy)
+//   k_bin_conv, k_grid_colfft_conv, k_conv_correction
+//                    the convolutional-gridding variant (conv_device.hpp)
 //
 // The dirty image is I = Re(IDFT2(G)) / W (Section 4, Eq. 5). The shift of Section 6.2.4 is
 // folded into the input as the modulation (-1)^(ku + kv), which for even N moves the phase
@@ -22,16 +24,52 @@
 namespace blink {
 
 // ---------------------------------------------------------------- twiddles
-__global__ void k_twiddles(float2* tw, int n) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  double s, c;
-  sincospi(2.0 * (double)j / (double)n, &s, &c);   // exact argument: 2j/n is a dyadic rational
-  tw[j] = make_float2((float)c, (float)s);
+// The stage-ordered table of one size N (fft_device.hpp): FP64 sincospi of an exact dyadic
+// argument, rounded to FP32. Unused slots of A (m >= R1) hold zero.
+__global__ void k_twiddles(float2* tw, int logn) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= tw_size(logn)) return;
+  const int n = 1 << logn;
+  const int r1 = logn <= 4 ? 1 : (logn >= 8 ? 16 : n / 16);
+  long num = 0, den = 1;
+  bool used = true;
+  if (j < kTwA) {
+    const int k = j / kTwRow, m = j % kTwRow;
+    if (m == 16) {
+      num = k;
+      den = 16;
+    } else {
+      used = m < r1;
+      num = (long)k * m;
+      den = 16L * r1;
+    }
+  } else {
+    const int m = (j - kTwA) / 256, k = (j - kTwA) % 256;
+    num = (long)k * m;
+    den = n;
+  }
+  double s = 0.0, c = 0.0;
+  sincospi(2.0 * (double)(num % den) / (double)den, &s, &c);
+  tw[j] = used ? make_float2((float)c, (float)s) : make_float2(0.f, 0.f);
 }
 
-hipError_t launch_twiddles(float2* tw, int n, hipStream_t s) {
-  k_twiddles<<<(n + 255) / 256, 256, 0, s>>>(tw, n);
+int twiddle_table_size(int logn) { return tw_size(logn); }
+
+// ---------------------------------------------------------------- split-form DFT operands
+__global__ void k_dft_operands(const float2* __restrict__ tw, uint4* ops) {
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x < 64) make_dft_operands<kPrecSplitF16>(tw, ops, lane);
+  else if (threadIdx.x < 128) make_dft_operands<kPrecSplitBf16>(tw, ops, lane);
+}
+
+hipError_t launch_dft_operands(const float2* tw, uint4* ops, hipStream_t s) {
+  k_dft_operands<<<1, 128, 0, s>>>(tw, ops);
+  return hipGetLastError();
+}
+
+hipError_t launch_twiddles(float2* tw, int logn, hipStream_t s) {
+  const int n = tw_size(logn);
+  k_twiddles<<<(n + 255) / 256, 256, 0, s>>>(tw, logn);
   return hipGetLastError();
 }
 
@@ -55,6 +93,68 @@ hipError_t launch_bin(const BinArgs& a, hipStream_t s) {
   if (a.Q <= 0) return hipSuccess;
   k_bin<<<a.Q, kBinThreads, 0, s>>>(a);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- convolutional binning
+__global__ __launch_bounds__(kBinThreads) void k_bin_conv(BinArgs a, ConvSpec cs, int rec_stride) {
+  __shared__ BinShared sh;
+  const int tcl = blockIdx.x;
+  const long tc = (long)a.tc0 + tcl;
+  const int t = (int)(tc / a.C), c = (int)(tc % a.C);
+  const int N = 1 << a.logn;
+  const int nstrips = (N / 2) >> a.log_strip;
+  const double k = (a.freq[c] / kSpeedOfLight) * ((double)N * a.pixel_scale);
+  bin_visibilities_conv(a.uvw + (size_t)t * a.B * 3, a.flags ? a.flags + (size_t)tc * a.B : nullptr, a.B, k, a.logn,
+                        a.log_strip, cs, reinterpret_cast<ConvRec*>(a.plc) + (size_t)tcl * rec_stride,
+                        a.strip_off + (size_t)tcl * (nstrips + 1), a.n_kept + tcl, a.n_out ? a.n_out + tc : nullptr,
+                        sh);
+}
+
+int conv_records_per_pair(int B, int width, int min_strip) {
+  return 2 * B * ((width + min_strip - 1) / min_strip + 2);
+}
+
+hipError_t launch_bin_conv(const BinArgs& a, ConvParams cp, int rec_stride, hipStream_t s) {
+  if (a.Q <= 0) return hipSuccess;
+  k_bin_conv<<<a.Q, kBinThreads, 0, s>>>(a, ConvSpec{cp.width, (float)cp.beta}, rec_stride);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_conv_correction(float* corr, int n, int width, double beta, int shift) {
+  __shared__ double s_part[256];
+  conv_correction_entry(corr, n, blockIdx.x, width, beta, shift, s_part);
+}
+
+hipError_t launch_conv_correction(float* corr, int logn, ConvParams cp, int shift, hipStream_t s) {
+  const int n = 1 << logn;
+  k_conv_correction<<<n, 256, 0, s>>>(corr, n, cp.width, cp.beta, shift);
+  return hipGetLastError();
+}
+
+template <int LOGN>
+struct ConvStrip {
+  static hipError_t run(int* out) {
+    *out = ColSmax<LOGN, false>::value;
+    return hipSuccess;
+  }
+};
+
+int conv_strip_width(int logn) {
+  int s = 0;
+  return by_logn<ConvStrip>(logn, &s) == hipSuccess ? s : 0;
+}
+
+hipError_t launch_grid_colfft_conv(const ColArgs& a, int n_img, ConvParams cp, int prec, const float2* tw,
+                                   hipStream_t s) {
+  const float beta = (float)cp.beta;
+  switch (prec) {
+    case BLINK_PREC_FP32: return PrecLaunch<BLINK_PREC_FP32>::grid_colfft_conv(a, n_img, cp.width, beta, tw, s);
+    case BLINK_PREC_SPLIT_F16:
+      return PrecLaunch<BLINK_PREC_SPLIT_F16>::grid_colfft_conv(a, n_img, cp.width, beta, tw, s);
+    case BLINK_PREC_SPLIT_BF16:
+      return PrecLaunch<BLINK_PREC_SPLIT_BF16>::grid_colfft_conv(a, n_img, cp.width, beta, tw, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // ---------------------------------------------------------------- full grid (blink_grid)
@@ -188,12 +288,13 @@ hipError_t launch_grid_colfft(const ColArgs& a, int n_img, int strip, int prec, 
 }
 
 hipError_t launch_dense_colfft(const float2* grids, int n_img, int logn, int shift, int prec, float2* H,
-                               const float2* tw, hipStream_t s) {
+                               const float2* tw, const uint4* ops, hipStream_t s) {
   switch (prec) {
-    case BLINK_PREC_FP32: return PrecLaunch<BLINK_PREC_FP32>::dense_colfft(grids, n_img, logn, shift, H, tw, s);
-    case BLINK_PREC_SPLIT_F16: return PrecLaunch<BLINK_PREC_SPLIT_F16>::dense_colfft(grids, n_img, logn, shift, H, tw, s);
+    case BLINK_PREC_FP32: return PrecLaunch<BLINK_PREC_FP32>::dense_colfft(grids, n_img, logn, shift, H, tw, ops, s);
+    case BLINK_PREC_SPLIT_F16:
+      return PrecLaunch<BLINK_PREC_SPLIT_F16>::dense_colfft(grids, n_img, logn, shift, H, tw, ops, s);
     case BLINK_PREC_SPLIT_BF16:
-      return PrecLaunch<BLINK_PREC_SPLIT_BF16>::dense_colfft(grids, n_img, logn, shift, H, tw, s);
+      return PrecLaunch<BLINK_PREC_SPLIT_BF16>::dense_colfft(grids, n_img, logn, shift, H, tw, ops, s);
     default: return hipErrorInvalidValue;
   }
 }

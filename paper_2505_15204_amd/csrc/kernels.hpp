@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "conv_device.hpp"
 #include "imaging_device.hpp"
 #include "launch.hpp"
 
@@ -18,7 +19,7 @@ struct ColSmax {
   using P = FftPlan<LOGN>;
   static constexpr int N = P::N;
   static constexpr int per_col = P::NP * 8 + (UNIFORM ? N * 4 : 0);
-  static constexpr int avail = kLdsBytes - N * 8 - 1024;
+  static constexpr int avail = kLdsBytes - tw_size(LOGN) * 8 - 1024;
   static constexpr int value = pow2_floor(cmin(cmin(N / 2, 1024 / P::T), avail / per_col));
 };
 
@@ -37,7 +38,7 @@ struct GridCfg {
 template <int LOGN, int TPB>
 struct RowFits {
   static constexpr bool value = TPB >= 1 && TPB * FftPlan<LOGN>::T <= 1024 && TPB <= (1 << LOGN) / 2 &&
-                                TPB * FftPlan<LOGN>::NP * 8 + (1 << LOGN) * 8 <= kLdsBytes;
+                                TPB * FftPlan<LOGN>::NP * 8 + tw_size(LOGN) * 8 <= kLdsBytes;
 };
 
 template <int LOGN>
@@ -57,8 +58,9 @@ __global__ __launch_bounds__(fft_block(S * FftPlan<LOGN>::T, PREC)) void k_grid_
                                                                                         const float2* __restrict__ twg) {
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, NP = P::NP;
+  constexpr int NT = fft_block(S * FftPlan<LOGN>::T, PREC), TW = tw_size(LOGN);
   __shared__ float2 sbuf[S * NP];
-  __shared__ float2 stw[N];
+  __shared__ float2 stw[TW];
   __shared__ unsigned scnt[UNIFORM ? S * N : 1];
   __shared__ int s_tmp;
   __shared__ unsigned s_max;
@@ -66,26 +68,49 @@ __global__ __launch_bounds__(fft_block(S * FftPlan<LOGN>::T, PREC)) void k_grid_
   const int slot = blockIdx.x, img = a.img0 + slot, strip = blockIdx.y;
   const int tcl = img / a.P;
   const int nstrips = (N / 2) / S;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = twg[i];   // visible after the task's first barrier
+  for (int i = threadIdx.x; i < TW; i += NT) stw[i] = twg[i];   // visible after the task's first barrier
   const int* so = a.strip_off + (size_t)tcl * (nstrips + 1);
-  grid_colfft_task<LOGN, S, UNIFORM, PREC>(a.vis + (size_t)img * a.B, a.plc + (size_t)tcl * 2 * a.B, so[strip],
+  grid_colfft_task<LOGN, S, UNIFORM, PREC, NT>(a.vis + (size_t)img * a.B, a.plc + (size_t)tcl * 2 * a.B, so[strip],
                                            so[strip + 1], strip, a.shift != 0, a.H + (size_t)slot * N * (N / 2),
-                                           a.occ + img, stw, sbuf, scnt, &s_tmp, &s_max);
+                                           a.occ + img, stw, sbuf, scnt, &s_tmp, SplitCtx{&s_max, a.dft_ops});
+}
+
+// ---------------------------------------------------------------- fused conv gridding + column FFT
+template <int LOGN, int S, int PREC>
+__global__ __launch_bounds__(fft_block(S * FftPlan<LOGN>::T, PREC)) void k_grid_colfft_conv(
+    ColArgs a, ConvSpec cs, const float2* __restrict__ twg) {
+  using P = FftPlan<LOGN>;
+  constexpr int N = P::N, NP = P::NP;
+  constexpr int NT = fft_block(S * FftPlan<LOGN>::T, PREC), TW = tw_size(LOGN);
+  __shared__ float2 sbuf[S * NP];
+  __shared__ float2 stw[TW];
+  __shared__ unsigned s_max;
+  const int slot = blockIdx.x, img = a.img0 + slot, strip = blockIdx.y;
+  const int tcl = img / a.P;
+  const int nstrips = (N / 2) / S;
+  for (int i = threadIdx.x; i < TW; i += NT) stw[i] = twg[i];   // visible after the task's first barrier
+  const int* so = a.strip_off + (size_t)tcl * (nstrips + 1);
+  const ConvRec* rec = reinterpret_cast<const ConvRec*>(a.plc) + (size_t)tcl * a.rec_stride;
+  grid_colfft_conv_task<LOGN, S, PREC, NT>(a.vis + (size_t)img * a.B, rec, so[strip], so[strip + 1], strip,
+                                           a.shift != 0, cs, a.H + (size_t)slot * N * (N / 2), stw, sbuf,
+                                           SplitCtx{&s_max, a.dft_ops});
 }
 
 // ---------------------------------------------------------------- dense grid column FFT
 template <int LOGN, int PREC>
 __global__ __launch_bounds__(fft_block(ColSmax<LOGN, false>::value * FftPlan<LOGN>::T, PREC)) void k_dense_colfft(
-    const float2* __restrict__ grids, int shift, float2* __restrict__ H, const float2* __restrict__ twg) {
+    const float2* __restrict__ grids, int shift, float2* __restrict__ H, const float2* __restrict__ twg,
+    const uint4* __restrict__ ops) {
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, T = P::T, S = ColSmax<LOGN, false>::value, NP = P::NP, mask = N - 1;
+  constexpr int TW = tw_size(LOGN);
   constexpr bool SPLIT = PREC != kPrecFp32 && LOGN >= 4;
   __shared__ float2 sbuf[S * NP];
-  __shared__ float2 stw[N];
+  __shared__ float2 stw[TW];
   __shared__ unsigned s_max;
   const int img = blockIdx.x, strip = blockIdx.y;
   const float2* G = grids + (size_t)img * N * N;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = twg[i];
+  for (int i = threadIdx.x; i < TW; i += blockDim.x) stw[i] = twg[i];
   if (threadIdx.x == 0) s_max = 0u;
   // Hermitian part Gh[kv][ku] = (G[kv][ku] + conj G[-kv][-ku]) / 2; column 0 packs
   // Gh[.][0] + i Gh[.][N/2], whose transforms are both real.
@@ -109,17 +134,15 @@ __global__ __launch_bounds__(fft_block(ColSmax<LOGN, false>::value * FftPlan<LOG
   }
   __syncthreads();
   if constexpr (SPLIT) {
-    fft_inverse_split<LOGN, PREC, true>(
-        sbuf, S, stw, [&](int c, int e) { return sbuf[c * NP + pad_index(e)]; }, [](int, int, float2) {}, &s_max);
+    fft_inverse_split<LOGN, PREC, true, true>(
+        sbuf, S, stw, [&](int c, int e) { return sbuf[c * NP + pad_index(e)]; }, [](int, int, float2) {},
+        SplitCtx{&s_max, ops});
   } else {
     const bool active = (int)threadIdx.x < S * T;
     const int col = active ? (int)threadIdx.x / T : 0, lt = (int)threadIdx.x % T;
     float2* cb = sbuf + col * NP;
     float2 v[P::R];
-    if (active) {
-#pragma unroll
-      for (int m = 0; m < P::R; ++m) v[m] = cb[pad_index(lt + m * T)];
-    }
+    if (active) stage_load_lds<N, P::R, T, P::R0>(v, cb, lt);
     fft_inverse<LOGN, true>(v, cb, stw, lt, [](int, float2) {}, active);
   }
   float2* Hi = H + (size_t)img * N * (N / 2);
@@ -145,15 +168,16 @@ __global__ __launch_bounds__(fft_block(TPB * FftPlan<LOGN>::T, PREC)) void k_row
                                                                                       const float2* __restrict__ twg) {
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, NP = P::NP;
+  constexpr int NT = fft_block(TPB * FftPlan<LOGN>::T, PREC), TW = tw_size(LOGN);
   __shared__ float2 sbuf[TPB * NP];
-  __shared__ float2 stw[N];
+  __shared__ float2 stw[TW];
   __shared__ unsigned s_max;
   const int slot = blockIdx.x, img = a.img0 + slot;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = twg[i];   // visible after row_task's barrier
+  for (int i = threadIdx.x; i < TW; i += NT) stw[i] = twg[i];   // visible after row_task's barrier
   const double W = image_weight(a, img);
   if (a.weight_sum && blockIdx.y == 0 && threadIdx.x == 0) a.weight_sum[img] = W;
   row_task<LOGN, TPB, PREC>(a.H + (size_t)slot * N * (N / 2), blockIdx.y, inverse_weight(W),
-                            a.images + (size_t)slot * N * N, stw, sbuf, &s_max);
+                            a.images + (size_t)slot * N * N, stw, sbuf, SplitCtx{&s_max, a.dft_ops}, a.corr);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -206,12 +230,23 @@ struct ForPrec {
   };
 
   template <int LOGN>
+  struct ConvL {
+    static hipError_t run(const ColArgs* a, int n_img, ConvSpec cs, const float2* tw, hipStream_t s) {
+      constexpr int S = ColSmax<LOGN, false>::value;
+      dim3 grid(n_img, ((1 << LOGN) / 2) / S);
+      k_grid_colfft_conv<LOGN, S, PREC><<<grid, fft_block(S * FftPlan<LOGN>::T, PREC), 0, s>>>(*a, cs, tw);
+      return hipGetLastError();
+    }
+  };
+
+  template <int LOGN>
   struct DenseL {
-    static hipError_t run(const float2* g, int n_img, int shift, float2* H, const float2* tw, hipStream_t s) {
+    static hipError_t run(const float2* g, int n_img, int shift, float2* H, const float2* tw, const uint4* ops,
+                          hipStream_t s) {
       constexpr int N = 1 << LOGN;
       constexpr int S = ColSmax<LOGN, false>::value;
       dim3 grid(n_img, (N / 2) / S);
-      k_dense_colfft<LOGN, PREC><<<grid, fft_block(S * FftPlan<LOGN>::T, PREC), 0, s>>>(g, shift, H, tw);
+      k_dense_colfft<LOGN, PREC><<<grid, fft_block(S * FftPlan<LOGN>::T, PREC), 0, s>>>(g, shift, H, tw, ops);
       return hipGetLastError();
     }
   };
@@ -250,13 +285,17 @@ struct ForPrec {
     return by_logn<ColL>(a.logn, &a, n_img, strip, tw, s);
   }
   static hipError_t dense_colfft(const float2* grids, int n_img, int logn, int shift, float2* H, const float2* tw,
-                                 hipStream_t s) {
+                                 const uint4* ops, hipStream_t s) {
     if (n_img <= 0) return hipSuccess;
-    return by_logn<DenseL>(logn, grids, n_img, shift, H, tw, s);
+    return by_logn<DenseL>(logn, grids, n_img, shift, H, tw, ops, s);
   }
   static hipError_t row_c2r(const RowArgs& a, int n_img, int tpb, const float2* tw, hipStream_t s) {
     if (n_img <= 0) return hipSuccess;
     return by_logn<RowL>(a.logn, &a, n_img, tpb, tw, s);
+  }
+  static hipError_t grid_colfft_conv(const ColArgs& a, int n_img, ConvSpec cs, const float2* tw, hipStream_t s) {
+    if (n_img <= 0) return hipSuccess;
+    return by_logn<ConvL>(a.logn, &a, n_img, cs, tw, s);
   }
 };
 
@@ -266,12 +305,17 @@ hipError_t PrecLaunch<PREC>::grid_colfft(const ColArgs& a, int n_img, int strip,
 }
 template <int PREC>
 hipError_t PrecLaunch<PREC>::dense_colfft(const float2* grids, int n_img, int logn, int shift, float2* H,
-                                          const float2* tw, hipStream_t s) {
-  return ForPrec<PREC>::dense_colfft(grids, n_img, logn, shift, H, tw, s);
+                                          const float2* tw, const uint4* ops, hipStream_t s) {
+  return ForPrec<PREC>::dense_colfft(grids, n_img, logn, shift, H, tw, ops, s);
 }
 template <int PREC>
 hipError_t PrecLaunch<PREC>::row_c2r(const RowArgs& a, int n_img, int tpb, const float2* tw, hipStream_t s) {
   return ForPrec<PREC>::row_c2r(a, n_img, tpb, tw, s);
+}
+template <int PREC>
+hipError_t PrecLaunch<PREC>::grid_colfft_conv(const ColArgs& a, int n_img, int width, float beta, const float2* tw,
+                                              hipStream_t s) {
+  return ForPrec<PREC>::grid_colfft_conv(a, n_img, ConvSpec{width, beta}, tw, s);
 }
 
 static_assert(kPrecFp32 == BLINK_PREC_FP32 && kPrecSplitF16 == BLINK_PREC_SPLIT_F16 &&

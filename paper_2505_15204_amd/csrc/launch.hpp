@@ -14,8 +14,13 @@ int col_strip_options(int logn, bool uniform, int* out);   // columns per workgr
 int row_block_options(int logn, int* out);                 // row-pair transforms per workgroup
 int grid_strip_width(int logn);                            // full-grid gridding kernel
 
-// FP32 twiddle table exp(+2 pi i j / N), j < N, generated in FP64 on the device.
-hipError_t launch_twiddles(float2* tw, int n, hipStream_t s);
+// FP32 stage-ordered twiddle table of N = 2^logn (tw_size(logn) float2, layout in
+// fft_device.hpp), generated in FP64 on the device.
+hipError_t launch_twiddles(float2* tw, int logn, hipStream_t s);
+int twiddle_table_size(int logn);   // float2 elements
+// The split forms' DFT operand table (uint4 [2][64][4]) from the twiddle table of any N.
+hipError_t launch_dft_operands(const float2* tw, uint4* ops, hipStream_t s);
+constexpr int kDftOpsCount = 2 * 64 * 4;   // uint4 elements
 
 // Cell indices and strip-binned placement lists, one workgroup per (time, channel) pair.
 // Pairs tc0 .. tc0+Q-1 of the [T][C] batch. Placements with column >= ku_limit are dropped
@@ -56,13 +61,15 @@ struct ColArgs {
   int Q, P, B, logn, uniform, shift, img0;
   float2* H;                // [n_img][N][N/2]
   int* occ;                 // [Q][P]
+  const uint4* dft_ops;     // DFT operand table of the split forms
+  int rec_stride;           // convolutional path: records per (t,c) pair (plc holds ConvRec)
 };
 // `prec` selects the FFT form: BLINK_PREC_FP32 or a split matrix-core precision.
 hipError_t launch_grid_colfft(const ColArgs& a, int n_img, int strip, int prec, const float2* tw, hipStream_t s);
 
 // Column FFT of the Hermitian part of dense grids into H (blink_ifft2d).
 hipError_t launch_dense_colfft(const float2* grids, int n_img, int logn, int shift, int prec, float2* H,
-                               const float2* tw, hipStream_t s);
+                               const float2* tw, const uint4* dft_ops, hipStream_t s);
 
 // Per-image 1/W (and W as double) from kept counts (natural) or occupancy (uniform).
 hipError_t launch_image_weights(const int* n_kept, const int* occ, int uniform, int P, int img0, int n_img,
@@ -80,8 +87,26 @@ struct RowArgs {
   const int* n_kept;        // [Q]
   const int* occ;           // [Q][P]
   double* weight_sum;       // chunk base or null
+  const uint4* dft_ops;     // DFT operand table of the split forms
+  const float* corr;        // grid correction 1/c per pixel index [N], or null
 };
 hipError_t launch_row_c2r(const RowArgs& a, int n_img, int tpb, int prec, const float2* tw, hipStream_t s);
+
+// ---------------------------------------------------------------- convolutional gridding
+// Separable exponential-of-semicircle kernel of `width` cells (conv_device.hpp).
+struct ConvParams {
+  int width;
+  double beta;
+};
+// Records per (t,c) pair the convolutional binning may write for strips of width >= min_strip.
+int conv_records_per_pair(int B, int width, int min_strip);
+hipError_t launch_bin_conv(const BinArgs& a, ConvParams cp, int rec_stride, hipStream_t s);
+// Fused convolutional gridding + column FFT (strip width: the largest compiled for natural weighting).
+hipError_t launch_grid_colfft_conv(const ColArgs& a, int n_img, ConvParams cp, int prec, const float2* tw,
+                                   hipStream_t s);
+int conv_strip_width(int logn);
+// corr[x] = 1 / c(X/N) for x < N (FP64 quadrature, stored as FP32).
+hipError_t launch_conv_correction(float* corr, int logn, ConvParams cp, int shift, hipStream_t s);
 
 // The same three launchers for one precision form; FP32 is built in kernels.hip, each split
 // precision in its own object from split.hip.
@@ -89,8 +114,10 @@ template <int PREC>
 struct PrecLaunch {
   static hipError_t grid_colfft(const ColArgs& a, int n_img, int strip, const float2* tw, hipStream_t s);
   static hipError_t dense_colfft(const float2* grids, int n_img, int logn, int shift, float2* H, const float2* tw,
-                                 hipStream_t s);
+                                 const uint4* dft_ops, hipStream_t s);
   static hipError_t row_c2r(const RowArgs& a, int n_img, int tpb, const float2* tw, hipStream_t s);
+  static hipError_t grid_colfft_conv(const ColArgs& a, int n_img, int width, float beta, const float2* tw,
+                                     hipStream_t s);
 };
 extern template struct PrecLaunch<BLINK_PREC_FP32>;
 extern template struct PrecLaunch<BLINK_PREC_SPLIT_F16>;
@@ -121,6 +148,7 @@ struct DescArgs {
   int strip_stride;
   float2* H;                       // [workgroups][max_n * max_n / 2]
   const float2* tw[13];            // twiddle tables per log2 N
+  const uint4* dft_ops;            // DFT operand table of the split forms
 };
 hipError_t launch_desc_prep(const DescArgs& a, hipStream_t s);
 hipError_t launch_persistent(const DescArgs& a, int workgroups, int prec, hipStream_t s);

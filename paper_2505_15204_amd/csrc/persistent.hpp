@@ -74,7 +74,7 @@ struct Log2<1> {
 
 template <int LOGN, int BLOCK, bool UNIFORM, int PREC>
 __device__ __noinline__ void image_job(ImageJob j, const float2* __restrict__ tw, float2* sbuf, unsigned* scnt,
-                                       int* s_int, unsigned* s_max) {
+                                       int* s_int, SplitCtx sp) {
   constexpr int N = 1 << LOGN;
   constexpr int S = desc_cols(LOGN, BLOCK);
   constexpr int NBLK = (N / 2) / S;         // column strips, and row blocks of S row pairs
@@ -88,15 +88,15 @@ __device__ __noinline__ void image_job(ImageJob j, const float2* __restrict__ tw
   if (threadIdx.x == 0) *s_occ = 0;
   __syncthreads();                          // placement list and offsets complete; binning scratch free
   for (int strip = 0; strip < NBLK; ++strip) {
-    grid_colfft_task<LOGN, S, UNIFORM, PREC>(j.V, j.plc, j.off[strip], j.off[strip + 1], strip, j.shift != 0, j.H,
-                                             s_occ, tw, sbuf, scnt, s_tmp, s_max);
+    grid_colfft_task<LOGN, S, UNIFORM, PREC, BLOCK>(j.V, j.plc, j.off[strip], j.off[strip + 1], strip, j.shift != 0, j.H,
+                                             s_occ, tw, sbuf, scnt, s_tmp, sp);
     __syncthreads();                        // the next strip reuses the strip buffer
   }
   const double W = UNIFORM ? (double)*s_occ : 2.0 * (double)*s_kept;
   if (j.wsum && threadIdx.x == 0) *j.wsum = W;
   const float scale = inverse_weight(W);
   for (int rb = 0; rb < NBLK; ++rb) {
-    row_task<LOGN, S, PREC>(j.H, rb, scale, j.out, tw, sbuf, s_max);
+    row_task<LOGN, S, PREC>(j.H, rb, scale, j.out, tw, sbuf, sp);
     __syncthreads();
   }
 }
@@ -137,16 +137,16 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(DescArgs a) {
     j.wsum = a.weight_sum ? a.weight_sum + img : nullptr;
     j.shift = a.shift;
     switch (logn) {
-      case 3: image_job<3, BLOCK, UNIFORM, PREC>(j, a.tw[3], sbuf, scnt, s_int, &s_max); break;
-      case 4: image_job<4, BLOCK, UNIFORM, PREC>(j, a.tw[4], sbuf, scnt, s_int, &s_max); break;
-      case 5: image_job<5, BLOCK, UNIFORM, PREC>(j, a.tw[5], sbuf, scnt, s_int, &s_max); break;
-      case 6: image_job<6, BLOCK, UNIFORM, PREC>(j, a.tw[6], sbuf, scnt, s_int, &s_max); break;
-      case 7: image_job<7, BLOCK, UNIFORM, PREC>(j, a.tw[7], sbuf, scnt, s_int, &s_max); break;
-      case 8: image_job<8, BLOCK, UNIFORM, PREC>(j, a.tw[8], sbuf, scnt, s_int, &s_max); break;
-      case 9: image_job<9, BLOCK, UNIFORM, PREC>(j, a.tw[9], sbuf, scnt, s_int, &s_max); break;
-      case 10: image_job<10, BLOCK, UNIFORM, PREC>(j, a.tw[10], sbuf, scnt, s_int, &s_max); break;
-      case 11: image_job<11, BLOCK, UNIFORM, PREC>(j, a.tw[11], sbuf, scnt, s_int, &s_max); break;
-      case 12: image_job<12, BLOCK, UNIFORM, PREC>(j, a.tw[12], sbuf, scnt, s_int, &s_max); break;
+      case 3: image_job<3, BLOCK, UNIFORM, PREC>(j, a.tw[3], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
+      case 4: image_job<4, BLOCK, UNIFORM, PREC>(j, a.tw[4], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
+      case 5: image_job<5, BLOCK, UNIFORM, PREC>(j, a.tw[5], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
+      case 6: image_job<6, BLOCK, UNIFORM, PREC>(j, a.tw[6], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
+      case 7: image_job<7, BLOCK, UNIFORM, PREC>(j, a.tw[7], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
+      case 8: image_job<8, BLOCK, UNIFORM, PREC>(j, a.tw[8], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
+      case 9: image_job<9, BLOCK, UNIFORM, PREC>(j, a.tw[9], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
+      case 10: image_job<10, BLOCK, UNIFORM, PREC>(j, a.tw[10], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
+      case 11: image_job<11, BLOCK, UNIFORM, PREC>(j, a.tw[11], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
+      case 12: image_job<12, BLOCK, UNIFORM, PREC>(j, a.tw[12], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
       default: break;
     }
   }

@@ -8,7 +8,8 @@
 //     M[2j][2q] = cos a,  M[2j][2q+1] = -sin a,  M[2j+1][2q] = sin a,  M[2j+1][2q+1] = cos a,
 // a = 2 pi (j q mod 16) / 16, and 32 butterflies at a time form the 32 x 32 right-hand side of
 // two v_mfma_f32_32x32x16 products (K = 16 reals each). Every FP32 operand x is split into
-// hi = round(x) and lo = round(x - hi) in the 16-bit type, and the product is
+// hi = round(x) and lo = round(x - hi) in the 16-bit type (FP16 data: hi rounded toward zero,
+// lo to nearest; otherwise both to nearest), and the product is
 //     M x ~ M_lo x_hi + M_hi x_lo + M_hi x_hi        (the lo * lo term is dropped)
 // accumulated in FP32: about 21 significant bits for FP16 (11 + 11), 16 for BF16 (8 + 8).
 // Twiddle multiplications between stages, and a final radix-2/4/8 stage where N is not a power
@@ -34,6 +35,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <type_traits>
 
 #include "fft_device.hpp"
@@ -75,24 +77,28 @@ __device__ __forceinline__ void split_value(float x, typename Split<PREC>::elem&
   lo = (E)(x - (float)hi);
 }
 
-// The A operands (hi and lo, for K blocks 0 and 1) of this lane: row n of M, columns 16 kb + 8 g + e.
-// `tw` holds exp(+2 pi i j / N) for j < N; entry t N/16 is exp(+2 pi i t / 16).
+// The A operands (hi and lo, for K blocks 0 and 1) of one lane: row n of M, columns 16 kb + 8 g + e,
+// from the 16-point DFT entries of a twiddle table (stage-ordered twiddle layout). They depend only on the lane,
+// so they are computed once per context (make_dft_operands) into a table of 4 x 16 bytes per lane
+// and precision: {hi kb 0, hi kb 1, lo kb 0, lo kb 1}.
 template <int PREC>
 struct DftOperands {
   typename Split<PREC>::vec hi[2], lo[2];
 };
 
-template <int PREC, int N>
-__device__ __forceinline__ DftOperands<PREC> dft16_operands(const float2* __restrict__ tw) {
+constexpr int kDftOpsPerPrec = 64 * 4;   // uint4 per precision
+
+template <int PREC>
+__device__ __forceinline__ DftOperands<PREC> dft16_operands_for_lane(const float2* __restrict__ tw, int lane) {
   DftOperands<PREC> F;
-  const int lane = threadIdx.x & 63, n = lane & 31, g = lane >> 5;
+  const int n = lane & 31, g = lane >> 5;
   const int j = n >> 1, p = n & 1;
 #pragma unroll
   for (int kb = 0; kb < 2; ++kb) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int q = 8 * kb + 4 * g + (e >> 1), r = e & 1;
-      const float2 w = tw[((j * q) & 15) * (N / 16)];
+      const float2 w = dft16_entry(tw, (j * q) & 15);
       const float f = (p == 0) ? (r == 0 ? w.x : -w.y) : (r == 0 ? w.y : w.x);
       typename Split<PREC>::elem h, l;
       split_value<PREC>(f, h, l);
@@ -103,6 +109,52 @@ __device__ __forceinline__ DftOperands<PREC> dft16_operands(const float2* __rest
   return F;
 }
 
+// Writes the operand table of one precision (64 lanes) from a twiddle table.
+template <int PREC>
+__device__ void make_dft_operands(const float2* __restrict__ tw, uint4* ops, int lane) {
+  const DftOperands<PREC> F = dft16_operands_for_lane<PREC>(tw, lane);
+  uint4* o = ops + (PREC - 1) * kDftOpsPerPrec + lane * 4;
+  o[0] = __builtin_bit_cast(uint4, F.hi[0]);
+  o[1] = __builtin_bit_cast(uint4, F.hi[1]);
+  o[2] = __builtin_bit_cast(uint4, F.lo[0]);
+  o[3] = __builtin_bit_cast(uint4, F.lo[1]);
+}
+
+// This lane's operands from the table (four 16-byte loads).
+template <int PREC>
+__device__ __forceinline__ DftOperands<PREC> dft16_operands(const uint4* __restrict__ ops) {
+  const uint4* o = ops + (PREC - 1) * kDftOpsPerPrec + (threadIdx.x & 63) * 4;
+  DftOperands<PREC> F;
+  F.hi[0] = __builtin_bit_cast(typename Split<PREC>::vec, o[0]);
+  F.hi[1] = __builtin_bit_cast(typename Split<PREC>::vec, o[1]);
+  F.lo[0] = __builtin_bit_cast(typename Split<PREC>::vec, o[2]);
+  F.lo[1] = __builtin_bit_cast(typename Split<PREC>::vec, o[3]);
+  return F;
+}
+
+// What the split form needs besides the data: the workgroup's LDS word for the FP16 maximum and
+// the context's DFT operand table (global memory).
+struct SplitCtx {
+  unsigned* s_max = nullptr;
+  const uint4* ops = nullptr;
+};
+
+// FP16 split of one complex value: hi = (re, im) rounded toward zero to FP16 (one packed word),
+// lo = the exact remainders x - hi rounded to nearest FP16, which the compiler forms with fused
+// mixed-precision operations on the halves of hi. hi + lo carries about 21 bits of x. (Written
+// without inline assembly so that the compiler sees every register the matrix core reads.)
+__device__ __forceinline__ void split_f16_pair(float re, float im, uint32_t& hi, uint32_t& lo) {
+  typedef __fp16 h2 __attribute__((ext_vector_type(2)));
+  typedef _Float16 f2 __attribute__((ext_vector_type(2)));
+  const h2 h = __builtin_amdgcn_cvt_pkrtz(re, im);
+  const f2 hf = __builtin_bit_cast(f2, h);
+  f2 l;
+  l[0] = (_Float16)(re - (float)hf[0]);
+  l[1] = (_Float16)(im - (float)hf[1]);
+  hi = __builtin_bit_cast(uint32_t, h);
+  lo = __builtin_bit_cast(uint32_t, l);
+}
+
 // One batch of 32 radix-16 butterflies: x[4 kb + i] is this lane's complex input 8 kb + 4 g + i.
 // Returns the FP32 result; output t (< 8) of this lane is complex 4 (t / 2) + 2 g + t % 2,
 // at (r[2 t], r[2 t + 1]).
@@ -110,17 +162,34 @@ template <int PREC>
 __device__ __forceinline__ f32x16 dft16_mfma(const float2 (&x)[8], const DftOperands<PREC>& F) {
   using S = Split<PREC>;
   typename S::vec bhi[2], blo[2];
+  if constexpr (PREC == kPrecSplitF16) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-  for (int kb = 0; kb < 2; ++kb) {
+    for (int kb = 0; kb < 2; ++kb) {
+      u32x4 h, l;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      typename S::elem h, l;
-      split_value<PREC>(x[4 * kb + i].x, h, l);
-      bhi[kb][2 * i] = h;
-      blo[kb][2 * i] = l;
-      split_value<PREC>(x[4 * kb + i].y, h, l);
-      bhi[kb][2 * i + 1] = h;
-      blo[kb][2 * i + 1] = l;
+      for (int i = 0; i < 4; ++i) {
+        uint32_t hw, lw;
+        split_f16_pair(x[4 * kb + i].x, x[4 * kb + i].y, hw, lw);
+        h[i] = hw;
+        l[i] = lw;
+      }
+      bhi[kb] = __builtin_bit_cast(typename S::vec, h);
+      blo[kb] = __builtin_bit_cast(typename S::vec, l);
+    }
+  } else {
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        typename S::elem h, l;
+        split_value<PREC>(x[4 * kb + i].x, h, l);
+        bhi[kb][2 * i] = h;
+        blo[kb][2 * i] = l;
+        split_value<PREC>(x[4 * kb + i].y, h, l);
+        bhi[kb][2 * i + 1] = h;
+        blo[kb][2 * i + 1] = l;
+      }
     }
   }
   f32x16 acc;
@@ -161,18 +230,19 @@ __device__ __forceinline__ int f16_scale_exponent(float mx) {
 
 // Complete inverse FFT of `ntrans` transforms of length N = 2^LOGN (LOGN >= 4) held by one block.
 // Transform c lives at buf + c * NP (padded, natural order) between stages. The first stage's
-// inputs come from load(c, e); the outputs go to sink(c, e, value), or, with ToLds, back into buf
-// at pad(e) with the block synchronised on return. Every thread of the block calls this; the
-// block size is a multiple of 64 and at least ntrans * N / 16. `tw` is the twiddle table for N
-// (visible to the block on entry); `s_max` as for block_max_abs (FP16 only).
-template <int LOGN, int PREC, bool ToLds, class Load, class Sink>
+// inputs come from buf (FromBuf) or from load(c, e); the outputs go to sink(c, e, value), or,
+// with ToLds, back into buf at pad(e) with the block synchronised on return. Every thread of the block calls this; the
+// block size is a multiple of 64 and at least ntrans * N / 16. `tw` is the twiddle table of N in
+// the stage-ordered twiddle layout (visible to the block on entry); sp.s_max as for block_max_abs (FP16 only)
+// and sp.ops the DFT operand table.
+template <int LOGN, int PREC, bool ToLds, bool FromBuf, class Load, class Sink>
 __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const float2* __restrict__ tw, Load load,
-                                                  Sink sink, unsigned* s_max) {
+                                                  Sink sink, SplitCtx sp) {
   using P = FftPlan<LOGN>;
   static_assert(LOGN >= 4, "the split form needs at least one radix-16 stage");
   static_assert(PREC == kPrecSplitF16 || PREC == kPrecSplitBf16, "split precision");
   constexpr int N = P::N, T = P::T, NP = P::NP, NB = N / 16;
-  const DftOperands<PREC> F = dft16_operands<PREC, N>(tw);
+  const DftOperands<PREC> F = dft16_operands<PREC>(sp.ops);
   const int lane = threadIdx.x & 63, n = lane & 31, g = lane >> 5, w = threadIdx.x >> 6;
   const int total = ntrans * NB;
 
@@ -183,22 +253,37 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
     b = beta % NB;
     return beta < total;
   };
+  // LDS address of input i of butterfly b of transform c (element b + q NB, q = split_in_q(g, i)):
+  // one base plus a compile-time offset when NB is a multiple of 16.
+  auto in_addr = [&](int c, int b, int i) {
+    if constexpr (NB % 16 == 0) {
+      const int qoff = i < 4 ? i : i + 4;
+      return c * NP + pad_index(b) + pad_offset(4 * NB) * g + pad_offset(qoff * NB);
+    } else {
+      return c * NP + pad_index(b + split_in_q(g, i) * NB);
+    }
+  };
   // Emits the outputs of one MFMA stage with span NS; `last` stages go to the sink (or LDS).
+  // Output t is element base + j NS with j = 2 g + jc(t), jc(t) = 4 (t / 2) + t % 2.
   auto emit = [&](const f32x16& r, int c, int b, bool act, auto ns_tag, auto last_tag, float u) {
     constexpr int NS = decltype(ns_tag)::value;
     constexpr bool LAST = decltype(last_tag)::value;
+    static_assert(NS == 1 || NS % 16 == 0, "stage spans are 1, 16 or 256");
     if (!act) return;
     const int k = b & (NS - 1);
+    const int base = (b - k) * 16 + k;
+    const int abase = NS == 1 ? c * NP + 17 * b + 2 * g : c * NP + pad_index(base) + pad_offset(2 * NS) * g;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      const int e = (b - k) * 16 + k + split_out_j(g, t) * NS;
+      const int jc = 4 * (t >> 1) + (t & 1);
+      const int off = NS == 1 ? jc : pad_offset(jc * NS);
       float2 val = make_float2(r[2 * t], r[2 * t + 1]);
       if constexpr (LAST) {
         val = cscale(val, u);
-        if constexpr (ToLds) buf[c * NP + pad_index(e)] = val;
-        else sink(c, e, val);
+        if constexpr (ToLds) buf[abase + off] = val;
+        else sink(c, base + (2 * g + jc) * NS, val);
       } else {
-        buf[c * NP + pad_index(e)] = val;
+        buf[abase + off] = val;
       }
     }
   };
@@ -211,7 +296,10 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
   for (int h = 0; h < 2; ++h) {
     act[h] = bfly(h, cc[h], bb[h]);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) x[h][i] = act[h] ? load(cc[h], bb[h] + split_in_q(g, i) * NB) : make_float2(0.f, 0.f);
+    for (int i = 0; i < 8; ++i) {
+      if constexpr (FromBuf) x[h][i] = act[h] ? buf[in_addr(cc[h], bb[h], i)] : make_float2(0.f, 0.f);
+      else x[h][i] = act[h] ? load(cc[h], bb[h] + split_in_q(g, i) * NB) : make_float2(0.f, 0.f);
+    }
   }
   float u = 1.f;
   if constexpr (PREC == kPrecSplitF16) {
@@ -220,7 +308,7 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int i = 0; i < 8; ++i) m = fmaxf(m, fmaxf(fabsf(x[h][i].x), fabsf(x[h][i].y)));
-    const int e = f16_scale_exponent(block_max_abs(m, s_max));   // also: every load of buf is done
+    const int e = f16_scale_exponent(block_max_abs(m, sp.s_max));   // also: every load of buf is done
     const float s = ldexpf(1.f, e);
     u = ldexpf(1.f, -e);
 #pragma unroll
@@ -245,7 +333,6 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
     // ---- later stages
     auto mfma_stage = [&](auto ns_tag, auto last_tag) {
       constexpr int NS = decltype(ns_tag)::value;
-      constexpr int STRIDE = N / (NS * 16);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         act[h] = bfly(h, cc[h], bb[h]);
@@ -253,8 +340,8 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const int q = split_in_q(g, i);
-          const float2 v = act[h] ? buf[cc[h] * NP + pad_index(bb[h] + q * NB)] : make_float2(0.f, 0.f);
-          x[h][i] = cmul(v, tw[k * q * STRIDE]);
+          const float2 v = act[h] ? buf[in_addr(cc[h], bb[h], i)] : make_float2(0.f, 0.f);
+          x[h][i] = cmul(v, stage_twiddle<NS>(tw, k, q));
         }
       }
       __syncthreads();

@@ -111,3 +111,19 @@ def test_desc_workspace_and_validation(L):
     assert L.blink_set_desc_plan(None, 512, 0) == blink.BLINK_ERR_ARG
     assert L.blink_graph_launch(None, None) == blink.BLINK_ERR_ARG
     assert L.blink_graph_destroy(None) == blink.BLINK_OK
+
+
+def test_conv_argument_checks(L):
+    dummy = ctypes.c_void_p(0x1000)
+
+    def call(N=64, width=8, beta=18.4, prec=0, T=1, ctx=None):
+        return L.blink_image_batch_conv(ctx, dummy, None, dummy, dummy, T, 1, 1, 10, N, 1e-3, width, beta, prec, 1,
+                                        dummy, None, None, ctypes.c_void_p(0x10000), 1 << 20, None)
+    assert call(N=100) == blink.BLINK_ERR_SIZE
+    assert call(T=-1) == blink.BLINK_ERR_ARG
+    assert call() == blink.BLINK_ERR_ARG                      # NULL context
+    s = blink.image_batch_conv_workspace_size(1, 2, 2, 8128, 1024, 8)
+    assert s > blink.image_batch_workspace_size(1, 2, 2, 8128, 1024)
+    for bad in ((1, 1, 1, 10, 64, 0), (1, 1, 1, 10, 64, 32), (1, 1, 1, 10, 64, 17), (1, 1, 1, 10, 16, 8)):
+        with pytest.raises(blink.BlinkError):
+            blink.image_batch_conv_workspace_size(*bad)
