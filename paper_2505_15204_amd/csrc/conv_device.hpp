@@ -191,6 +191,55 @@ __device__ __forceinline__ void scatter_strip_conv(const ConvRec* __restrict__ r
   }
 }
 
+// The same with one wave per record: lane l takes tap (row l / 8, column l % 8) for W <= 8, or
+// four passes over a 16 x 16 tap tile for larger W, so a record's taps are issued as one wave of
+// independent LDS atomics. Needs a workgroup of whole waves (NT a multiple of 64).
+template <int LOGN, int S, int NT>
+__device__ __forceinline__ void scatter_strip_conv_waves(const ConvRec* __restrict__ rec, int o0, int o1,
+                                                         const float2* __restrict__ V, int strip, bool modulate,
+                                                         ConvSpec cs, float2* sbuf) {
+  static_assert(NT % 64 == 0, "whole waves");
+  constexpr int N = 1 << LOGN, NP = padded_len(N), HALF = N / 2, NW = NT / 64;
+  const float h = 0.5f * cs.width, tw = 2.f / cs.width;
+  const int c_lo = strip * S;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tile = cs.width <= 8 ? 8 : 16, passes = cs.width <= 8 ? 1 : 4;
+  for (int i = o0 + wave; i < o1; i += NW) {
+    const ConvRec r = rec[i];
+    const int b = r.bconj & 0x7fffffff;
+    float2 val = V[b];
+    if (r.bconj < 0) val.y = -val.y;
+    const int ju0 = (int)((unsigned)r.cells & 0xffffu) - 32768, jv0 = (int)((unsigned)r.cells >> 16) - 32768;
+    for (int p = 0; p < passes; ++p) {
+      const int t = p * 64 + lane;
+      const int ti = t / tile, tj = t % tile;
+      const float du = r.du0 + tj, dv = r.dv0 + ti;
+      if (ti >= cs.width || tj >= cs.width || !(du < h) || !(dv < h)) continue;
+      const int ku = (ju0 + tj) & (N - 1);
+      int col;
+      bool nyq = false;
+      if (ku >= c_lo && ku < c_lo + S) col = ku - c_lo;
+      else if (strip == 0 && ku == HALF) { col = 0; nyq = true; }
+      else continue;
+      const int kv = (jv0 + ti) & (N - 1);
+      const float w = es_weight(du, tw, cs.beta) * es_weight(dv, tw, cs.beta);
+      float sx = val.x * w, sy = val.y * w;
+      if (nyq) {                                      // packed as i * column N/2
+        const float t0 = sx;
+        sx = -sy;
+        sy = t0;
+      }
+      if (modulate && ((ku + kv) & 1)) {
+        sx = -sx;
+        sy = -sy;
+      }
+      float* q = &sbuf[col * NP + pad_index(kv)].x;
+      atomicAdd(q, sx);
+      atomicAdd(q + 1, sy);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- fused conv gridding + column FFT
 // One strip of S half-spectrum columns of one image: zero the LDS strip, spread the strip's
 // records, transform the columns and store the strip into Hi (column 0 keeps the packed Nyquist
@@ -208,7 +257,8 @@ __device__ __forceinline__ void grid_colfft_conv_task(const float2* __restrict__
     if (threadIdx.x == 0) *sp.s_max = 0u;
   }
   __syncthreads();
-  scatter_strip_conv<LOGN, S>(rec, o0, o1, V, strip, shift, cs, sbuf);
+  if constexpr (NT % 64 == 0) scatter_strip_conv_waves<LOGN, S, NT>(rec, o0, o1, V, strip, shift, cs, sbuf);
+  else scatter_strip_conv<LOGN, S>(rec, o0, o1, V, strip, shift, cs, sbuf);
   __syncthreads();
   strip_fft_store<LOGN, S, PREC, NT, false>(sbuf, strip, Hi, tw, sp);
 }

@@ -118,22 +118,21 @@ __device__ __forceinline__ void dft(float2* v) {
 
 // ---------------------------------------------------------------- twiddle table layout
 // Twiddle table of one size N, by stage (generated in FP64 and rounded to FP32 on the device):
-//   A[17 k + m]      = exp(+2 pi i k m / (16 R1)),  k < 16, m < R1   second stage (span 16)
-//   A[17 k + 16]     = exp(+2 pi i k / 16),         k < 16           16-point DFT entries
+//   A[16 m + k]      = exp(+2 pi i k m / (16 R1)),  k < 16, m < R1   second stage (span 16)
+//   D[t]             = exp(+2 pi i t / 16),         t < 16           16-point DFT entries
 //   B[256 m + k]     = exp(+2 pi i k m / N),        k < 256, m < R2  third stage (span 256), N >= 512
-// with B = A + 272. A row holds 17 values, so the 16 values of k a wave reads for one m fall in
-// distinct banks; a B row is contiguous in k.
-constexpr int kTwRow = 17;
-constexpr int kTwA = 16 * kTwRow;
+// with D = A + 256 and B = A + 272. For one m the lanes of a wave read consecutive k: distinct
+// LDS banks, and one cache line per 16 values when the table is read from global memory.
+constexpr int kTwA = 16 * 16 + 16;
 __host__ __device__ constexpr int tw_size(int logn) { return kTwA + (logn >= 9 ? (1 << logn) : 0); }
 
 template <int NS>
 __device__ __forceinline__ float2 stage_twiddle(const float2* __restrict__ tw, int k, int m) {
   static_assert(NS == 16 || NS == 256, "twiddled stages have span 16 or 256");
-  if constexpr (NS == 16) return tw[k * kTwRow + m];
+  if constexpr (NS == 16) return tw[m * 16 + k];
   else return tw[kTwA + m * 256 + k];
 }
-__device__ __forceinline__ float2 dft16_entry(const float2* __restrict__ tw, int t) { return tw[t * kTwRow + 16]; }
+__device__ __forceinline__ float2 dft16_entry(const float2* __restrict__ tw, int t) { return tw[256 + t]; }
 
 // ---------------------------------------------------------------- plan
 template <int LOGN>

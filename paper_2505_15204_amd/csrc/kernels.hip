@@ -25,7 +25,7 @@ namespace blink {
 
 // ---------------------------------------------------------------- twiddles
 // The stage-ordered table of one size N (fft_device.hpp): FP64 sincospi of an exact dyadic
-// argument, rounded to FP32. Unused slots of A (m >= R1) hold zero.
+// argument, rounded to FP32. Unused rows of A (m >= R1) hold zero.
 __global__ void k_twiddles(float2* tw, int logn) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= tw_size(logn)) return;
@@ -33,17 +33,15 @@ __global__ void k_twiddles(float2* tw, int logn) {
   const int r1 = logn <= 4 ? 1 : (logn >= 8 ? 16 : n / 16);
   long num = 0, den = 1;
   bool used = true;
-  if (j < kTwA) {
-    const int k = j / kTwRow, m = j % kTwRow;
-    if (m == 16) {
-      num = k;
-      den = 16;
-    } else {
-      used = m < r1;
-      num = (long)k * m;
-      den = 16L * r1;
-    }
-  } else {
+  if (j < 256) {                      // A: row m, column k
+    const int m = j / 16, k = j % 16;
+    used = m < r1;
+    num = (long)k * m;
+    den = 16L * r1;
+  } else if (j < kTwA) {              // D: 16-point DFT entries
+    num = j - 256;
+    den = 16;
+  } else {                            // B: row m, column k
     const int m = (j - kTwA) / 256, k = (j - kTwA) % 256;
     num = (long)k * m;
     den = n;
