@@ -12,8 +12,9 @@ Prints one JSON line with images/s (FP32 form), the roofline position of the dom
 the FP64 CPU oracle timed on a bounded sample of the same workload on the host cores, and the
 other forms measured beside it on the same GPU: the split-precision matrix-core FFT forms on
 this workload and on the 4096^2 precision workload (images/s ratio to FP32), convolutional
-gridding (W = 8) on this workload, and the uneven batch (4096 images of 512^2 .. 2048^2 in one
-persistent launch, eager and as a hipGraph).
+gridding (W = 8) on this workload, the Stokes I + band average of one time step's images, and
+the uneven batch (4096 images of 512^2 .. 2048^2 in one persistent launch, eager and as a
+hipGraph).
 """
 import argparse
 import json
@@ -355,6 +356,17 @@ def main():
                                              "kernels": {k: ck[k] for k in ("bin", "grid_colfft", "row_fft") if k in ck}}
         log(f"conv W=8: {v:.0f} images/s ({v / value:.3f} x nearest-cell FP32)")
         del cws
+        # Stokes I + band average of one time step's images (1536 images -> 1), HBM-bound.
+        avg_out = torch.empty((1, 1, 1, N, N), dtype=torch.float32, device="cuda:0")
+        ms = timed(torch, lambda i: ctx.blink_image_average(images, blink.AVG_CHANNEL | blink.AVG_POL, out=avg_out),
+                   10, 2) / 10
+        moved = (C * P + 1) * 4 * N * N
+        forms["vcs-1024"]["stokes_i_band_average"] = {
+            "images_in": C * P, "ms": round(ms, 4), "bytes": moved,
+            "achieved_GB_s": round(moved / (ms / 1e3) / 1e9, 1),
+            "frac_hbm": round(moved / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"Stokes I + band average of {C * P} images: {ms:.3f} ms "
+            f"({moved / (ms / 1e3) / 1e9:.0f} GB/s)")
         forms["precision-4096"] = bench_precision_workload(ctx, torch, blink, synth, 3, 1)
         forms["uneven"] = bench_uneven(ctx, torch, blink, synth, 3)
 

@@ -169,6 +169,17 @@ blink_status blink_image_batch_conv(blink_ctx ctx, const blink_cf32 *vis, const 
                                     double *weight_sum, int32_t *n_out, void *workspace,
                                     size_t workspace_bytes, void *hip_stream);
 
+/* ---------------------------------------------------------------- image averages
+ * The paper averages its dirty images over time and over the band (Section 7.1: a long-exposure
+ * image over all seconds and the 30.72 MHz band; Section 7.2: all channels of each 20 ms bin).
+ * blink_image_average averages images float [T][C][P][N][N] (device) over every axis set in
+ * `axes` and keeps the others: out float [T'][C'][P'][N][N] with T' = 1 if averaged over time,
+ * else T (likewise C', P'). Averaging P = 2 (XX, YY) gives Stokes I = (XX + YY) / 2. Sums are
+ * FP64; out must not overlap images. */
+enum { BLINK_AVG_TIME = 1, BLINK_AVG_CHANNEL = 2, BLINK_AVG_POL = 4 };
+blink_status blink_image_average(blink_ctx ctx, const float *images, int T, int C, int P, int grid_n,
+                                 int axes, float *out, void *hip_stream);
+
 /* ---------------------------------------------------------------- uneven batches
  * Section 6.2.4 grids many fine channels and integration intervals in parallel on one GPU and
  * transforms all grids at once. blink_image_batch_desc does this for images that differ in grid
@@ -295,7 +306,8 @@ enum {
     BLINK_KERNEL_DESC_PREP = 6,    /* descriptor checks and image order (uneven batches) */
     BLINK_KERNEL_PERSISTENT = 7,   /* persistent fused binning + gridding + FFT (uneven batches) */
     BLINK_KERNEL_CONV_CORRECTION = 8, /* grid-correction table of the convolutional path */
-    BLINK_KERNEL_COUNT = 9
+    BLINK_KERNEL_AVERAGE = 9,      /* image averages (blink_image_average) */
+    BLINK_KERNEL_COUNT = 10
 };
 
 /* Enable (nonzero) or disable timing; either way the recorded launches are discarded. */

@@ -63,6 +63,8 @@ def load(path: str):
     L.blink_ref_grid_conv.argtypes = [P, P, P, i32, i32, f64, i32, f64, i32, f64, P, P, P]
     L.blink_ref_conv_correction.restype = i32
     L.blink_ref_conv_correction.argtypes = [i32, i32, f64, i32, P]
+    L.blink_ref_image_average.restype = i32
+    L.blink_ref_image_average.argtypes = [P, i32, i32, i32, i32, i32, P]
     L.blink_ref_image_batch_conv.restype = i32
     L.blink_ref_image_batch_conv.argtypes = [P, P, P, P, i32, i32, i32, i32, i32, f64, i32, f64, i32, P, P, P,
                                              i32]
@@ -166,6 +168,18 @@ class Oracle:
     def max_threads(self) -> int:
         return int(self.L.blink_ref_max_threads())
 
+    def image_average(self, images, axes):
+        """Average float images [T][C][P][N][N] over the axes in `axes` (1 time, 2 channel,
+        4 polarisation); returns float64 [T'][C'][P'][N][N]."""
+        a = _c(images, np.float32)
+        T, C, P, N, _ = a.shape
+        shape = (1 if axes & 1 else T, 1 if axes & 2 else C, 1 if axes & 4 else P, N, N)
+        out = np.empty(shape, dtype=np.float64)
+        rc = self.L.blink_ref_image_average(_ptr(a), T, C, P, N, int(axes), _ptr(out))
+        if rc != 0:
+            raise ValueError(f"blink_ref_image_average failed with code {rc}")
+        return out
+
     # -- convolutional gridding (exponential-of-semicircle kernel, grid correction)
     def es_kernel(self, z: float, beta: float) -> float:
         return self.L.blink_ref_es_kernel(float(z), float(beta))
@@ -246,6 +260,10 @@ def image_batch(*a, **k):
 
 def max_threads() -> int:
     return default().max_threads()
+
+
+def image_average(*a, **k):
+    return default().image_average(*a, **k)
 
 
 def es_kernel(*a, **k):

@@ -381,3 +381,29 @@ int blink_ref_image_batch_conv(const float *vis, const uint8_t *flags, const dou
     free(corr);
     return err;
 }
+
+/* ------------------------------------------------------------------------------------------
+ * Image averages (Sections 7.1 and 7.2: images are averaged over time and over the band, e.g.
+ * all channels of one time bin). images [T][C][P][N][N] float; each axis selected in `axes`
+ * (1 time, 2 channel, 4 polarisation) is averaged (its extent becomes 1), the others are kept:
+ * out [T'][C'][P'][N][N] double. Over P = 2 (XX, YY) this is Stokes I = (XX + YY) / 2.
+ * ------------------------------------------------------------------------------------------ */
+int blink_ref_image_average(const float *images, int T, int C, int P, int grid_n, int axes, double *out)
+{
+    if (!images || !out || T < 1 || C < 1 || P < 1 || grid_n < 1 || axes < 0 || axes > 7) return 1;
+    const size_t NN = (size_t)grid_n * grid_n;
+    const int To = (axes & 1) ? 1 : T, Co = (axes & 2) ? 1 : C, Po = (axes & 4) ? 1 : P;
+    const double count = (double)((axes & 1) ? T : 1) * ((axes & 2) ? C : 1) * ((axes & 4) ? P : 1);
+    memset(out, 0, sizeof(double) * NN * (size_t)To * Co * Po);
+    for (int t = 0; t < T; ++t)
+        for (int c = 0; c < C; ++c)
+            for (int p = 0; p < P; ++p) {
+                int to = (axes & 1) ? 0 : t, co = (axes & 2) ? 0 : c, po = (axes & 4) ? 0 : p;
+                const float *src = images + (((size_t)t * C + c) * P + p) * NN;
+                double *dst = out + (((size_t)to * Co + co) * Po + po) * NN;
+                for (size_t i = 0; i < NN; ++i) dst[i] += (double)src[i];
+            }
+    const size_t total = NN * (size_t)To * Co * Po;
+    for (size_t i = 0; i < total; ++i) out[i] /= count;
+    return 0;
+}

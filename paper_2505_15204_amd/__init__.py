@@ -21,7 +21,8 @@ PLANS_PATH = os.path.join(PKG, "plans_gfx950.json")     # autotuned execution pl
 BLINK_OK, BLINK_ERR_ARG, BLINK_ERR_SIZE, BLINK_ERR_NOMEM, BLINK_ERR_HIP, BLINK_ERR_STATE = range(6)
 WEIGHT_NATURAL, WEIGHT_UNIFORM = 0, 1
 KERNELS = ("bin", "grid", "grid_colfft", "dense_colfft", "weights", "row_fft", "desc_prep", "persistent",
-           "conv_correction")   # BLINK_KERNEL_* ids
+           "conv_correction", "average")
+AVG_TIME, AVG_CHANNEL, AVG_POL = 1, 2, 4   # BLINK_KERNEL_* ids
 DESC_BAD = 1
 
 # blink_image_desc as a NumPy structured dtype (64 bytes, C layout)
@@ -94,6 +95,8 @@ def lib() -> ctypes.CDLL:
     L.blink_image_batch_conv.restype = i32
     L.blink_image_batch_conv.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, f64, i32, i32, P, P, P,
                                          P, sz, P]
+    L.blink_image_average.restype = i32
+    L.blink_image_average.argtypes = [P, P, i32, i32, i32, i32, i32, P, P]
     L.blink_autotune_image_batch.restype = i32
     L.blink_autotune_image_batch.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32, P, P,
                                              P, P, sz, P, P, P, P, P]
@@ -463,6 +466,23 @@ class Context:
                                      self._stream(stream))
         _check(st, self.handle, "blink_image_batch")
         return {"images": out, "weight_sum": weight_sum, "n_out": n_out}
+
+    def blink_image_average(self, images, axes: int, out=None, stream=None):
+        """Average float32 images [T][C][P][N][N] over the axes in `axes` (AVG_TIME | AVG_CHANNEL |
+        AVG_POL); returns float32 [T'][C'][P'][N][N] (averaged axes have extent 1)."""
+        torch = self._torch()
+        self._require("images", images, torch.float32)
+        T, C, P, N, N2 = images.shape
+        if N != N2:
+            raise ValueError("images must be square")
+        shape = (1 if axes & AVG_TIME else T, 1 if axes & AVG_CHANNEL else C, 1 if axes & AVG_POL else P, N, N)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=images.device)
+        self._require("out", out, torch.float32, shape)
+        st = lib().blink_image_average(self.handle, _ptr(images), T, C, P, N, int(axes), _ptr(out),
+                                       self._stream(stream))
+        _check(st, self.handle, "blink_image_average")
+        return out
 
     def blink_image_batch_conv(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float,
                                kernel_width: int = 8, kernel_beta: float = 18.4, precision: int = PREC_FP32,

@@ -792,6 +792,28 @@ blink_status blink_image_batch_conv(blink_ctx ctx, const blink_cf32* vis, const 
   return BLINK_OK;
 }
 
+blink_status blink_image_average(blink_ctx ctx, const float* images, int T, int C, int P, int grid_n, int axes,
+                                 float* out, void* hip_stream) {
+  if (T < 0 || C < 0 || P < 0 || axes < 0 || axes > 7) return fail(ctx, BLINK_ERR_ARG, "bad sizes or axes %d", axes);
+  const int logn = log2_exact(grid_n);
+  if (logn < 0) return fail(ctx, BLINK_ERR_SIZE, "grid_n=%d unsupported", grid_n);
+  if (!ctx) return BLINK_ERR_ARG;
+  if (ctx->broken) return fail(ctx, BLINK_ERR_STATE, "context unusable after an earlier HIP error");
+  if ((size_t)T * C * P == 0) return BLINK_OK;
+  if (!images || !out) return fail(ctx, BLINK_ERR_ARG, "NULL images or out");
+  if ((uintptr_t)images % 16 || (uintptr_t)out % 16) return fail(ctx, BLINK_ERR_ARG, "arrays must be 16-byte aligned");
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e;
+  {
+    KernelTimer kt(ctx, BLINK_KERNEL_AVERAGE, s);
+    e = blink::launch_image_average(images, T, C, P, logn, axes, out, s);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "image average kernel");
+  return BLINK_OK;
+}
+
 // ---------------------------------------------------------------- uneven batches
 }  // extern "C"
 

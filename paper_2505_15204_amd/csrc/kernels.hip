@@ -155,6 +155,43 @@ hipError_t launch_grid_colfft_conv(const ColArgs& a, int n_img, ConvParams cp, i
   }
 }
 
+// ---------------------------------------------------------------- image averages
+// Averages of images [T][C][P][N][N] over the axes in `axes` (1 time, 2 channel, 4 polarisation;
+// Sections 7.1 and 7.2 average over time and over the band, the polarisation average of XX and YY
+// is Stokes I). One thread per 4 consecutive pixels of one output image, FP64 sums.
+__global__ __launch_bounds__(256) void k_image_average(const float4* __restrict__ in, int T, int C, int P, long nn4,
+                                                       int axes, float4* __restrict__ out) {
+  const int To = (axes & 1) ? 1 : T, Co = (axes & 2) ? 1 : C, Po = (axes & 4) ? 1 : P;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)To * Co * Po * nn4) return;
+  const long img = gid / nn4, px = gid - img * nn4;
+  const int po = (int)(img % Po), co = (int)((img / Po) % Co), to = (int)(img / ((long)Po * Co));
+  const int t0 = (axes & 1) ? 0 : to, t1 = (axes & 1) ? T : to + 1;
+  const int c0 = (axes & 2) ? 0 : co, c1 = (axes & 2) ? C : co + 1;
+  const int p0 = (axes & 4) ? 0 : po, p1 = (axes & 4) ? P : po + 1;
+  double ax = 0.0, ay = 0.0, az = 0.0, aw = 0.0;
+  for (int t = t0; t < t1; ++t)
+    for (int c = c0; c < c1; ++c)
+      for (int p = p0; p < p1; ++p) {
+        const float4 v = in[(((long)t * C + c) * P + p) * nn4 + px];
+        ax += v.x;
+        ay += v.y;
+        az += v.z;
+        aw += v.w;
+      }
+  const double inv = 1.0 / ((double)(t1 - t0) * (c1 - c0) * (p1 - p0));
+  out[gid] = make_float4((float)(ax * inv), (float)(ay * inv), (float)(az * inv), (float)(aw * inv));
+}
+
+hipError_t launch_image_average(const float* in, int T, int C, int P, int logn, int axes, float* out, hipStream_t s) {
+  const long nn4 = (1L << (2 * logn)) / 4;
+  const long n_out = (long)((axes & 1) ? 1 : T) * ((axes & 2) ? 1 : C) * ((axes & 4) ? 1 : P) * nn4;
+  if (n_out <= 0) return hipSuccess;
+  k_image_average<<<(unsigned)((n_out + 255) / 256), 256, 0, s>>>((const float4*)in, T, C, P, nn4, axes,
+                                                                    (float4*)out);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- full grid (blink_grid)
 template <int LOGN, bool UNIFORM>
 __global__ __launch_bounds__(256) void k_grid_full(GridArgs a) {

@@ -108,6 +108,9 @@ int conv_strip_width(int logn);
 // corr[x] = 1 / c(X/N) for x < N (FP64 quadrature, stored as FP32).
 hipError_t launch_conv_correction(float* corr, int logn, ConvParams cp, int shift, hipStream_t s);
 
+// Averages of images [T][C][P][N][N] over the axes in `axes` (1 time, 2 channel, 4 pol).
+hipError_t launch_image_average(const float* in, int T, int C, int P, int logn, int axes, float* out, hipStream_t s);
+
 // The same three launchers for one precision form; FP32 is built in kernels.hip, each split
 // precision in its own object from split.hip.
 template <int PREC>

@@ -44,6 +44,9 @@ struct PersistLds {
     }
     return m;
   }
+  // The largest twiddle table is staged in LDS when it fits beside the strip and counts of
+  // uniform weighting; otherwise the jobs read the tables from global memory.
+  static constexpr bool tw_in_lds = (max_f2() + tw_size(12)) * 8 + max_counts() * 4 + 1024 <= kLdsBytes;
 };
 static_assert(sizeof(BinShared) <= sizeof(float2) * PersistLds<512>::max_f2(), "binning scratch aliases the strip");
 
@@ -72,9 +75,11 @@ struct Log2<1> {
   static constexpr int value = 0;
 };
 
-template <int LOGN, int BLOCK, bool UNIFORM, int PREC>
+// `tw` is the twiddle table of N in global memory; with TWL it is first copied to `stw` (LDS)
+// unless the previous job of this workgroup had the same size (*s_tw_logn).
+template <int LOGN, int BLOCK, bool UNIFORM, int PREC, bool TWL>
 __device__ __noinline__ void image_job(ImageJob j, const float2* __restrict__ tw, float2* sbuf, unsigned* scnt,
-                                       int* s_int, SplitCtx sp) {
+                                       int* s_int, SplitCtx sp, float2* stw, int* s_tw_logn) {
   constexpr int N = 1 << LOGN;
   constexpr int S = desc_cols(LOGN, BLOCK);
   constexpr int NBLK = (N / 2) / S;         // column strips, and row blocks of S row pairs
@@ -84,6 +89,14 @@ __device__ __noinline__ void image_job(ImageJob j, const float2* __restrict__ tw
   int* s_kept = s_int + 1;
   int* s_occ = s_int + 2;
   BinShared& bsh = *reinterpret_cast<BinShared*>(sbuf);
+  if constexpr (TWL) {
+    if (*s_tw_logn != LOGN) {           // the same value in every thread: a uniform branch
+      for (int i = threadIdx.x; i < tw_size(LOGN); i += BLOCK) stw[i] = tw[i];
+      __syncthreads();                  // every thread has read *s_tw_logn and the table is complete
+      if (threadIdx.x == 0) *s_tw_logn = LOGN;
+    }
+    tw = stw;
+  }
   bin_visibilities(j.uvw, j.flags, j.B, j.k, LOGN, LOGS, N / 2, j.plc, j.off, s_kept, j.n_out, nullptr, bsh);
   if (threadIdx.x == 0) *s_occ = 0;
   __syncthreads();                          // placement list and offsets complete; binning scratch free
@@ -109,6 +122,10 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(DescArgs a) {
   __shared__ int s_int[4];
   __shared__ int s_next;
   __shared__ unsigned s_max;
+  constexpr bool TWL = L::tw_in_lds;
+  __shared__ float2 stw[TWL ? tw_size(12) : 1];
+  __shared__ int s_tw_logn;
+  if (threadIdx.x == 0) s_tw_logn = -1;   // visible after the claim barrier below
   const size_t slot_elems = (size_t)1 << (2 * a.max_logn - 1);
   float2* H = a.H + (size_t)blockIdx.x * slot_elems;
   int2* plc = a.plc + (size_t)blockIdx.x * 2 * a.max_b;
@@ -137,16 +154,16 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(DescArgs a) {
     j.wsum = a.weight_sum ? a.weight_sum + img : nullptr;
     j.shift = a.shift;
     switch (logn) {
-      case 3: image_job<3, BLOCK, UNIFORM, PREC>(j, a.tw[3], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
-      case 4: image_job<4, BLOCK, UNIFORM, PREC>(j, a.tw[4], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
-      case 5: image_job<5, BLOCK, UNIFORM, PREC>(j, a.tw[5], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
-      case 6: image_job<6, BLOCK, UNIFORM, PREC>(j, a.tw[6], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
-      case 7: image_job<7, BLOCK, UNIFORM, PREC>(j, a.tw[7], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
-      case 8: image_job<8, BLOCK, UNIFORM, PREC>(j, a.tw[8], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
-      case 9: image_job<9, BLOCK, UNIFORM, PREC>(j, a.tw[9], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
-      case 10: image_job<10, BLOCK, UNIFORM, PREC>(j, a.tw[10], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
-      case 11: image_job<11, BLOCK, UNIFORM, PREC>(j, a.tw[11], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
-      case 12: image_job<12, BLOCK, UNIFORM, PREC>(j, a.tw[12], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}); break;
+      case 3: image_job<3, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[3], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
+      case 4: image_job<4, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[4], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
+      case 5: image_job<5, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[5], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
+      case 6: image_job<6, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[6], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
+      case 7: image_job<7, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[7], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
+      case 8: image_job<8, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[8], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
+      case 9: image_job<9, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[9], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
+      case 10: image_job<10, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[10], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
+      case 11: image_job<11, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[11], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
+      case 12: image_job<12, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[12], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
       default: break;
     }
   }

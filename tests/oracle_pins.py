@@ -436,7 +436,20 @@ def pin_conv_batch_consistency(O):
             assert np.abs(out["images"][0, 0, p] - want).max() <= 1e-12 * np.abs(want).max()
 
 
-CONV_PINS = [pin_es_kernel_values, pin_es_transform, pin_conv_width1_is_nearest_cell, pin_conv_hermitian,
+def pin_image_average(O):
+    """Averages against numpy's mean over the same axes; Stokes I of identical pols is that pol."""
+    g = np.random.default_rng(35)
+    imgs = g.normal(size=(3, 4, 2, 8, 8)).astype(np.float32)
+    for axes in range(8):
+        ax = tuple(i for i, bit in enumerate((1, 2, 4)) if axes & bit)
+        ref = imgs.astype(np.float64).mean(axis=ax, keepdims=True) if ax else imgs.astype(np.float64)
+        got = O.image_average(imgs, axes)
+        assert got.shape == ref.shape and np.abs(got - ref).max() <= 1e-12, axes
+    same = np.repeat(imgs[:, :, :1], 2, axis=2)
+    assert np.array_equal(O.image_average(same, 4)[:, :, 0], imgs[:, :, 0].astype(np.float64))
+
+
+CONV_PINS = [pin_image_average, pin_es_kernel_values, pin_es_transform, pin_conv_width1_is_nearest_cell, pin_conv_hermitian,
              pin_conv_matches_direct_transform, pin_conv_batch_consistency]
 
 
