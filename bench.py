@@ -229,7 +229,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="tune the execution plan on time step 0 instead of loading the committed plan file")
     ap.add_argument("--save-plans", default="", help="write the context's plans (JSON) to this path")
-    ap.add_argument("--plan", default="", help="force a plan col_strip,row_block,group")
+    ap.add_argument("--plan", default="", help="force a plan col_strip,row_block,group[,col_loop]")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the split-precision and uneven-batch measurements beside the headline")
     ap.add_argument("--form-steps", type=int, default=20, help="steps per split-precision form measurement")
@@ -279,8 +279,8 @@ def main():
 
     tune = None
     if args.plan:
-        c, r, g = (int(x) for x in args.plan.split(","))
-        ctx.set_plan(N, 0, c, r, g)
+        c, r, g, *lp = (int(x) for x in args.plan.split(","))
+        ctx.set_plan(N, 0, c, r, g, col_loop=lp[0] if lp else 1)
     elif not args.autotune and os.path.exists(blink.PLANS_PATH):
         ctx.load_plans(blink.PLANS_PATH)
         tune = {"source": os.path.relpath(blink.PLANS_PATH, ROOT)}

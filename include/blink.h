@@ -264,7 +264,10 @@ blink_status blink_graph_destroy(blink_graph graph);
  *   row_block  row-pair transforms per workgroup of the row FFT kernel
  *   group      images per column/row launch pair (0 = as many as the workspace holds, at most 256
  *              with the queried workspace); small groups keep the intermediates in the last-level
- *              cache between the two passes. */
+ *              cache between the two passes.
+ *   col_loop   strips each workgroup of the fused gridding + column FFT kernel takes in turn
+ *              (1 .. 64; 1 = one strip per workgroup). Above 1 the workgroup requests the next
+ *              strips' placements while it transforms and stores the current one. */
 
 /* Compiled options for grid_n and weighting (the same for every precision form): up to 4 strip
  * widths and 4 row blocks each. */
@@ -273,24 +276,25 @@ blink_status blink_plan_options(int grid_n, int weighting, int *col_strips, int 
 
 /* Current plan of a context (a default until set or tuned). */
 blink_status blink_get_plan(blink_ctx ctx, int grid_n, int weighting, int precision,
-                            int *col_strip, int *row_block, int *group);
+                            int *col_strip, int *row_block, int *group, int *col_loop);
 
-/* Set a plan; col_strip and row_block must be compiled options, group >= 0. */
+/* Set a plan; col_strip and row_block must be compiled options, group >= 0, 1 <= col_loop <= 64. */
 blink_status blink_set_plan(blink_ctx ctx, int grid_n, int weighting, int precision,
-                            int col_strip, int row_block, int group);
+                            int col_strip, int row_block, int group, int col_loop);
 
 /* Autotuner: runs blink_image_batch on the caller's problem (same arguments) for every compiled
- * (col_strip, row_block) pair and group sizes 16 .. 256, times each with hipEvents on hip_stream,
- * and keeps the fastest as the context's plan for (grid_n, weighting, precision). Synchronises
- * with the host. On return `images` etc. hold a valid result, and col_strip, row_block, group and
- * best_ms (any may be NULL) describe the choice. */
+ * (col_strip, row_block) pair and group sizes 16 .. 256 with col_loop 1, then col_loop 2, 4, .. 16
+ * on the fastest of those; times each with hipEvents on hip_stream and keeps the fastest as the
+ * context's plan for (grid_n, weighting, precision). Synchronises with the host. On return
+ * `images` etc. hold a valid result, and col_strip, row_block, group, col_loop and best_ms (any
+ * may be NULL) describe the choice. */
 blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32 *vis, const uint8_t *flags,
                                         const double *uvw_m, const double *freq_hz, int T, int C,
                                         int P, int B, int grid_n, double pixel_scale, int weighting,
                                         int precision, int shift, float *images, double *weight_sum,
                                         int32_t *n_out, void *workspace, size_t workspace_bytes,
                                         void *hip_stream, int *col_strip, int *row_block,
-                                        int *group, double *best_ms);
+                                        int *group, int *col_loop, double *best_ms);
 
 /* ---------------------------------------------------------------- kernel timing
  * Not part of the method: per-kernel timing for measurement. While enabled, every kernel launch

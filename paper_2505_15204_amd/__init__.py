@@ -87,9 +87,9 @@ def lib() -> ctypes.CDLL:
     L.blink_plan_options.restype = i32
     L.blink_plan_options.argtypes = [i32, i32, P, P, P, P]
     L.blink_get_plan.restype = i32
-    L.blink_get_plan.argtypes = [P, i32, i32, i32, P, P, P]
+    L.blink_get_plan.argtypes = [P, i32, i32, i32, P, P, P, P]
     L.blink_set_plan.restype = i32
-    L.blink_set_plan.argtypes = [P, i32, i32, i32, i32, i32, i32]
+    L.blink_set_plan.argtypes = [P, i32, i32, i32, i32, i32, i32, i32]
     L.blink_image_batch_conv_workspace_size.restype = i32
     L.blink_image_batch_conv_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
     L.blink_image_batch_conv.restype = i32
@@ -99,7 +99,7 @@ def lib() -> ctypes.CDLL:
     L.blink_image_average.argtypes = [P, P, i32, i32, i32, i32, i32, P, P]
     L.blink_autotune_image_batch.restype = i32
     L.blink_autotune_image_batch.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32, P, P,
-                                             P, P, sz, P, P, P, P, P]
+                                             P, P, sz, P, P, P, P, P, P]
     i64 = ctypes.c_int64
     desc_args = [P, P, i32, P, i64, P, i64, P, i64, i32, i32, i32, i32, i32, P, i64, P, P, P, P, sz]
     L.blink_desc_workspace_size.restype = i32
@@ -232,14 +232,14 @@ class Context:
 
     # -- execution plans (scheduling only; results are the same up to rounding order)
     def get_plan(self, grid_n: int, weighting: int = 0, precision: int = PREC_FP32) -> dict:
-        c, r, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        c, r, g, lp = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(lib().blink_get_plan(self.handle, grid_n, weighting, precision, ctypes.byref(c), ctypes.byref(r),
-                                    ctypes.byref(g)), self.handle, "blink_get_plan")
-        return {"col_strip": c.value, "row_block": r.value, "group": g.value}
+                                    ctypes.byref(g), ctypes.byref(lp)), self.handle, "blink_get_plan")
+        return {"col_strip": c.value, "row_block": r.value, "group": g.value, "col_loop": lp.value}
 
     def set_plan(self, grid_n: int, weighting: int = 0, col_strip: int = 0, row_block: int = 0, group: int = 0,
-                 precision: int = PREC_FP32):
-        _check(lib().blink_set_plan(self.handle, grid_n, weighting, precision, col_strip, row_block, group),
+                 precision: int = PREC_FP32, col_loop: int = 1):
+        _check(lib().blink_set_plan(self.handle, grid_n, weighting, precision, col_strip, row_block, group, col_loop),
                self.handle, "blink_set_plan")
 
     def save_plans(self, path: str, sizes=(256, 512, 1024, 2048, 4096), precisions=PRECISIONS):
@@ -253,7 +253,7 @@ class Context:
 
     def load_plans(self, path: str):
         """Apply the plans of this device from a file written by save_plans (keys without a
-        precision field are FP32 plans)."""
+        precision field are FP32 plans; plans without col_loop take one strip per workgroup)."""
         import json
         torch = self._torch()
         name = torch.cuda.get_device_properties(self.device).gcnArchName
@@ -264,7 +264,8 @@ class Context:
             else:
                 dev, n, w, prec = "/".join(parts[:-2]), parts[-2], parts[-1], str(PREC_FP32)
             if dev == name:
-                self.set_plan(int(n), int(w), p["col_strip"], p["row_block"], p["group"], precision=int(prec))
+                self.set_plan(int(n), int(w), p["col_strip"], p["row_block"], p["group"], precision=int(prec),
+                              col_loop=p.get("col_loop", 1))
 
     def autotune_image_batch(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float, weighting: int = 0,
                              precision: int = PREC_FP32, shift: bool = True, out=None, workspace=None, stream=None):
@@ -284,14 +285,14 @@ class Context:
         wsum = torch.empty((T, C, P), dtype=torch.float64, device=dev)
         nout = torch.empty((T, C), dtype=torch.int32, device=dev)
         ws = self._workspace(image_batch_workspace_size(T, C, P, B, N, weighting, precision), workspace)
-        c, r, g, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        c, r, g, lp, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         st = lib().blink_autotune_image_batch(self.handle, _ptr(vis), _ptr(flags), _ptr(uvw_m), _ptr(freq_hz), T, C,
                                               P, B, N, float(pixel_scale), int(weighting), int(precision),
                                               int(bool(shift)), _ptr(out), _ptr(wsum), _ptr(nout), _ptr(ws),
                                               ws.numel(), self._stream(stream), ctypes.byref(c), ctypes.byref(r),
-                                              ctypes.byref(g), ctypes.byref(ms))
+                                              ctypes.byref(g), ctypes.byref(lp), ctypes.byref(ms))
         _check(st, self.handle, "blink_autotune_image_batch")
-        return {"col_strip": c.value, "row_block": r.value, "group": g.value}, ms.value
+        return {"col_strip": c.value, "row_block": r.value, "group": g.value, "col_loop": lp.value}, ms.value
 
     # -- uneven batches (one descriptor per image)
     def _desc_args(self, desc, vis, uvw_m, flags, images, weighting, precision, shift, weight_sum, n_out, status,

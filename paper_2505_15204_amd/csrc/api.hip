@@ -27,7 +27,7 @@ struct blink_ctx_s {
   // execution plan per (log2 N, weighting, precision form): fused-kernel strip width, row
   // transforms per workgroup, images per column/row launch pair (0 = as many as the workspace holds)
   struct Plan {
-    int col_strip = 0, row_tpb = 0, group = 0;
+    int col_strip = 0, row_tpb = 0, group = 0, col_loop = 1;
   } plan[13][2][kPrecForms];
   // descriptor-path plan (blink_set_desc_plan) and device facts
   int desc_block = 512, desc_workgroups = 0;
@@ -164,6 +164,8 @@ struct ImageLayout {
 // The fused path keeps at most kMaxGroupImages half-spectrum intermediates per launch pair
 // unless a plan asks for more.
 constexpr size_t kMaxGroupImages = 256;
+// Largest number of strips one workgroup of the fused column kernel takes in turn (plan col_loop).
+constexpr int kMaxColLoop = 64;
 
 int min_col_strip(int logn, int uniform) {
   int opts[4];
@@ -358,6 +360,7 @@ blink_status blink_create(blink_ctx* out, int hip_device) {
         ctx->plan[l][u][pf].col_strip = col[0];
         ctx->plan[l][u][pf].row_tpb = best;
         ctx->plan[l][u][pf].group = 0;
+        ctx->plan[l][u][pf].col_loop = 1;
       }
     }
   }
@@ -627,6 +630,7 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
     ca.H = (float2*)(ws + L.H);
     ca.occ = ba.occ;
     ca.dft_ops = ctx->dft_ops;
+    ca.col_loop = plan.col_loop;
     const int n_img = q * P;
     blink::RowArgs ra{};
     ra.H = ca.H;
@@ -1132,7 +1136,7 @@ blink_status blink_plan_options(int grid_n, int weighting, int* col_strips, int*
 }
 
 blink_status blink_get_plan(blink_ctx ctx, int grid_n, int weighting, int precision, int* col_strip, int* row_block,
-                            int* group) {
+                            int* group, int* col_loop) {
   const int logn = log2_exact(grid_n);
   if (logn < 0) return fail(ctx, BLINK_ERR_SIZE, "grid_n=%d unsupported", grid_n);
   if (!ctx || (weighting != 0 && weighting != 1) || !valid_precision(precision)) return BLINK_ERR_ARG;
@@ -1140,14 +1144,17 @@ blink_status blink_get_plan(blink_ctx ctx, int grid_n, int weighting, int precis
   if (col_strip) *col_strip = p.col_strip;
   if (row_block) *row_block = p.row_tpb;
   if (group) *group = p.group;
+  if (col_loop) *col_loop = p.col_loop;
   return BLINK_OK;
 }
 
 blink_status blink_set_plan(blink_ctx ctx, int grid_n, int weighting, int precision, int col_strip, int row_block,
-                            int group) {
+                            int group, int col_loop) {
   const int logn = log2_exact(grid_n);
   if (logn < 0) return fail(ctx, BLINK_ERR_SIZE, "grid_n=%d unsupported", grid_n);
   if (!ctx || (weighting != 0 && weighting != 1) || group < 0 || !valid_precision(precision)) return BLINK_ERR_ARG;
+  if (col_loop < 1 || col_loop > kMaxColLoop)
+    return fail(ctx, BLINK_ERR_ARG, "col_loop=%d outside 1..%d", col_loop, kMaxColLoop);
   int col[4], row[4];
   const int nc = blink::col_strip_options(logn, weighting != 0, col);
   const int nr = blink::row_block_options(logn, row);
@@ -1161,6 +1168,7 @@ blink_status blink_set_plan(blink_ctx ctx, int grid_n, int weighting, int precis
   p.col_strip = col_strip;
   p.row_tpb = row_block;
   p.group = group;
+  p.col_loop = col_loop;
   return BLINK_OK;
 }
 
@@ -1169,7 +1177,7 @@ blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32* vis, co
                                         int grid_n, double pixel_scale, int weighting, int precision, int shift,
                                         float* images, double* weight_sum, int32_t* n_out, void* workspace,
                                         size_t workspace_bytes, void* hip_stream, int* col_strip, int* row_block,
-                                        int* group, double* best_ms) {
+                                        int* group, int* col_loop, double* best_ms) {
   int logn = 0;
   blink_status st = check_problem(ctx, vis, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting, images,
                                   workspace, &logn);
@@ -1193,31 +1201,46 @@ blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32* vis, co
   double best = 1e300;
   auto best_plan = saved;
   blink_status result = BLINK_OK;
+  auto& p = ctx->plan[logn][weighting][precision];
+  // time the context's current plan for (grid_n, weighting, precision): best of two runs after one
+  auto time_plan = [&]() {
+    double t = 1e300;
+    for (int rep = 0; rep < 3 && result == BLINK_OK; ++rep) {
+      hipError_t he = hipEventRecord(e0, s);
+      result = blink_image_batch(ctx, vis, flags, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting,
+                                 precision, shift, images, weight_sum, n_out, workspace, workspace_bytes, hip_stream);
+      if (he == hipSuccess) he = hipEventRecord(e1, s);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess && result == BLINK_OK) result = hip_fail(ctx, he, "autotune timing");
+      if (rep > 0 && ms < t) t = ms;        // the first run warms caches and code
+    }
+    if (result == BLINK_OK && t < best) {
+      best = t;
+      best_plan = p;
+    }
+  };
+  // every (group, strip width, row block) with one strip per column workgroup, then 2, 4, .. 16
+  // strips per workgroup on the best of those
   for (int gi = 0; gi < 5 && result == BLINK_OK; ++gi) {
     for (int ci = 0; ci < nc && result == BLINK_OK; ++ci) {
       for (int ri = 0; ri < nr && result == BLINK_OK; ++ri) {
-        auto& p = ctx->plan[logn][weighting][precision];
         p.col_strip = col[ci];
         p.row_tpb = row[ri];
         p.group = groups[gi];
-        double t = 1e300;
-        for (int rep = 0; rep < 3 && result == BLINK_OK; ++rep) {
-          hipError_t he = hipEventRecord(e0, s);
-          result = blink_image_batch(ctx, vis, flags, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting,
-                                     precision, shift, images, weight_sum, n_out, workspace, workspace_bytes,
-                                     hip_stream);
-          if (he == hipSuccess) he = hipEventRecord(e1, s);
-          if (he == hipSuccess) he = hipEventSynchronize(e1);
-          float ms = 0.f;
-          if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-          if (he != hipSuccess && result == BLINK_OK) result = hip_fail(ctx, he, "autotune timing");
-          if (rep > 0 && ms < t) t = ms;        // the first run warms caches and code
-        }
-        if (result == BLINK_OK && t < best) {
-          best = t;
-          best_plan = p;
-        }
+        p.col_loop = 1;
+        time_plan();
       }
+    }
+  }
+  if (result == BLINK_OK) {
+    const auto first = best_plan;
+    const int nstrips = (1 << logn) / 2 / first.col_strip;
+    for (int loop = 2; loop <= 16 && loop <= nstrips && result == BLINK_OK; loop *= 2) {
+      p = first;
+      p.col_loop = loop;
+      time_plan();
     }
   }
   (void)hipEventDestroy(e0);
@@ -1231,6 +1254,7 @@ blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32* vis, co
   if (col_strip) *col_strip = best_plan.col_strip;
   if (row_block) *row_block = best_plan.row_tpb;
   if (group) *group = best_plan.group;
+  if (col_loop) *col_loop = best_plan.col_loop;
   if (best_ms) *best_ms = best;
   return result;
 }

@@ -144,26 +144,31 @@ __device__ inline void bin_visibilities(const double* __restrict__ uvw, const ui
 // Accumulates the placements [o0, o1) of strip `strip` into the LDS strip buffer (column c at
 // sbuf[c*stride + pad(kv)] when PADDED, else sbuf[c*stride + kv]); V are the image's
 // visibilities; the mirrored placement takes the conjugate; `modulate` applies (-1)^(ku+kv).
+// place_one adds one placement record r (with its visibility v) to the strip.
+template <int LOGN, int S, bool PADDED, bool COUNT>
+__device__ __forceinline__ void place_one(int2 r, float2 val, int strip, int stride, bool modulate, float2* sbuf,
+                                          unsigned* scnt) {
+  constexpr int N = 1 << LOGN;
+  const int kv = r.x >> LOGN, ku = r.x & (N - 1);
+  if (r.y < 0) val.y = -val.y;
+  if (modulate && ((kv + ku) & 1)) {
+    val.x = -val.x;
+    val.y = -val.y;
+  }
+  const int col = ku - strip * S;
+  float2* dst = sbuf + col * stride + (PADDED ? pad_index(kv) : kv);
+  atomicAdd(&dst->x, val.x);
+  atomicAdd(&dst->y, val.y);
+  if constexpr (COUNT) atomicAdd(&scnt[col * N + kv], 1u);
+}
+
 template <int LOGN, int S, bool PADDED, bool COUNT>
 __device__ __forceinline__ void scatter_strip(const int2* __restrict__ plc, int o0, int o1,
                                               const float2* __restrict__ V, int strip, int stride,
                                               bool modulate, float2* sbuf, unsigned* scnt) {
-  constexpr int N = 1 << LOGN;
   for (int i = o0 + (int)threadIdx.x; i < o1; i += blockDim.x) {
     const int2 r = plc[i];
-    const int kv = r.x >> LOGN, ku = r.x & (N - 1);
-    const int b = r.y & 0x7fffffff;
-    float2 val = V[b];
-    if (r.y < 0) val.y = -val.y;
-    if (modulate && ((kv + ku) & 1)) {
-      val.x = -val.x;
-      val.y = -val.y;
-    }
-    const int col = ku - strip * S;
-    float2* dst = sbuf + col * stride + (PADDED ? pad_index(kv) : kv);
-    atomicAdd(&dst->x, val.x);
-    atomicAdd(&dst->y, val.y);
-    if constexpr (COUNT) atomicAdd(&scnt[col * N + kv], 1u);
+    place_one<LOGN, S, PADDED, COUNT>(r, V[r.y & 0x7fffffff], strip, stride, modulate, sbuf, scnt);
   }
 }
 
@@ -211,7 +216,7 @@ __device__ __forceinline__ void store_strip(const float2* sbuf, int strip, float
     const float2* src = sbuf + c * NP + pad_index(y0);
     float2* dst = Hi + (size_t)y0 * HALF + strip * S + c;
     const bool real_only = REAL0 && strip == 0 && c == 0;
-#pragma unroll 4
+#pragma unroll
     for (int j = 0; j < ITER; ++j) {
       float2 val = src[pad_offset(j * RPI)];
       if (real_only) val.y = 0.f;
@@ -289,6 +294,104 @@ __device__ __forceinline__ void grid_colfft_task(const float2* __restrict__ V, c
     __syncthreads();
   }
   strip_fft_store<LOGN, S, PREC, NT, true>(sbuf, strip, Hi, tw, sp);
+}
+
+// ---------------------------------------------------------------- pipelined strips of one image
+// The strips strip0, strip0 + dstrip, ... (< nstrips) of one image, each as grid_colfft_task
+// does it, with the global loads of the placements software-pipelined across strips: the first
+// PF*NT placement records of the strip after next and the visibilities of the next strip are
+// requested before the current strip's column FFT and store, so they arrive while the workgroup
+// computes and the scatter of the next strip starts from registers. Placements beyond the first
+// PF*NT of a strip are loaded in the scatter as in grid_colfft_task. s_off (LDS, nstrips + 1
+// ints) holds the image's strip offsets, copied by the caller before the first barrier.
+//
+// Every prefetch load of an existing strip is issued unconditionally (slots past the strip's end
+// read record 0 and visibility 0 of the image, in bounds whenever B > 0) and whether a slot holds
+// a placement is decided where it is consumed, from the strip offsets, so the loads are never
+// folded into branches. With B = 0 (no visibilities, an empty placement list) nothing is
+// requested: `pf_strips` is nstrips when B > 0, else 0.
+// With the strip store one straight run of stores, the number of memory operations after each
+// prefetch is fixed: consuming a prefetched value waits only for the loads before it, never for
+// the previous strip's stores (the memory counter is in order), and those stores drain while the
+// next strip is gridded and transformed.
+template <int PF>
+struct StripPrefetch {
+  int2 r[PF];       // placement records of slots threadIdx.x + j*NT of the strip
+  float2 v[PF];     // their visibilities (requested by prefetch_vis)
+};
+
+template <int PF, int NT>
+__device__ __forceinline__ bool prefetch_slot_used(const int* s_off, int strip, int nstrips, int j) {
+  return strip < nstrips && s_off[strip] + (int)threadIdx.x + j * NT < s_off[strip + 1];
+}
+
+template <int PF, int NT>
+__device__ __forceinline__ void prefetch_records(const int2* __restrict__ plc, const int* s_off, int strip,
+                                                 int nstrips, StripPrefetch<PF>& p) {
+  if (strip >= nstrips) return;   // nothing left to request (uniform over the workgroup)
+#pragma unroll
+  for (int j = 0; j < PF; ++j)
+    p.r[j] = plc[prefetch_slot_used<PF, NT>(s_off, strip, nstrips, j) ? s_off[strip] + (int)threadIdx.x + j * NT : 0];
+}
+
+template <int PF, int NT>
+__device__ __forceinline__ void prefetch_vis(const float2* __restrict__ V, const int* s_off, int strip, int nstrips,
+                                             StripPrefetch<PF>& p) {
+  if (strip >= nstrips) return;
+#pragma unroll
+  for (int j = 0; j < PF; ++j)
+    p.v[j] = V[prefetch_slot_used<PF, NT>(s_off, strip, nstrips, j) ? (p.r[j].y & 0x7fffffff) : 0];
+}
+
+template <int LOGN, int S, bool UNIFORM, int PREC, int NT, int PF>
+__device__ __forceinline__ void grid_colfft_strips(const float2* __restrict__ V, const int2* __restrict__ plc,
+                                                   const int* s_off, int strip0, int dstrip, int nstrips,
+                                                   int pf_strips, bool shift, float2* __restrict__ Hi, int* occ_img,
+                                                   const float2* __restrict__ tw, float2* sbuf, unsigned* scnt,
+                                                   int* s_tmp, SplitCtx sp = {}) {
+  using P = FftPlan<LOGN>;
+  constexpr int N = P::N, NP = P::NP;
+  constexpr bool SPLIT = PREC != kPrecFp32 && LOGN >= 4;
+  StripPrefetch<PF> cur, nxt;
+  __syncthreads();   // s_off is visible
+  prefetch_records<PF, NT>(plc, s_off, strip0, pf_strips, cur);
+  prefetch_vis<PF, NT>(V, s_off, strip0, pf_strips, cur);
+  prefetch_records<PF, NT>(plc, s_off, strip0 + dstrip, pf_strips, nxt);
+  // Wait for the prologue's loads here (vmcnt(0) only): the loop then starts every strip with
+  // the same loads in flight whether it comes from here or from the previous strip, so the waits
+  // inside it count past the previous strip's stores instead of draining them.
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  for (int strip = strip0; strip < nstrips; strip += dstrip) {
+#pragma unroll 4
+    for (int i = threadIdx.x; i < S * NP; i += NT) sbuf[i] = make_float2(0.f, 0.f);
+    if constexpr (UNIFORM)
+      for (int i = threadIdx.x; i < S * N; i += NT) scnt[i] = 0u;
+    if (threadIdx.x == 0) {
+      *s_tmp = 0;
+      if constexpr (SPLIT) *sp.s_max = 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PF; ++j)
+      if (prefetch_slot_used<PF, NT>(s_off, strip, nstrips, j))
+        place_one<LOGN, S, true, UNIFORM>(cur.r[j], cur.v[j], strip, NP, shift, sbuf, scnt);
+    const int o1 = s_off[strip + 1];
+    scatter_strip<LOGN, S, true, UNIFORM>(plc, cmin(s_off[strip] + PF * NT, o1), o1, V, strip, NP, shift, sbuf,
+                                          scnt);
+    __syncthreads();
+    if constexpr (UNIFORM) {
+      int occ = uniform_divide<LOGN, S, true, NT>(sbuf, scnt, NP, strip == 0 ? 1 : 2, 2);
+      block_add_to_global(occ, s_tmp, occ_img);
+      __syncthreads();
+    }
+    // requests for the next strips, answered during this strip's transform and store
+#pragma unroll
+    for (int j = 0; j < PF; ++j) cur.r[j] = nxt.r[j];
+    prefetch_vis<PF, NT>(V, s_off, strip + dstrip, pf_strips, cur);
+    prefetch_records<PF, NT>(plc, s_off, strip + 2 * dstrip, pf_strips, nxt);
+    strip_fft_store<LOGN, S, PREC, NT, true>(sbuf, strip, Hi, tw, sp);
+    __syncthreads();   // the store's reads of the strip buffer are done before it is cleared again
+  }
 }
 
 // ---------------------------------------------------------------- row task

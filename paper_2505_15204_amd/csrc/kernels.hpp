@@ -13,13 +13,14 @@ namespace blink {
 
 // ---------------------------------------------------------------- configuration
 // Largest strip width (columns per workgroup) of the fused column kernel that fits 1024 threads
-// and the 160 KB of LDS (strip buffer, twiddle table and, for uniform weighting, counts).
+// and the 160 KB of LDS (strip buffer, twiddle table, strip offsets and, for uniform weighting,
+// counts).
 template <int LOGN, bool UNIFORM>
 struct ColSmax {
   using P = FftPlan<LOGN>;
   static constexpr int N = P::N;
   static constexpr int per_col = P::NP * 8 + (UNIFORM ? N * 4 : 0);
-  static constexpr int avail = kLdsBytes - tw_size(LOGN) * 8 - 1024;
+  static constexpr int avail = kLdsBytes - tw_size(LOGN) * 8 - (N / 2 + 1) * 4 - 1024;
   static constexpr int value = pow2_floor(cmin(cmin(N / 2, 1024 / P::T), avail / per_col));
 };
 
@@ -47,6 +48,9 @@ struct RowDefault {
   static constexpr int value = cmin(P::N / 2, (256 / P::T) > 0 ? 256 / P::T : 1);
 };
 
+// Placement records per thread that the fused column kernel requests one strip ahead.
+constexpr int kColPrefetch = 2;
+
 // Workgroup size for `work` FFT threads: exact for FP32, whole waves for the split forms.
 __host__ __device__ constexpr int fft_block(int work, int prec) {
   return prec == kPrecFp32 ? work : ((work + 63) / 64) * 64;
@@ -62,17 +66,21 @@ __global__ __launch_bounds__(fft_block(S * FftPlan<LOGN>::T, PREC)) void k_grid_
   __shared__ float2 sbuf[S * NP];
   __shared__ float2 stw[TW];
   __shared__ unsigned scnt[UNIFORM ? S * N : 1];
+  __shared__ int s_off[(N / 2) / S + 1];
   __shared__ int s_tmp;
   __shared__ unsigned s_max;
-  // blockIdx.x = slot of the image in this launch's group; the image is img0 + slot in the chunk
-  const int slot = blockIdx.x, img = a.img0 + slot, strip = blockIdx.y;
+  // blockIdx.x = slot of the image in this launch's group; the image is img0 + slot in the chunk.
+  // The workgroup takes the strips blockIdx.y, blockIdx.y + gridDim.y, ... of that image.
+  const int slot = blockIdx.x, img = a.img0 + slot;
   const int tcl = img / a.P;
   const int nstrips = (N / 2) / S;
   for (int i = threadIdx.x; i < TW; i += NT) stw[i] = twg[i];   // visible after the task's first barrier
   const int* so = a.strip_off + (size_t)tcl * (nstrips + 1);
-  grid_colfft_task<LOGN, S, UNIFORM, PREC, NT>(a.vis + (size_t)img * a.B, a.plc + (size_t)tcl * 2 * a.B, so[strip],
-                                           so[strip + 1], strip, a.shift != 0, a.H + (size_t)slot * N * (N / 2),
-                                           a.occ + img, stw, sbuf, scnt, &s_tmp, SplitCtx{&s_max, a.dft_ops});
+  for (int i = threadIdx.x; i <= nstrips; i += NT) s_off[i] = so[i];   // visible after the task's first barrier
+  grid_colfft_strips<LOGN, S, UNIFORM, PREC, NT, kColPrefetch>(
+      a.vis + (size_t)img * a.B, a.plc + (size_t)tcl * 2 * a.B, s_off, blockIdx.y, gridDim.y, nstrips,
+      a.B > 0 ? nstrips : 0, a.shift != 0,
+      a.H + (size_t)slot * N * (N / 2), a.occ + img, stw, sbuf, scnt, &s_tmp, SplitCtx{&s_max, a.dft_ops});
 }
 
 // ---------------------------------------------------------------- fused conv gridding + column FFT
@@ -203,7 +211,8 @@ struct ForPrec {
   template <int LOGN, int S, bool U>
   static hipError_t col_one(const ColArgs* a, int n_img, const float2* tw, hipStream_t s) {
     if constexpr (S >= 1) {
-      dim3 grid(n_img, ((1 << LOGN) / 2) / S);
+      const int nstrips = ((1 << LOGN) / 2) / S, loop = a->col_loop > 1 ? a->col_loop : 1;
+      dim3 grid(n_img, (nstrips + loop - 1) / loop);
       k_grid_colfft<LOGN, S, U, PREC><<<grid, fft_block(S * FftPlan<LOGN>::T, PREC), 0, s>>>(*a, tw);
       return hipGetLastError();
     } else {

@@ -63,6 +63,7 @@ struct ColArgs {
   int* occ;                 // [Q][P]
   const uint4* dft_ops;     // DFT operand table of the split forms
   int rec_stride;           // convolutional path: records per (t,c) pair (plc holds ConvRec)
+  int col_loop;             // strips each column workgroup takes in turn (<= 1: one strip each)
 };
 // `prec` selects the FFT form: BLINK_PREC_FP32 or a split matrix-core precision.
 hipError_t launch_grid_colfft(const ColArgs& a, int n_img, int strip, int prec, const float2* tw, hipStream_t s);

@@ -36,6 +36,11 @@ def rel_l2(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
+def restore(ctx, N, weighting, plan, precision=0):
+    ctx.set_plan(N, weighting, plan["col_strip"], plan["row_block"], plan["group"], precision=precision,
+                 col_loop=plan["col_loop"])
+
+
 def make(torch, N, weighting, C, P):
     spec = synth.Spec(f"plans-{N}", 21, 128, 1, P, synth.vcs_channels()[:C * 97:97], N, synth.ARCMIN * 1024 / N,
                       20, 0.1, weighting=weighting)
@@ -59,20 +64,27 @@ def test_every_plan_matches_oracle(torch, ctx, N, weighting, C, P):
     n_img = C * P
     groups = sorted({0, 1, max(1, n_img - 1)})
     default = ctx.get_plan(N, weighting)
+
+    def check(col, row, grp, loop):
+        say(f"plan N={N} w={weighting} col_strip={col} row_block={row} group={grp} col_loop={loop}")
+        ctx.set_plan(N, weighting, col, row, grp, col_loop=loop)
+        res = ctx.blink_image_batch(vis, flags, uvw, freq, N, spec.pixel_scale, weighting)
+        assert np.array_equal(res["weight_sum"].cpu().numpy(), ref["weight_sum"])
+        img = res["images"].cpu().numpy()
+        for idx in np.ndindex(1, C, P):
+            e = rel_l2(img[idx], ref["images"][idx])
+            assert e <= IMAGE_TOL, (col, row, grp, loop, idx, e)
     try:
         for col in cols:
             for row in rows:
                 for grp in groups:
-                    say(f"plan N={N} w={weighting} col_strip={col} row_block={row} group={grp}")
-                    ctx.set_plan(N, weighting, col, row, grp)
-                    res = ctx.blink_image_batch(vis, flags, uvw, freq, N, spec.pixel_scale, weighting)
-                    assert np.array_equal(res["weight_sum"].cpu().numpy(), ref["weight_sum"])
-                    img = res["images"].cpu().numpy()
-                    for idx in np.ndindex(1, C, P):
-                        e = rel_l2(img[idx], ref["images"][idx])
-                        assert e <= IMAGE_TOL, (col, row, grp, idx, e)
+                    check(col, row, grp, 1)
+            # strips per column workgroup: a power of two, one that does not divide the strip
+            # count, and more than there are strips (one workgroup per image)
+            for loop in (4, 3, 64):
+                check(col, rows[0], 0, loop)
     finally:
-        ctx.set_plan(N, weighting, default["col_strip"], default["row_block"], default["group"])
+        restore(ctx, N, weighting, default)
 
 
 def test_set_plan_rejects_uncompiled_options(torch, ctx):
@@ -83,6 +95,9 @@ def test_set_plan_rejects_uncompiled_options(torch, ctx):
         ctx.set_plan(1024, 0, 16, 5, 0)
     with pytest.raises(blink.BlinkError):
         ctx.set_plan(1024, 0, 16, 4, -1)
+    for loop in (0, 65):
+        with pytest.raises(blink.BlinkError):
+            ctx.set_plan(1024, 0, 16, 4, 0, col_loop=loop)
 
 
 def test_autotuner_picks_a_compiled_plan_and_leaves_valid_images(torch, ctx, tmp_path):
@@ -95,14 +110,15 @@ def test_autotuner_picks_a_compiled_plan_and_leaves_valid_images(torch, ctx, tmp
         plan, ms = ctx.autotune_image_batch(vis, flags, uvw, freq, 1024, spec.pixel_scale, 0, out=out)
         cols, rows = blink.plan_options(1024, 0)
         assert plan["col_strip"] in cols and plan["row_block"] in rows and plan["group"] > 0 and ms > 0
+        assert plan["col_loop"] in (1, 2, 4, 8, 16)
         assert ctx.get_plan(1024, 0) == plan
         img = out.cpu().numpy()
         for idx in np.ndindex(1, 3, 2):
             assert rel_l2(img[idx], ref["images"][idx]) <= IMAGE_TOL
         path = tmp_path / "plans.json"
         ctx.save_plans(str(path))
-        ctx.set_plan(1024, 0, default["col_strip"], default["row_block"], default["group"])
+        restore(ctx, 1024, 0, default)
         ctx.load_plans(str(path))
         assert ctx.get_plan(1024, 0) == plan
     finally:
-        ctx.set_plan(1024, 0, default["col_strip"], default["row_block"], default["group"])
+        restore(ctx, 1024, 0, default)

@@ -123,7 +123,8 @@ def test_split_image_batch(torch, ctx, generated, name, spec, prec, pname):
 
 @pytest.mark.parametrize("prec,pname", SPLITS, ids=[s[1] for s in SPLITS])
 def test_split_every_plan(torch, ctx, generated, prec, pname):
-    """Every compiled (strip width, row block) variant of the split kernels at 1024^2 and 4096^2."""
+    """Every compiled (strip width, row block) variant of the split kernels at 1024^2 and 4096^2, and
+    four strips per column workgroup."""
     import paper_2505_15204_amd as blink
     for name, spec in (PROBLEMS[3], PROBLEMS[5]):
         prob, ref = generated(name, spec)
@@ -133,15 +134,16 @@ def test_split_every_plan(torch, ctx, generated, prec, pname):
         saved = ctx.get_plan(N, spec.weighting, prec)
         try:
             for col in cols:
-                for row in rows:
-                    say(f"{pname} plan N={N} col={col} row={row}")
-                    ctx.set_plan(N, spec.weighting, col, row, 0, precision=prec)
+                for row, loop in [(r, 1) for r in rows] + [(rows[0], 4)]:
+                    say(f"{pname} plan N={N} col={col} row={row} col_loop={loop}")
+                    ctx.set_plan(N, spec.weighting, col, row, 0, precision=prec, col_loop=loop)
                     img = ctx.blink_image_batch(vis, flags, uvw, freq, N, spec.pixel_scale, spec.weighting,
                                                 precision=prec)["images"].cpu().numpy()
                     for idx in np.ndindex(spec.T, spec.C, spec.P):
-                        assert rel_l2(img[idx], ref["images"][idx]) <= MIXED_TOL, (col, row, idx)
+                        assert rel_l2(img[idx], ref["images"][idx]) <= MIXED_TOL, (col, row, loop, idx)
         finally:
-            ctx.set_plan(N, spec.weighting, saved["col_strip"], saved["row_block"], saved["group"], precision=prec)
+            ctx.set_plan(N, spec.weighting, saved["col_strip"], saved["row_block"], saved["group"], precision=prec,
+                         col_loop=saved["col_loop"])
 
 
 def test_split_grid_zero_and_huge_values(torch, ctx):
