@@ -53,6 +53,11 @@ def load(path: str):
     L.blink_ref_image_batch.restype = i32
     L.blink_ref_image_batch.argtypes = [P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32,
                                         P, P, P, P, P, i32]
+    L.blink_ref_image_batch_c128.restype = i32
+    L.blink_ref_image_batch_c128.argtypes = [P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32,
+                                             P, P, P, P, P, i32]
+    L.blink_ref_correct_vis.restype = i32
+    L.blink_ref_correct_vis.argtypes = [P, P, P, i32, i32, i32, i32, P, i32, f64, f64, P]
     L.blink_ref_max_threads.restype = i32
     L.blink_ref_max_threads.argtypes = []
     L.blink_ref_es_kernel.restype = f64
@@ -165,6 +170,47 @@ class Oracle:
             raise ValueError(f"blink_ref_image_batch failed with code {rc}")
         return {"images": images, "weight_sum": W, "n_out": nout, "cell_idx": cell, "counts": counts}
 
+    def image_batch_c128(self, vis, flags, uvw, freq_hz, grid_n, pixel_scale, weighting=0, shift=True,
+                         n_threads=0):
+        """image_batch on complex double visibilities [T][C][P][B] (no rounding to complex64)."""
+        v = _c(vis, np.complex128)
+        T, C, P, B = v.shape
+        f = None if flags is None else _c(flags, np.uint8)
+        u = _c(uvw, np.float64)
+        fr = _c(freq_hz, np.float64)
+        N = int(grid_n)
+        images = np.empty((T, C, P, N, N), dtype=np.float64)
+        W = np.empty((T, C, P), dtype=np.float64)
+        nout = np.empty((T, C), dtype=np.int32)
+        rc = self.L.blink_ref_image_batch_c128(_ptr(v), _ptr(f), _ptr(u), _ptr(fr), T, C, P, B, N,
+                                              float(pixel_scale), int(weighting), int(bool(shift)),
+                                              _ptr(images), _ptr(W), _ptr(nout), None, None, int(n_threads))
+        if rc != 0:
+            raise ValueError(f"blink_ref_image_batch_c128 failed with code {rc}")
+        return {"images": images, "weight_sum": W, "n_out": nout}
+
+    def correct_vis(self, vis, uvw, freq_hz, gains=None, l0=0.0, m0=0.0):
+        """Corrected visibilities (complex128 [T][C][P][B]): per-antenna factors gains
+        [C][P][A] (complex64, or None) and the phase-centre rotation to (l0, m0)."""
+        v = _c(vis, np.complex64)
+        T, C, P, B = v.shape
+        u = _c(uvw, np.float64)
+        fr = _c(freq_hz, np.float64)
+        g = None if gains is None else _c(gains, np.complex64)
+        A = 0 if g is None else g.shape[-1]
+        out = np.empty((T, C, P, B), dtype=np.complex128)
+        rc = self.L.blink_ref_correct_vis(_ptr(v), _ptr(u), _ptr(fr), T, C, P, B, _ptr(g), int(A), float(l0),
+                                         float(m0), _ptr(out))
+        if rc != 0:
+            raise ValueError(f"blink_ref_correct_vis failed with code {rc}")
+        return out
+
+    def image_batch_corrected(self, vis, flags, uvw, freq_hz, grid_n, pixel_scale, weighting=0, gains=None,
+                              l0=0.0, m0=0.0, shift=True, n_threads=0):
+        """Corrections, then the whole path on the complex double corrected visibilities."""
+        vc = self.correct_vis(vis, uvw, freq_hz, gains, l0, m0)
+        return self.image_batch_c128(vc, flags, uvw, freq_hz, grid_n, pixel_scale, weighting, shift, n_threads)
+
     def max_threads(self) -> int:
         return int(self.L.blink_ref_max_threads())
 
@@ -256,6 +302,18 @@ def ifft2d(*a, **k):
 
 def image_batch(*a, **k):
     return default().image_batch(*a, **k)
+
+
+def image_batch_c128(*a, **k):
+    return default().image_batch_c128(*a, **k)
+
+
+def correct_vis(*a, **k):
+    return default().correct_vis(*a, **k)
+
+
+def image_batch_corrected(*a, **k):
+    return default().image_batch_corrected(*a, **k)
 
 
 def max_threads() -> int:

@@ -30,13 +30,14 @@ double blink_ref_cells_per_metre(double freq_hz, int grid_n, double pixel_scale)
 }
 
 /* Section 6.2.4: nearest-cell placement with no convolution kernel; natural weighting by default.
- * Hermitian completion: the visibility of baseline (i,j) at (u,v) implies conj(V) at (-u,-v). */
-int blink_ref_grid(const float *vis, const uint8_t *flags, const double *uvw, int P, int B,
-                   double freq_hz, int grid_n, double pixel_scale, int weighting,
-                   double *grid, int32_t *counts, int32_t *cell_idx,
-                   double *weight_sum, int32_t *n_out)
+ * Hermitian completion: the visibility of baseline (i,j) at (u,v) implies conj(V) at (-u,-v).
+ * The visibilities come either as complex64 (vis32) or as complex double (vis64). */
+static int grid_one(const float *vis32, const double *vis64, const uint8_t *flags, const double *uvw,
+                    int P, int B, double freq_hz, int grid_n, double pixel_scale, int weighting,
+                    double *grid, int32_t *counts, int32_t *cell_idx,
+                    double *weight_sum, int32_t *n_out)
 {
-    if (!is_pow2(grid_n) || P < 1 || B < 0 || !vis || !uvw || !grid || !weight_sum || !n_out)
+    if (!is_pow2(grid_n) || P < 1 || B < 0 || !(vis32 || vis64) || !uvw || !grid || !weight_sum || !n_out)
         return 1;
     if (weighting != 0 && weighting != 1)
         return 1;
@@ -73,8 +74,9 @@ int blink_ref_grid(const float *vis, const uint8_t *flags, const double *uvw, in
         cnt[c2] += 1;
         ++kept;
         for (int p = 0; p < P; ++p) {
-            const float *v = vis + 2 * ((size_t)p * B + b);
-            double re = (double)v[0], im = (double)v[1];
+            const size_t at = 2 * ((size_t)p * B + b);
+            double re = vis64 ? vis64[at] : (double)vis32[at];
+            double im = vis64 ? vis64[at + 1] : (double)vis32[at + 1];
             double *g = grid + 2 * NN * (size_t)p;
             g[2 * c1] += re;
             g[2 * c1 + 1] += im;
@@ -104,6 +106,16 @@ int blink_ref_grid(const float *vis, const uint8_t *flags, const double *uvw, in
     *n_out = outside;
     free(cnt);
     return 0;
+}
+
+int blink_ref_grid(const float *vis, const uint8_t *flags, const double *uvw, int P, int B,
+                   double freq_hz, int grid_n, double pixel_scale, int weighting,
+                   double *grid, int32_t *counts, int32_t *cell_idx,
+                   double *weight_sum, int32_t *n_out)
+{
+    if (!vis) return 1;
+    return grid_one(vis, NULL, flags, uvw, P, B, freq_hz, grid_n, pixel_scale, weighting, grid, counts,
+                    cell_idx, weight_sum, n_out);
 }
 
 /* Textbook iterative radix-2 decimation-in-time FFT with the + sign of the inverse transform
@@ -200,14 +212,14 @@ int blink_ref_max_threads(void)
 #endif
 }
 
-int blink_ref_image_batch(const float *vis, const uint8_t *flags, const double *uvw,
-                          const double *freq_hz, int T, int C, int P, int B, int grid_n,
-                          double pixel_scale, int weighting, int shift, double *images,
-                          double *weight_sum, int32_t *n_out, int32_t *cell_idx,
-                          int32_t *counts, int n_threads)
+static int image_batch(const float *vis32, const double *vis64, const uint8_t *flags, const double *uvw,
+                       const double *freq_hz, int T, int C, int P, int B, int grid_n,
+                       double pixel_scale, int weighting, int shift, double *images,
+                       double *weight_sum, int32_t *n_out, int32_t *cell_idx,
+                       int32_t *counts, int n_threads)
 {
     if (!is_pow2(grid_n) || T < 0 || C < 0 || P < 1 || B < 0) return 1;
-    if (!vis || !uvw || !freq_hz || !images) return 1;
+    if (!(vis32 || vis64) || !uvw || !freq_hz || !images) return 1;
     if (weighting != 0 && weighting != 1) return 1;
     const int N = grid_n;
     const size_t NN = (size_t)N * N;
@@ -223,10 +235,11 @@ int blink_ref_image_batch(const float *vis, const uint8_t *flags, const double *
         if (!grid) { err = 2; continue; }
         double W = 0.0;
         int32_t nout = 0;
-        int rc = blink_ref_grid(vis + 2 * (size_t)tc * P * B, flags ? flags + (size_t)tc * B : NULL,
-                                uvw + 3 * (size_t)t * B, P, B, freq_hz[c], N, pixel_scale,
-                                weighting, grid, counts ? counts + (size_t)tc * NN : NULL,
-                                cell_idx ? cell_idx + (size_t)tc * B : NULL, &W, &nout);
+        const size_t at = 2 * (size_t)tc * P * B;
+        int rc = grid_one(vis32 ? vis32 + at : NULL, vis64 ? vis64 + at : NULL,
+                          flags ? flags + (size_t)tc * B : NULL, uvw + 3 * (size_t)t * B, P, B, freq_hz[c],
+                          N, pixel_scale, weighting, grid, counts ? counts + (size_t)tc * NN : NULL,
+                          cell_idx ? cell_idx + (size_t)tc * B : NULL, &W, &nout);
         for (int p = 0; rc == 0 && p < P; ++p) {
             rc = blink_ref_ifft2d(grid + 2 * NN * (size_t)p, N, W, shift,
                                   images + ((size_t)tc * P + p) * NN, NULL);
@@ -237,6 +250,84 @@ int blink_ref_image_batch(const float *vis, const uint8_t *flags, const double *
         free(grid);
     }
     return err;
+}
+
+int blink_ref_image_batch(const float *vis, const uint8_t *flags, const double *uvw,
+                          const double *freq_hz, int T, int C, int P, int B, int grid_n,
+                          double pixel_scale, int weighting, int shift, double *images,
+                          double *weight_sum, int32_t *n_out, int32_t *cell_idx,
+                          int32_t *counts, int n_threads)
+{
+    if (!vis) return 1;
+    return image_batch(vis, NULL, flags, uvw, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting, shift,
+                       images, weight_sum, n_out, cell_idx, counts, n_threads);
+}
+
+int blink_ref_image_batch_c128(const double *vis, const uint8_t *flags, const double *uvw,
+                               const double *freq_hz, int T, int C, int P, int B, int grid_n,
+                               double pixel_scale, int weighting, int shift, double *images,
+                               double *weight_sum, int32_t *n_out, int32_t *cell_idx,
+                               int32_t *counts, int n_threads)
+{
+    if (!vis) return 1;
+    return image_batch(NULL, vis, flags, uvw, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting, shift,
+                       images, weight_sum, n_out, cell_idx, counts, n_threads);
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Visibility corrections before gridding (Section 6.2.3): calibration
+ * solutions applied per antenna, then the geometric correction that moves the phase centre to the
+ * pointing direction (the paper does that step in the imager, where (u, v, w) are known). Cable
+ * length corrections are per-antenna phases and enter through the same per-antenna factors.
+ * Baseline b is the cross pair (i, j), i > j, b = i (i - 1) / 2 + j: the lower-triangular order
+ * in which the correlation step stores visibilities (Section 6.2.2), without autocorrelations.
+ * ------------------------------------------------------------------------------------------ */
+int blink_ref_correct_vis(const float *vis, const double *uvw, const double *freq_hz, int T, int C,
+                          int P, int B, const float *gains, int n_ant, double l0, double m0,
+                          double *out)
+{
+    if (T < 0 || C < 0 || P < 1 || B < 0 || !vis || !uvw || !freq_hz || !out) return 1;
+    if (gains && (n_ant < 2 || (long)n_ant * (n_ant - 1) / 2 != B)) return 1;
+    if (!(l0 * l0 + m0 * m0 < 1.0)) return 1;
+    const double n0 = sqrt(1.0 - l0 * l0 - m0 * m0);
+    /* antenna pair of every baseline, in baseline order */
+    int *ant_i = (int *)malloc(sizeof(int) * (size_t)(B > 0 ? B : 1));
+    int *ant_j = (int *)malloc(sizeof(int) * (size_t)(B > 0 ? B : 1));
+    if (!ant_i || !ant_j) { free(ant_i); free(ant_j); return 2; }
+    if (gains) {
+        int b = 0;
+        for (int i = 1; i < n_ant; ++i)
+            for (int j = 0; j < i; ++j, ++b) { ant_i[b] = i; ant_j[b] = j; }
+    }
+    for (int t = 0; t < T; ++t) {
+        for (int c = 0; c < C; ++c) {
+            const double cycles_per_metre = freq_hz[c] / SPEED_OF_LIGHT;
+            for (int b = 0; b < B; ++b) {
+                const double *x = uvw + 3 * ((size_t)t * B + b);
+                /* geometric delay of the new phase centre, in turns: (f/c)(u l0 + v m0 + w (n0 - 1)) */
+                const double turns = cycles_per_metre * (x[0] * l0 + x[1] * m0 + x[2] * (n0 - 1.0));
+                const double rot_re = cos(2.0 * M_PI * turns), rot_im = sin(2.0 * M_PI * turns);
+                for (int p = 0; p < P; ++p) {
+                    const size_t at = 2 * ((((size_t)t * C + c) * P + p) * B + b);
+                    double re = (double)vis[at], im = (double)vis[at + 1];
+                    if (gains) {
+                        /* J_i V conj(J_j) */
+                        const float *gi = gains + 2 * (((size_t)c * P + p) * n_ant + ant_i[b]);
+                        const float *gj = gains + 2 * (((size_t)c * P + p) * n_ant + ant_j[b]);
+                        const double ar = gi[0], ai = gi[1], br = gj[0], bi = -(double)gj[1];
+                        const double r1 = ar * re - ai * im, i1 = ar * im + ai * re;
+                        re = r1 * br - i1 * bi;
+                        im = r1 * bi + i1 * br;
+                    }
+                    out[at] = re * rot_re - im * rot_im;
+                    out[at + 1] = re * rot_im + im * rot_re;
+                }
+            }
+        }
+    }
+    free(ant_i);
+    free(ant_j);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------------------------

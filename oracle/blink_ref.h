@@ -75,6 +75,24 @@ int blink_ref_image_batch(const float *vis, const uint8_t *flags, const double *
                           double *weight_sum, int32_t *n_out, int32_t *cell_idx,
                           int32_t *counts, int n_threads);
 
+/* The same with complex double visibilities [T][C][P][B] (e.g. blink_ref_correct_vis output). */
+int blink_ref_image_batch_c128(const double *vis, const uint8_t *flags, const double *uvw,
+                               const double *freq_hz, int T, int C, int P, int B, int grid_n,
+                               double pixel_scale, int weighting, int shift, double *images,
+                               double *weight_sum, int32_t *n_out, int32_t *cell_idx,
+                               int32_t *counts, int n_threads);
+
+/* Visibility corrections before gridding (Section 6.2.3): for baseline b = (i, j), i > j,
+ * b = i (i - 1) / 2 + j, and channel c with frequency f,
+ *   V' = J[c][p][i] V conj(J[c][p][j]) exp(+2 pi i (f/c) (u l0 + v m0 + w (n0 - 1))),
+ * n0 = sqrt(1 - l0^2 - m0^2), (u, v, w) = uvw[t][b] in metres. A source at direction cosines
+ * (l0, m0) then has zero phase (it appears at the phase centre). gains: complex64 [C][P][n_ant]
+ * or NULL (all 1; n_ant ignored); with gains, B must equal n_ant (n_ant - 1) / 2.
+ * l0^2 + m0^2 < 1. vis complex64 [T][C][P][B]; out complex double [T][C][P][B]. */
+int blink_ref_correct_vis(const float *vis, const double *uvw, const double *freq_hz, int T, int C,
+                          int P, int B, const float *gains, int n_ant, double l0, double m0,
+                          double *out);
+
 /* Convolutional gridding (beyond the paper's nearest-cell placement, Section 6.2.4; the paper plans
  * a gridding kernel against aliasing, Section 10). Kernel: phi(z) = exp(beta (sqrt(1 - z^2) - 1))
  * for |z| < 1 ("exponential of semicircle", Barnett, Magland & af Klinteberg 2019), z = 2 d / W for

@@ -449,8 +449,81 @@ def pin_image_average(O):
     assert np.array_equal(O.image_average(same, 4)[:, :, 0], imgs[:, :, 0].astype(np.float64))
 
 
-CONV_PINS = [pin_image_average, pin_es_kernel_values, pin_es_transform, pin_conv_width1_is_nearest_cell, pin_conv_hermitian,
-             pin_conv_matches_direct_transform, pin_conv_batch_consistency]
+# ----------------------------------------------------------------------------- corrections
+
+def correction_problem(seed, n_ant=7, T=2, C=3, P=2):
+    """Random visibilities and non-coplanar baselines (w != 0) of n_ant antennas."""
+    g = np.random.default_rng(seed)
+    B = n_ant * (n_ant - 1) // 2
+    pos = g.uniform(-400.0, 400.0, size=(n_ant, 3))
+    pos[:, 2] = g.uniform(-40.0, 40.0, size=n_ant)
+    rows, cols = np.tril_indices(n_ant, k=-1)          # (1,0), (2,0), (2,1), ...: b = i(i-1)/2 + j
+    uvw = np.repeat((pos[rows] - pos[cols])[None], T, axis=0)
+    uvw[1:] += g.normal(scale=0.5, size=uvw[1:].shape)  # the baselines move a little in time
+    freq = 150.0e6 + 1.28e6 * np.arange(C)
+    vis = (g.normal(size=(T, C, P, B)) + 1j * g.normal(size=(T, C, P, B))).astype(np.complex64)
+    return vis, uvw, freq, rows, cols
+
+
+def pin_corrections_identity(O):
+    """Unit gains and no phase-centre offset leave the visibilities, and the images, unchanged."""
+    vis, uvw, freq, _, _ = correction_problem(40)
+    T, C, P, B = vis.shape
+    ones = np.ones((C, P, 7), dtype=np.complex64)
+    for gains in (None, ones):
+        vc = O.correct_vis(vis, uvw, freq, gains, 0.0, 0.0)
+        assert np.array_equal(vc, vis.astype(np.complex128))
+    a = O.image_batch(vis, None, uvw, freq, 32, 2.0e-3, 0)
+    b = O.image_batch_corrected(vis, None, uvw, freq, 32, 2.0e-3, 0, ones, 0.0, 0.0)
+    assert np.array_equal(a["images"], b["images"]) and np.array_equal(a["weight_sum"], b["weight_sum"])
+
+
+def pin_corrections_undo_gains(O):
+    """Visibilities corrupted by per-antenna gains, built as diag(g) M diag(g)^H on the full
+    correlation matrix M, are restored by the solutions 1/g."""
+    vis, uvw, freq, rows, cols = correction_problem(41)
+    T, C, P, B = vis.shape
+    A = 7
+    g = np.random.default_rng(42)
+    gains = (g.uniform(0.5, 1.5, size=(C, P, A)) * np.exp(2j * np.pi * g.uniform(size=(C, P, A))))
+    obs = np.empty((T, C, P, B), dtype=np.complex128)
+    for t, c, p in np.ndindex(T, C, P):
+        M = np.zeros((A, A), dtype=np.complex128)
+        M[rows, cols] = vis[t, c, p]
+        M[cols, rows] = np.conj(vis[t, c, p])
+        D = np.diag(gains[c, p])
+        obs[t, c, p] = (D @ M @ D.conj().T)[rows, cols]
+    sol = (1.0 / gains).astype(np.complex64)
+    back = O.correct_vis(obs.astype(np.complex64), uvw, freq, sol, 0.0, 0.0)
+    assert np.abs(back - vis).max() <= 1e-5 * np.abs(vis).max()
+
+
+def pin_corrections_phase_centre(O):
+    """A point source at (l0, m0), with the w term of Eq. 4 (non-coplanar baselines), has the
+    same visibility S on every baseline after the phase centre moves to (l0, m0), so the
+    naturally weighted image has S at the centre pixel."""
+    vis, uvw, freq, _, _ = correction_problem(43, P=1)
+    T, C, P, B = vis.shape
+    l0, m0, S = 0.031, -0.047, 2.5
+    n0 = math.sqrt(1.0 - l0 * l0 - m0 * m0)
+    src = np.empty((T, C, 1, B), dtype=np.complex128)
+    for c in range(C):
+        lam = C_LIGHT / freq[c]
+        src[:, c, 0] = S * np.exp(-2j * np.pi * (uvw[..., 0] * l0 + uvw[..., 1] * m0 + uvw[..., 2] * (n0 - 1.0)) / lam)
+    vc = O.correct_vis(src.astype(np.complex64), uvw, freq, None, l0, m0)
+    assert np.abs(vc - S).max() <= 1e-6 * S
+    N = 32
+    res = O.image_batch_corrected(src.astype(np.complex64), None, uvw, freq, N, 2.0e-3, 0, None, l0, m0)
+    for t, c in np.ndindex(T, C):
+        assert abs(res["images"][t, c, 0, N // 2, N // 2] - S) <= 1e-6 * S
+    # without the correction the source sits off the phase centre: the centre pixel is lower
+    plain = O.image_batch(src.astype(np.complex64), None, uvw, freq, N, 2.0e-3, 0)
+    assert (plain["images"][:, :, 0, N // 2, N // 2] < 0.9 * S).all()
+
+
+EXTRA_PINS = [pin_image_average, pin_es_kernel_values, pin_es_transform, pin_conv_width1_is_nearest_cell,
+              pin_conv_hermitian, pin_conv_matches_direct_transform, pin_conv_batch_consistency,
+              pin_corrections_identity, pin_corrections_undo_gains, pin_corrections_phase_centre]
 
 
 PINS = [pin_cell_worked, pin_tiny_grid, pin_ifft1d_bruteforce, pin_ifft2d_bruteforce,

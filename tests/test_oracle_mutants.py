@@ -44,6 +44,14 @@ MUTANTS = {
     "conv_transform_frequency": ("cos(M_PI * nu * width * sin(t))", "cos(2.0 * M_PI * nu * width * sin(t))"),
     "conv_edge_not_strict": ("fabs(rv) < half && fabs(ru) < half", "fabs(rv) <= half && fabs(ru) <= half"),
     "conv_weight_halved": ("*weight_sum = 2.0 * (double)kept;", "*weight_sum = (double)kept;"),
+    # visibility corrections
+    "corr_rotation_sign": ("rot_im = sin(2.0 * M_PI * turns);", "rot_im = -sin(2.0 * M_PI * turns);"),
+    "corr_w_term_dropped": ("x[2] * (n0 - 1.0)", "0.0 * x[2]"),
+    "corr_w_term_not_relative": ("x[2] * (n0 - 1.0)", "x[2] * n0"),
+    "corr_gain_conj_on_first": ("br = gj[0], bi = -(double)gj[1];", "br = gj[0], bi = (double)gj[1];"),
+    "corr_antennas_swapped": ("ant_i[b] = i; ant_j[b] = j;", "ant_i[b] = j; ant_j[b] = i;"),
+    "corr_frequency_missing": ("const double cycles_per_metre = freq_hz[c] / SPEED_OF_LIGHT;",
+                               "const double cycles_per_metre = 150.0e6 / SPEED_OF_LIGHT;"),
 }
 
 
@@ -57,7 +65,7 @@ def test_pins_catch_planted_mistake(tmp_path, name):
     lib = oracle.compile_library(str(path), str(tmp_path / f"libmut_{name}.so"))
     O = oracle.Oracle(oracle.load(lib))
     caught = []
-    for pin in oracle_pins.PINS + oracle_pins.CONV_PINS:
+    for pin in oracle_pins.PINS + oracle_pins.EXTRA_PINS:
         try:
             pin(O)
         except Exception:  # any failure of a pin counts as caught

@@ -12,7 +12,7 @@ def O():
     return oracle.default()
 
 
-@pytest.mark.parametrize("pin", oracle_pins.PINS + oracle_pins.CONV_PINS, ids=lambda p: p.__name__)
+@pytest.mark.parametrize("pin", oracle_pins.PINS + oracle_pins.EXTRA_PINS, ids=lambda p: p.__name__)
 def test_pin(O, pin):
     pin(O)
 
