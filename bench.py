@@ -356,6 +356,32 @@ def main():
                                              "kernels": {k: ck[k] for k in ("bin", "grid_colfft", "row_fft") if k in ck}}
         log(f"conv W=8: {v:.0f} images/s ({v / value:.3f} x nearest-cell FP32)")
         del cws
+        # Pre-gridding corrections (per-antenna solutions + phase-centre rotation) on the same workload.
+        gen = torch.Generator(device="cuda:0")
+        gen.manual_seed(20)
+        amp = 0.5 + torch.rand((C, P, spec.n_tiles), generator=gen, device="cuda:0", dtype=torch.float64)
+        pha = 2 * torch.pi * torch.rand((C, P, spec.n_tiles), generator=gen, device="cuda:0", dtype=torch.float64)
+        gains = torch.polar(amp, pha).to(torch.complex64)
+        xws = torch.empty(blink.image_batch_corrected_workspace_size(1, C, P, B, N), dtype=torch.uint8,
+                          device="cuda:0")
+
+        def xstep(i):
+            t = i % T
+            ctx.blink_image_batch_corrected(d["vis"][t:t + 1], d["flags"][t:t + 1], d["uvw_m"][t:t + 1],
+                                            d["freq_hz"], N, spec.pixel_scale, 0, gains=gains, l0=0.02, m0=-0.015,
+                                            out=images, weight_sum=wsum, n_out=nout, workspace=xws)
+        ms = timed(torch, xstep, fs, 2)
+        xprof, _ = profiled(ctx, torch, xstep, fs)
+        xub = dict(ub, correct=("pair", P * B * 16 + 24 * B // C + P * spec.n_tiles * 8))
+        xk = kernel_table(xprof, {"image": fs * C * P, "pair": fs * C}, xub)
+        v = fs * C * P / (ms / 1e3)
+        forms["vcs-1024"]["corrected_fp32"] = {
+            "images_per_s": round(v, 1), "vs_fp32": round(v / value, 4),
+            "corrections": "per-antenna complex solutions [C][P][128] and phase-centre rotation (l0, m0) = "
+                           "(0.02, -0.015) with the w term",
+            "kernels": {k: xk[k] for k in ("correct", "grid_colfft", "row_fft") if k in xk}}
+        log(f"corrected: {v:.0f} images/s ({v / value:.3f} x FP32)")
+        del xws, gains
         # Stokes I + band average of one time step's images (1536 images -> 1), HBM-bound.
         avg_out = torch.empty((1, 1, 1, N, N), dtype=torch.float32, device="cuda:0")
         ms = timed(torch, lambda i: ctx.blink_image_average(images, blink.AVG_CHANNEL | blink.AVG_POL, out=avg_out),

@@ -148,6 +148,41 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32 *vis, const uint8
                                int32_t *n_out, void *workspace, size_t workspace_bytes,
                                void *hip_stream);
 
+/* ---------------------------------------------------------------- visibility corrections
+ * The corrections the paper applies to the correlator output before imaging (Section 6.2.3):
+ * calibration solutions per antenna, then the geometric correction that moves the phase centre to
+ * the pointing direction (done in the imager, where (u, v, w) are known). Cable-length
+ * corrections are per-antenna phases and go into the same per-antenna factors. For baseline
+ * b = (i, j), i > j, b = i (i - 1) / 2 + j (the lower-triangular order of the correlation step,
+ * Section 6.2.2, without autocorrelations) and channel c of frequency f:
+ *   V' = J[c][p][i] V conj(J[c][p][j]) exp(+2 pi i (f / 299792458) (u l0 + v m0 + w (n0 - 1))),
+ * n0 = sqrt(1 - l0^2 - m0^2), (u, v, w) the baseline's uvw_m[t][b] in metres. A source at
+ * direction cosines (l0, m0) then has zero phase and images at the phase centre; the cells stay
+ * those of the uncorrected (u, v) (no re-projection of the baselines). */
+typedef struct blink_corrections {
+    const blink_cf32 *gains;   /* device complex64 [C][P][n_ant] per-antenna factors J, or NULL (all 1) */
+    int n_ant;                 /* antennas; with gains, B must equal n_ant (n_ant - 1) / 2 */
+    double l0, m0;             /* new phase centre, direction cosines; l0^2 + m0^2 < 1 (0, 0: none) */
+} blink_corrections;
+
+/* Workspace bytes for blink_image_batch_corrected (blink_image_batch's, plus one chunk of
+ * corrected visibilities). */
+blink_status blink_image_batch_corrected_workspace_size(int T, int C, int P, int B, int grid_n,
+                                                        int weighting, int precision, size_t *bytes);
+
+/* blink_image_batch on the corrected visibilities V' above: a correction pass per chunk writes
+ * V' into the workspace (delay and products in FP64, the rotation's sine and cosine in FP32 after
+ * an exact reduction to one turn, the result rounded once to complex64), and the gridding of
+ * blink_image_batch reads it in place of vis. corr is a host pointer (NULL: no corrections, the
+ * result is blink_image_batch's); its gains are device memory. ERR_ARG when B does not match
+ * n_ant with gains, or l0^2 + m0^2 >= 1. Same outputs, plans and workspace rules otherwise. */
+blink_status blink_image_batch_corrected(blink_ctx ctx, const blink_cf32 *vis, const uint8_t *flags,
+                                         const double *uvw_m, const double *freq_hz, int T, int C,
+                                         int P, int B, int grid_n, double pixel_scale, int weighting,
+                                         int precision, int shift, const blink_corrections *corr,
+                                         float *images, double *weight_sum, int32_t *n_out,
+                                         void *workspace, size_t workspace_bytes, void *hip_stream);
+
 /* ---------------------------------------------------------------- convolutional gridding
  * A step beyond the paper, which places visibilities on their nearest cell with no convolution
  * kernel (Section 6.2.4) and names a gridding kernel against aliasing as planned work (Sections 7
@@ -311,7 +346,8 @@ enum {
     BLINK_KERNEL_PERSISTENT = 7,   /* persistent fused binning + gridding + FFT (uneven batches) */
     BLINK_KERNEL_CONV_CORRECTION = 8, /* grid-correction table of the convolutional path */
     BLINK_KERNEL_AVERAGE = 9,      /* image averages (blink_image_average) */
-    BLINK_KERNEL_COUNT = 10
+    BLINK_KERNEL_CORRECT = 10,     /* visibility corrections (blink_image_batch_corrected) */
+    BLINK_KERNEL_COUNT = 11
 };
 
 /* Enable (nonzero) or disable timing; either way the recorded launches are discarded. */

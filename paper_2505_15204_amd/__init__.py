@@ -21,7 +21,7 @@ PLANS_PATH = os.path.join(PKG, "plans_gfx950.json")     # autotuned execution pl
 BLINK_OK, BLINK_ERR_ARG, BLINK_ERR_SIZE, BLINK_ERR_NOMEM, BLINK_ERR_HIP, BLINK_ERR_STATE = range(6)
 WEIGHT_NATURAL, WEIGHT_UNIFORM = 0, 1
 KERNELS = ("bin", "grid", "grid_colfft", "dense_colfft", "weights", "row_fft", "desc_prep", "persistent",
-           "conv_correction", "average")
+           "conv_correction", "average", "correct")
 AVG_TIME, AVG_CHANNEL, AVG_POL = 1, 2, 4   # BLINK_KERNEL_* ids
 DESC_BAD = 1
 
@@ -44,6 +44,12 @@ class BlinkError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"[{status}] {message}")
         self.status = status
+
+
+class Corrections(ctypes.Structure):
+    """blink_corrections: per-antenna factors (device pointer or None), antennas, phase centre."""
+    _fields_ = [("gains", ctypes.c_void_p), ("n_ant", ctypes.c_int), ("l0", ctypes.c_double),
+                ("m0", ctypes.c_double)]
 
 
 def header_functions() -> list:
@@ -84,6 +90,11 @@ def lib() -> ctypes.CDLL:
     L.blink_image_batch.restype = i32
     L.blink_image_batch.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32, P, P, P,
                                     P, sz, P]
+    L.blink_image_batch_corrected_workspace_size.restype = i32
+    L.blink_image_batch_corrected_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
+    L.blink_image_batch_corrected.restype = i32
+    L.blink_image_batch_corrected.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32,
+                                              ctypes.POINTER(Corrections), P, P, P, P, sz, P]
     L.blink_plan_options.restype = i32
     L.blink_plan_options.argtypes = [i32, i32, P, P, P, P]
     L.blink_get_plan.restype = i32
@@ -154,6 +165,15 @@ def image_batch_workspace_size(T: int, C: int, P: int, B: int, grid_n: int, weig
     n = ctypes.c_size_t()
     _check(lib().blink_image_batch_workspace_size(T, C, P, B, grid_n, weighting, precision, ctypes.byref(n)),
            what="blink_image_batch_workspace_size")
+    return n.value
+
+
+def image_batch_corrected_workspace_size(T: int, C: int, P: int, B: int, grid_n: int, weighting: int = 0,
+                                         precision: int = PREC_FP32) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().blink_image_batch_corrected_workspace_size(T, C, P, B, grid_n, weighting, precision,
+                                                            ctypes.byref(n)),
+           what="blink_image_batch_corrected_workspace_size")
     return n.value
 
 
@@ -466,6 +486,43 @@ class Context:
                                      _ptr(out), _ptr(weight_sum), _ptr(n_out), _ptr(ws), ws.numel(),
                                      self._stream(stream))
         _check(st, self.handle, "blink_image_batch")
+        return {"images": out, "weight_sum": weight_sum, "n_out": n_out}
+
+    def blink_image_batch_corrected(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float,
+                                    weighting: int = 0, gains=None, l0: float = 0.0, m0: float = 0.0,
+                                    precision: int = PREC_FP32, shift: bool = True, out=None, weight_sum=None,
+                                    n_out=None, workspace=None, stream=None):
+        """blink_image_batch on visibilities corrected by per-antenna factors gains (complex64
+        device tensor [C][P][n_ant], or None) and moved to the phase centre (l0, m0)."""
+        torch = self._torch()
+        T, C, P, B = vis.shape
+        N = int(grid_n)
+        self._require("vis", vis, torch.complex64)
+        if flags is not None:
+            self._require("flags", flags, torch.uint8, (T, C, B))
+        self._require("uvw_m", uvw_m, torch.float64, (T, B, 3))
+        self._require("freq_hz", freq_hz, torch.float64, (C,))
+        n_ant = 0
+        if gains is not None:
+            self._require("gains", gains, torch.complex64)
+            if gains.dim() != 3 or tuple(gains.shape[:2]) != (C, P):
+                raise ValueError(f"gains must be [C][P][n_ant] = [{C}][{P}][n_ant], got {tuple(gains.shape)}")
+            n_ant = int(gains.shape[2])
+        dev = vis.device
+        if out is None:
+            out = torch.empty((T, C, P, N, N), dtype=torch.float32, device=dev)
+        self._require("out", out, torch.float32, (T, C, P, N, N))
+        if weight_sum is None:
+            weight_sum = torch.empty((T, C, P), dtype=torch.float64, device=dev)
+        if n_out is None:
+            n_out = torch.empty((T, C), dtype=torch.int32, device=dev)
+        ws = self._workspace(image_batch_corrected_workspace_size(T, C, P, B, N, weighting, precision), workspace)
+        corr = Corrections(_ptr(gains), n_ant, float(l0), float(m0))
+        st = lib().blink_image_batch_corrected(self.handle, _ptr(vis), _ptr(flags), _ptr(uvw_m), _ptr(freq_hz), T, C,
+                                               P, B, N, float(pixel_scale), int(weighting), int(precision),
+                                               int(bool(shift)), ctypes.byref(corr), _ptr(out), _ptr(weight_sum),
+                                               _ptr(n_out), _ptr(ws), ws.numel(), self._stream(stream))
+        _check(st, self.handle, "blink_image_batch_corrected")
         return {"images": out, "weight_sum": weight_sum, "n_out": n_out}
 
     def blink_image_average(self, images, axes: int, out=None, stream=None):

@@ -157,7 +157,7 @@ BinLayout carve_bins(Carve& c, size_t Q, size_t P, size_t B, size_t nstrips) {
 
 struct ImageLayout {
   BinLayout bins;
-  size_t H, total;
+  size_t H, vc, total;   // vc: corrected visibilities of a chunk (blink_image_batch_corrected)
   bool ok;
 };
 
@@ -173,13 +173,14 @@ int min_col_strip(int logn, int uniform) {
   return n > 0 ? opts[n - 1] : 1;
 }
 
-ImageLayout image_layout(size_t Q, int P, int B, int logn, int uniform, size_t h_images) {
+ImageLayout image_layout(size_t Q, int P, int B, int logn, int uniform, size_t h_images, bool corrected = false) {
   const size_t N = size_t(1) << logn;
   const size_t nstrips = (N / 2) / min_col_strip(logn, uniform);
   Carve c;
   ImageLayout L;
   L.bins = carve_bins(c, Q, P, B, nstrips);
   L.H = c.take(h_images, N * (N / 2) * sizeof(float2));
+  L.vc = corrected ? c.take(Q * (size_t)P, (size_t)B * sizeof(float2)) : 0;
   L.total = c.off;
   L.ok = c.ok;
   return L;
@@ -423,6 +424,21 @@ blink_status blink_image_batch_workspace_size(int T, int C, int P, int B, int gr
   return BLINK_OK;
 }
 
+blink_status blink_image_batch_corrected_workspace_size(int T, int C, int P, int B, int grid_n, int weighting,
+                                                        int precision, size_t* bytes) {
+  if (!bytes || T < 0 || C < 0 || P < 1 || B < 0) return BLINK_ERR_ARG;
+  if (weighting != BLINK_WEIGHT_NATURAL && weighting != BLINK_WEIGHT_UNIFORM) return BLINK_ERR_ARG;
+  if (!valid_precision(precision)) return BLINK_ERR_ARG;
+  const int logn = log2_exact(grid_n);
+  if (logn < 0) return BLINK_ERR_SIZE;
+  const size_t n_img = (size_t)T * C * P;
+  ImageLayout L = image_layout((size_t)T * C, P, B, logn, weighting,
+                               n_img < kMaxGroupImages ? n_img : kMaxGroupImages, true);
+  if (!L.ok) return BLINK_ERR_SIZE;
+  *bytes = L.total;
+  return BLINK_OK;
+}
+
 blink_status blink_grid(blink_ctx ctx, const blink_cf32* vis, const uint8_t* flags, const double* uvw_m,
                         const double* freq_hz, int T, int C, int P, int B, int grid_n, double pixel_scale,
                         int weighting, blink_cf32* grids, int32_t* counts, double* weight_sum,
@@ -555,10 +571,12 @@ blink_status blink_ifft2d(blink_ctx ctx, const blink_cf32* grids, const double* 
   return BLINK_OK;
 }
 
-blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8_t* flags, const double* uvw_m,
-                               const double* freq_hz, int T, int C, int P, int B, int grid_n, double pixel_scale,
-                               int weighting, int precision, int shift, float* images, double* weight_sum,
-                               int32_t* n_out, void* workspace, size_t workspace_bytes, void* hip_stream) {
+// blink_image_batch, and blink_image_batch_corrected when corr is non-null (checked by the caller).
+static blink_status image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8_t* flags, const double* uvw_m,
+                                const double* freq_hz, int T, int C, int P, int B, int grid_n, double pixel_scale,
+                                int weighting, int precision, int shift, const blink_corrections* corr,
+                                float* images, double* weight_sum, int32_t* n_out, void* workspace,
+                                size_t workspace_bytes, void* hip_stream) {
   int logn = 0;
   blink_status st = check_problem(ctx, vis, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting,
                                   images, workspace, &logn);
@@ -566,19 +584,20 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
   if (!valid_precision(precision)) return fail(ctx, BLINK_ERR_ARG, "unsupported precision %d", precision);
   const size_t n_tc = (size_t)T * C;
   if (n_tc == 0) return BLINK_OK;
+  const bool corrected = corr != nullptr;
   const auto& plan = ctx->plan[logn][weighting][precision];
   const size_t want = plan.group > 0 ? (size_t)plan.group : kMaxGroupImages;
   size_t Q = largest_fitting_chunk(n_tc, workspace_bytes, [&](size_t q) {
-    return image_layout(q, P, B, logn, weighting, q * P < want ? q * P : want).total;
+    return image_layout(q, P, B, logn, weighting, q * P < want ? q * P : want, corrected).total;
   });
   size_t h_images = Q * P < want ? Q * P : want;
-  if (Q == 0 && image_layout(1, P, B, logn, weighting, 1).total <= workspace_bytes) {
+  if (Q == 0 && image_layout(1, P, B, logn, weighting, 1, corrected).total <= workspace_bytes) {
     Q = 1;                       // fall back to one intermediate at a time
     h_images = 1;
   }
   if (Q == 0)
     return fail(ctx, BLINK_ERR_SIZE, "workspace of %zu bytes is smaller than one (t,c) pair needs (%zu)",
-                workspace_bytes, image_layout(1, P, B, logn, weighting, 1).total);
+                workspace_bytes, image_layout(1, P, B, logn, weighting, 1, corrected).total);
   if (Q * P > (size_t)INT32_MAX) return fail(ctx, BLINK_ERR_SIZE, "batch too large");
   DeviceGuard g(ctx->device);
   if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
@@ -588,7 +607,7 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
   int log_s = 0;
   while ((1 << log_s) < S) ++log_s;
   char* ws = (char*)workspace;
-  ImageLayout L = image_layout(Q, P, B, logn, weighting, h_images);
+  ImageLayout L = image_layout(Q, P, B, logn, weighting, h_images, corrected);
   const int G = (int)h_images;
   for (size_t tc0 = 0; tc0 < n_tc; tc0 += Q) {
     const int q = (int)((n_tc - tc0) < Q ? (n_tc - tc0) : Q);
@@ -619,6 +638,30 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
     if (e != hipSuccess) return hip_fail(ctx, e, "bin kernel");
     blink::ColArgs ca{};
     ca.vis = (const float2*)vis + tc0 * P * B;
+    if (corrected) {
+      // the corrected visibilities of this chunk replace vis for the gridding
+      blink::CorrArgs xa{};
+      xa.vis = ca.vis;
+      xa.uvw = uvw_m;
+      xa.freq = freq_hz;
+      xa.gains = (const float2*)corr->gains;
+      xa.tc0 = (int)tc0;
+      xa.Q = q;
+      xa.C = C;
+      xa.P = P;
+      xa.B = B;
+      xa.n_ant = corr->n_ant;
+      xa.l0 = corr->l0;
+      xa.m0 = corr->m0;
+      xa.n0m1 = std::sqrt(1.0 - corr->l0 * corr->l0 - corr->m0 * corr->m0) - 1.0;
+      xa.out = (float2*)(ws + L.vc);
+      {
+        KernelTimer kt(ctx, BLINK_KERNEL_CORRECT, s);
+        e = blink::launch_correct_vis(xa, s);
+      }
+      if (e != hipSuccess) return hip_fail(ctx, e, "visibility correction kernel");
+      ca.vis = xa.out;
+    }
     ca.plc = ba.plc;
     ca.strip_off = ba.strip_off;
     ca.Q = q;
@@ -661,6 +704,31 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
     }
   }
   return BLINK_OK;
+}
+
+blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8_t* flags, const double* uvw_m,
+                               const double* freq_hz, int T, int C, int P, int B, int grid_n, double pixel_scale,
+                               int weighting, int precision, int shift, float* images, double* weight_sum,
+                               int32_t* n_out, void* workspace, size_t workspace_bytes, void* hip_stream) {
+  return image_batch(ctx, vis, flags, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting, precision, shift,
+                     nullptr, images, weight_sum, n_out, workspace, workspace_bytes, hip_stream);
+}
+
+blink_status blink_image_batch_corrected(blink_ctx ctx, const blink_cf32* vis, const uint8_t* flags,
+                                         const double* uvw_m, const double* freq_hz, int T, int C, int P, int B,
+                                         int grid_n, double pixel_scale, int weighting, int precision, int shift,
+                                         const blink_corrections* corr, float* images, double* weight_sum,
+                                         int32_t* n_out, void* workspace, size_t workspace_bytes,
+                                         void* hip_stream) {
+  if (corr) {
+    if (!(std::isfinite(corr->l0) && std::isfinite(corr->m0) && corr->l0 * corr->l0 + corr->m0 * corr->m0 < 1.0))
+      return fail(ctx, BLINK_ERR_ARG, "phase centre (l0=%g, m0=%g) is not a direction (l0^2 + m0^2 < 1)", corr->l0,
+                  corr->m0);
+    if (corr->gains && (corr->n_ant < 2 || (long long)corr->n_ant * (corr->n_ant - 1) / 2 != (long long)B))
+      return fail(ctx, BLINK_ERR_ARG, "n_ant=%d does not give B=%d cross baselines", corr->n_ant, B);
+  }
+  return image_batch(ctx, vis, flags, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting, precision, shift,
+                     corr, images, weight_sum, n_out, workspace, workspace_bytes, hip_stream);
 }
 
 blink_status blink_image_batch_conv_workspace_size(int T, int C, int P, int B, int grid_n, int kernel_width,

@@ -159,6 +159,57 @@ hipError_t launch_grid_colfft_conv(const ColArgs& a, int n_img, ConvParams cp, i
 // Averages of images [T][C][P][N][N] over the axes in `axes` (1 time, 2 channel, 4 polarisation;
 // Sections 7.1 and 7.2 average over time and over the band, the polarisation average of XX and YY
 // is Stokes I). One thread per 4 consecutive pixels of one output image, FP64 sums.
+// ---------------------------------------------------------------- visibility corrections
+// Antenna pair (i, j), i > j, of baseline b = i (i - 1) / 2 + j: the lower-triangular order in
+// which the correlation step stores visibilities (Section 6.2.2).
+__device__ __forceinline__ void antenna_pair(long long b, int& i, int& j) {
+  long long r = (long long)((1.0 + sqrt(1.0 + 8.0 * (double)b)) * 0.5);
+  while (r * (r - 1) / 2 > b) --r;
+  while ((r + 1) * r / 2 <= b) ++r;
+  i = (int)r;
+  j = (int)(b - r * (r - 1) / 2);
+}
+
+// One thread per (pair, baseline); the phase of the new phase centre is shared by the pols.
+// Workgroup w covers baselines (w % nbx) * 256 .. of pair w / nbx.
+__global__ __launch_bounds__(256) void k_correct_vis(CorrArgs a, int nbx) {
+  const int q = (int)(blockIdx.x / (unsigned)nbx);
+  const int b = (int)(blockIdx.x % (unsigned)nbx) * 256 + (int)threadIdx.x;
+  if (b >= a.B) return;
+  const long tc = (long)a.tc0 + q;
+  const long t = tc / a.C, c = tc % a.C;
+  const double* x = a.uvw + 3 * ((size_t)t * a.B + b);
+  // geometric delay in turns (FP64), reduced exactly to [-1/2, 1/2]; the sine and cosine of the
+  // reduced angle are taken in FP32 (|angle| <= pi, so their error is a few 1e-8)
+  const double turns = (a.freq[c] / kSpeedOfLight) * (x[0] * a.l0 + x[1] * a.m0 + x[2] * a.n0m1);
+  float snf, csf;
+  sincospif((float)(2.0 * (turns - rint(turns))), &snf, &csf);
+  const double sn = snf, cs = csf;
+  int i = 0, j = 0;
+  if (a.gains) antenna_pair(b, i, j);
+  for (int p = 0; p < a.P; ++p) {
+    const size_t at = ((size_t)q * a.P + p) * a.B + b;
+    const float2 v = a.vis[at];
+    double re = v.x, im = v.y;
+    if (a.gains) {
+      const float2 gi = a.gains[((size_t)c * a.P + p) * a.n_ant + i];
+      const float2 gj = a.gains[((size_t)c * a.P + p) * a.n_ant + j];
+      const double r1 = (double)gi.x * re - (double)gi.y * im, i1 = (double)gi.x * im + (double)gi.y * re;
+      re = r1 * gj.x + i1 * gj.y;          // (r1 + i i1) conj(gj)
+      im = i1 * gj.x - r1 * gj.y;
+    }
+    a.out[at] = make_float2((float)(re * cs - im * sn), (float)(re * sn + im * cs));
+  }
+}
+
+hipError_t launch_correct_vis(const CorrArgs& a, hipStream_t s) {
+  if (a.Q <= 0 || a.B <= 0) return hipSuccess;
+  const long nbx = ((long)a.B + 255) / 256;
+  if (nbx * a.Q > 0x7fffffffL) return hipErrorInvalidValue;
+  k_correct_vis<<<(unsigned)(nbx * a.Q), 256, 0, s>>>(a, (int)nbx);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_image_average(const float4* __restrict__ in, int T, int C, int P, long nn4,
                                                        int axes, float4* __restrict__ out) {
   const int To = (axes & 1) ? 1 : T, Co = (axes & 2) ? 1 : C, Po = (axes & 4) ? 1 : P;

@@ -109,6 +109,22 @@ int conv_strip_width(int logn);
 // corr[x] = 1 / c(X/N) for x < N (FP64 quadrature, stored as FP32).
 hipError_t launch_conv_correction(float* corr, int logn, ConvParams cp, int shift, hipStream_t s);
 
+// Visibility corrections before gridding (Section 6.2.3) for pairs tc0 .. tc0+Q-1 of the
+// [T][C] batch: out[q][p][b] = J[c][p][i] V[q][p][b] conj(J[c][p][j]) exp(+2 pi i (f_c/c)
+// (u l0 + v m0 + w (n0 - 1))) with (i, j) the antenna pair of baseline b (i > j,
+// b = i (i - 1) / 2 + j): delay and products in FP64, the sine and cosine in FP32 after an exact
+// reduction of the delay to [-1/2, 1/2] turn, rounded once to complex64.
+struct CorrArgs {
+  const float2* vis;        // chunk base [Q][P][B]
+  const double* uvw;        // [T][B][3]
+  const double* freq;       // [C]
+  const float2* gains;      // [C][P][n_ant] or null (all 1)
+  int tc0, Q, C, P, B, n_ant;
+  double l0, m0, n0m1;      // n0m1 = sqrt(1 - l0^2 - m0^2) - 1
+  float2* out;              // [Q][P][B]
+};
+hipError_t launch_correct_vis(const CorrArgs& a, hipStream_t s);
+
 // Averages of images [T][C][P][N][N] over the axes in `axes` (1 time, 2 channel, 4 pol).
 hipError_t launch_image_average(const float* in, int T, int C, int P, int logn, int axes, float* out, hipStream_t s);
 

@@ -127,3 +127,25 @@ def test_conv_argument_checks(L):
     for bad in ((1, 1, 1, 10, 64, 0), (1, 1, 1, 10, 64, 32), (1, 1, 1, 10, 64, 17), (1, 1, 1, 10, 16, 8)):
         with pytest.raises(blink.BlinkError):
             blink.image_batch_conv_workspace_size(*bad)
+
+
+def test_corrections_argument_checks(L):
+    """blink_image_batch_corrected: the blink_corrections layout, and its argument errors on the
+    host (phase centre off the unit disc, antennas that do not give B) before any device work."""
+    assert ctypes.sizeof(blink.Corrections) == 32 and blink.Corrections.l0.offset == 16
+    dummy = ctypes.c_void_p(0x1000)
+
+    def call(corr, B=21, N=64, T=1, ctx=None):
+        return L.blink_image_batch_corrected(ctx, dummy, None, dummy, dummy, T, 1, 1, B, N, 1e-3, 0, 0, 1,
+                                             ctypes.byref(corr) if corr is not None else None, dummy, None, None,
+                                             ctypes.c_void_p(0x10000), 1 << 20, None)
+    ok = blink.Corrections(None, 0, 0.01, -0.02)
+    assert call(ok) == blink.BLINK_ERR_ARG                    # NULL context
+    assert call(None) == blink.BLINK_ERR_ARG                  # NULL context, no corrections
+    assert call(ok, N=100) == blink.BLINK_ERR_SIZE
+    assert call(blink.Corrections(None, 0, 0.8, 0.7)) == blink.BLINK_ERR_ARG
+    assert call(blink.Corrections(None, 0, float("nan"), 0.0)) == blink.BLINK_ERR_ARG
+    assert call(blink.Corrections(dummy, 6, 0.0, 0.0)) == blink.BLINK_ERR_ARG     # 6 antennas: 15 baselines
+    assert call(blink.Corrections(dummy, 1, 0.0, 0.0), B=0) == blink.BLINK_ERR_ARG
+    s = blink.image_batch_corrected_workspace_size(1, 2, 2, 8128, 1024)
+    assert s >= blink.image_batch_workspace_size(1, 2, 2, 8128, 1024) + 2 * 2 * 8128 * 8
