@@ -58,6 +58,8 @@ def load(path: str):
                                              P, P, P, P, P, i32]
     L.blink_ref_correct_vis.restype = i32
     L.blink_ref_correct_vis.argtypes = [P, P, P, i32, i32, i32, i32, P, i32, f64, f64, P]
+    L.blink_ref_correlate.restype = i32
+    L.blink_ref_correlate.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P]
     L.blink_ref_max_threads.restype = i32
     L.blink_ref_max_threads.argtypes = []
     L.blink_ref_es_kernel.restype = f64
@@ -211,6 +213,22 @@ class Oracle:
         vc = self.correct_vis(vis, uvw, freq_hz, gains, l0, m0)
         return self.image_batch_c128(vc, flags, uvw, freq_hz, grid_n, pixel_scale, weighting, shift, n_threads)
 
+    def correlate(self, volt, n_int, n_favg, pol_mode=4):
+        """Visibilities of int8 voltages [S][F][A][2][2] (re, im): dict(vis complex64 [T][C][P][B],
+        autos complex64 [T][C][A][4])."""
+        v = _c(volt, np.int8)
+        S, F, A = v.shape[:3]
+        assert v.shape[3:] == (2, 2)
+        T, C = S // n_int, F // n_favg
+        B = A * (A - 1) // 2
+        vis = np.empty((T, C, pol_mode, B), dtype=np.complex64)
+        autos = np.empty((T, C, A, 4), dtype=np.complex64)
+        rc = self.L.blink_ref_correlate(_ptr(v), S, F, A, int(n_int), int(n_favg), int(pol_mode), _ptr(vis),
+                                       _ptr(autos))
+        if rc != 0:
+            raise ValueError(f"blink_ref_correlate failed with code {rc}")
+        return {"vis": vis, "autos": autos}
+
     def max_threads(self) -> int:
         return int(self.L.blink_ref_max_threads())
 
@@ -314,6 +332,10 @@ def correct_vis(*a, **k):
 
 def image_batch_corrected(*a, **k):
     return default().image_batch_corrected(*a, **k)
+
+
+def correlate(*a, **k):
+    return default().correlate(*a, **k)
 
 
 def max_threads() -> int:

@@ -498,3 +498,61 @@ int blink_ref_image_average(const float *images, int T, int C, int P, int grid_n
     for (size_t i = 0; i < total; ++i) out[i] /= count;
     return 0;
 }
+
+/* ------------------------------------------------------------------------------------------
+ * Correlation (Section 4, Eq. 3; Section 6.2.2): the conjugate multiply-accumulate of every
+ * pair of fine-channelised antenna voltages, averaged over an integration interval and over the
+ * fine channels of an output channel. Voltages are complex int8 (re, im) in the layout
+ * [S samples][F fine channels][A antennas][2 polarisations]; visibility (i, j), i > j, of
+ * polarisations (p, q) is mean(x_{i,p} conj(x_{j,q})) over n_int samples and n_favg channels.
+ * ------------------------------------------------------------------------------------------ */
+int blink_ref_correlate(const int8_t *volt, int S, int F, int A, int n_int, int n_favg, int pol_mode,
+                        float *vis, float *autos)
+{
+    if (S < 0 || F < 0 || A < 2 || n_int < 1 || n_favg < 1 || !volt || !vis) return 1;
+    if (S % n_int != 0 || F % n_favg != 0) return 1;
+    if (pol_mode != 2 && pol_mode != 4) return 1;
+    const int T = S / n_int, C = F / n_favg, P = pol_mode;
+    const long B = (long)A * (A - 1) / 2;
+    const double count = (double)n_int * (double)n_favg;
+    for (int t = 0; t < T; ++t) {
+        for (int c = 0; c < C; ++c) {
+            for (int i = 0; i < A; ++i) {
+                for (int j = 0; j <= i; ++j) {
+                    for (int p = 0; p < 2; ++p) {
+                        for (int q = 0; q < 2; ++q) {
+                            int64_t sre = 0, sim = 0;
+                            for (int s = t * n_int; s < (t + 1) * n_int; ++s) {
+                                for (int f = c * n_favg; f < (c + 1) * n_favg; ++f) {
+                                    const int8_t *xi = volt + ((((size_t)s * F + f) * A + i) * 2 + p) * 2;
+                                    const int8_t *xj = volt + ((((size_t)s * F + f) * A + j) * 2 + q) * 2;
+                                    /* x_i conj(x_j) */
+                                    sre += (int64_t)xi[0] * xj[0] + (int64_t)xi[1] * xj[1];
+                                    sim += (int64_t)xi[1] * xj[0] - (int64_t)xi[0] * xj[1];
+                                }
+                            }
+                            const float re = (float)((double)sre / count), im = (float)((double)sim / count);
+                            if (i == j) {
+                                if (autos) {
+                                    float *o = autos + 2 * ((((size_t)t * C + c) * A + i) * 4 + 2 * p + q);
+                                    o[0] = re;
+                                    o[1] = im;
+                                }
+                                continue;
+                            }
+                            int pp;
+                            if (P == 4) pp = 2 * p + q;
+                            else if (p == q) pp = p;
+                            else continue;
+                            const long b = (long)i * (i - 1) / 2 + j;
+                            float *o = vis + 2 * ((((size_t)t * C + c) * P + pp) * B + b);
+                            o[0] = re;
+                            o[1] = im;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    return 0;
+}

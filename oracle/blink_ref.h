@@ -121,6 +121,16 @@ int blink_ref_image_batch_conv(const float *vis, const uint8_t *flags, const dou
  * Over P = 2 (XX, YY) the polarisation average is Stokes I. */
 int blink_ref_image_average(const float *images, int T, int C, int P, int grid_n, int axes, double *out);
 
+/* Correlation (Section 4, Eq. 3; Section 6.2.2): volt complex int8 (re, im) [S][F][A][2 pols];
+ * T = S / n_int integration intervals, C = F / n_favg output channels (both must divide).
+ * vis: out complex64 [T][C][P][B], B = A (A - 1) / 2 cross baselines (i, j), i > j,
+ * b = i (i - 1) / 2 + j; P = 4 products (XX, XY, YX, YY) for pol_mode 4, or P = 2 (XX, YY) for
+ * pol_mode 2; V = (sum over the n_int samples and n_favg channels of x_{i,p} conj(x_{j,q}))
+ * / (n_int n_favg), the sums exact in int64, the division in double, rounded once to float.
+ * autos: out complex64 [T][C][A][4] (products XX, XY, YX, YY of each antenna with itself) or NULL. */
+int blink_ref_correlate(const int8_t *volt, int S, int F, int A, int n_int, int n_favg, int pol_mode,
+                        float *vis, float *autos);
+
 /* Number of threads blink_ref_image_batch would use for n_threads <= 0. */
 int blink_ref_max_threads(void);
 

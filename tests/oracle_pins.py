@@ -521,9 +521,81 @@ def pin_corrections_phase_centre(O):
     assert (plain["images"][:, :, 0, N // 2, N // 2] < 0.9 * S).all()
 
 
+# ----------------------------------------------------------------------------- correlation
+
+def numpy_correlate(volt, n_int, n_favg, pol_mode):
+    """Eq. 3 as a complex matrix product X X^H per (interval, output channel), numpy complex128."""
+    x = volt[..., 0].astype(np.float64) + 1j * volt[..., 1].astype(np.float64)     # [S][F][A][2]
+    S, F, A, _ = x.shape
+    T, C = S // n_int, F // n_favg
+    x = x.reshape(T, n_int, C, n_favg, A * 2).transpose(0, 2, 4, 1, 3).reshape(T, C, A * 2, n_int * n_favg)
+    R = x @ np.conj(x).transpose(0, 1, 3, 2) / (n_int * n_favg)                    # [T][C][2A][2A]
+    rows, cols = np.tril_indices(A, k=-1)
+    prods = [(0, 0), (0, 1), (1, 0), (1, 1)] if pol_mode == 4 else [(0, 0), (1, 1)]
+    vis = np.stack([R[:, :, 2 * rows + p, 2 * cols + q] for p, q in prods], axis=2)
+    autos = np.stack([R[:, :, 2 * np.arange(A) + p, 2 * np.arange(A) + q] for p, q in
+                      [(0, 0), (0, 1), (1, 0), (1, 1)]], axis=3)
+    return vis.astype(np.complex64), autos.astype(np.complex64)
+
+
+def pin_correlate_matrix_product(O):
+    """The correlator equals X X^H computed by numpy, exactly (integer sums, one rounding)."""
+    g = np.random.default_rng(60)
+    volt = g.integers(-128, 128, size=(12, 6, 5, 2, 2)).astype(np.int8)
+    for n_int, n_favg in ((3, 2), (12, 1), (1, 6)):
+        for mode in (4, 2):
+            got = O.correlate(volt, n_int, n_favg, mode)
+            vis, autos = numpy_correlate(volt, n_int, n_favg, mode)
+            assert np.array_equal(got["vis"], vis), (n_int, n_favg, mode)
+            assert np.array_equal(got["autos"], autos), (n_int, n_favg, mode)
+
+
+def pin_correlate_quarter_turns(O):
+    """Antenna voltages 100 i^m (X) and 50 i^n (Y), with m, n fixed per antenna and channel: every
+    product is exact, e.g. XY of (i, j) = 5000 i^(m_i - n_j), and the autocorrelations are real
+    powers 10000 and 2500."""
+    g = np.random.default_rng(61)
+    S, F, A = 4, 2, 6
+    m = g.integers(0, 4, size=(F, A))
+    n = g.integers(0, 4, size=(F, A))
+    unit = {0: (1, 0), 1: (0, 1), 2: (-1, 0), 3: (0, -1)}
+    volt = np.zeros((S, F, A, 2, 2), dtype=np.int8)
+    for f, a in np.ndindex(F, A):
+        volt[:, f, a, 0] = [100 * unit[m[f, a]][0], 100 * unit[m[f, a]][1]]
+        volt[:, f, a, 1] = [50 * unit[n[f, a]][0], 50 * unit[n[f, a]][1]]
+    res = O.correlate(volt, S, 1, 4)
+    ph = lambda k: 1j ** (k % 4)
+    b = 0
+    for i in range(1, A):
+        for j in range(i):
+            for f in range(F):
+                want = [10000 * ph(m[f, i] - m[f, j]), 5000 * ph(m[f, i] - n[f, j]),
+                        5000 * ph(n[f, i] - m[f, j]), 2500 * ph(n[f, i] - n[f, j])]
+                assert np.allclose(res["vis"][0, f, :, b], want, rtol=0, atol=0), (i, j, f)
+            b += 1
+    assert np.array_equal(res["autos"][0, :, :, 0], np.full((F, A), 10000, np.complex64))
+    assert np.array_equal(res["autos"][0, :, :, 3], np.full((F, A), 2500, np.complex64))
+
+
+def pin_correlate_averaging_groups(O):
+    """A real X voltage a(s, f) common to all antennas: every XX visibility is the mean of a^2
+    over its own block of n_int samples and n_favg channels (numpy's mean over the blocks)."""
+    S, F, A, n_int, n_favg = 6, 8, 3, 3, 4
+    a = (np.arange(S)[:, None] + 1) + 7 * np.arange(F)[None, :]
+    a = (a % 127).astype(np.int8)
+    volt = np.zeros((S, F, A, 2, 2), dtype=np.int8)
+    volt[:, :, :, 0, 0] = a[:, :, None]
+    res = O.correlate(volt, n_int, n_favg, 2)
+    power = (a.astype(np.float64) ** 2).reshape(S // n_int, n_int, F // n_favg, n_favg).mean(axis=(1, 3))
+    for b in range(A * (A - 1) // 2):
+        assert np.array_equal(res["vis"][:, :, 0, b], power.astype(np.complex64))
+        assert not res["vis"][:, :, 1, b].any()
+
+
 EXTRA_PINS = [pin_image_average, pin_es_kernel_values, pin_es_transform, pin_conv_width1_is_nearest_cell,
               pin_conv_hermitian, pin_conv_matches_direct_transform, pin_conv_batch_consistency,
-              pin_corrections_identity, pin_corrections_undo_gains, pin_corrections_phase_centre]
+              pin_corrections_identity, pin_corrections_undo_gains, pin_corrections_phase_centre,
+              pin_correlate_matrix_product, pin_correlate_quarter_turns, pin_correlate_averaging_groups]
 
 
 PINS = [pin_cell_worked, pin_tiny_grid, pin_ifft1d_bruteforce, pin_ifft2d_bruteforce,

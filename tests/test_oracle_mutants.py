@@ -52,6 +52,15 @@ MUTANTS = {
     "corr_antennas_swapped": ("ant_i[b] = i; ant_j[b] = j;", "ant_i[b] = j; ant_j[b] = i;"),
     "corr_frequency_missing": ("const double cycles_per_metre = freq_hz[c] / SPEED_OF_LIGHT;",
                                "const double cycles_per_metre = 150.0e6 / SPEED_OF_LIGHT;"),
+    # correlation
+    "cmac_conjugate_on_first": ("sim += (int64_t)xi[1] * xj[0] - (int64_t)xi[0] * xj[1];",
+                                "sim += (int64_t)xi[0] * xj[1] - (int64_t)xi[1] * xj[0];"),
+    "cmac_pol_products_swapped": ("if (P == 4) pp = 2 * p + q;", "if (P == 4) pp = p + 2 * q;"),
+    "cmac_norm_missing_channels": ("const double count = (double)n_int * (double)n_favg;",
+                                   "const double count = (double)n_int;"),
+    "cmac_channel_groups_wrong": ("for (int f = c * n_favg; f < (c + 1) * n_favg; ++f)",
+                                  "for (int f = c; f < c + n_favg; ++f)"),
+    "cmac_baseline_order": ("const long b = (long)i * (i - 1) / 2 + j;", "const long b = (long)j * (j - 1) / 2 + i;"),
 }
 
 
