@@ -183,6 +183,26 @@ blink_status blink_image_batch_corrected(blink_ctx ctx, const blink_cf32 *vis, c
                                          float *images, double *weight_sum, int32_t *n_out,
                                          void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* ---------------------------------------------------------------- correlation
+ * The step before the corrections (Section 6.2.2; Section 4, Eq. 3): the conjugate
+ * multiply-accumulate of every pair of fine-channelised antenna voltages, averaged over an
+ * integration interval and over the fine channels of an output channel, written in the layout
+ * blink_image_batch reads.
+ *   volt     device complex int8 (re, im bytes) [S samples][F fine channels][A antennas][2 pols]
+ *   vis      out complex64 [T][C][pol_mode][B]: T = S / n_int, C = F / n_favg,
+ *            B = A (A - 1) / 2 cross baselines (i, j), i > j, b = i (i - 1) / 2 + j; products
+ *            XX, XY, YX, YY (pol_mode 4) or XX, YY (pol_mode 2, directly imageable with P = 2)
+ *   autos    out complex64 [T][C][A][4] (XX, XY, YX, YY of each antenna with itself) or NULL
+ * V = (sum over the n_int samples and n_favg channels of x_{i,p} conj(x_{j,q})) / (n_int n_favg):
+ * the sums are exact (int32 on the matrix cores), the division is done in FP64 and rounded once,
+ * so the result is exactly the rounded mean. Requires volt 16-byte aligned, 4 <= A <= 256 with
+ * A % 4 == 0, n_int | S,
+ * n_favg | F, n_int n_favg <= 65535 (keeps the sums in int32), T and C <= 65535; otherwise
+ * ERR_ARG. No workspace. */
+blink_status blink_correlate(blink_ctx ctx, const int8_t *volt, int S, int F, int A, int n_int,
+                             int n_favg, int pol_mode, blink_cf32 *vis, blink_cf32 *autos,
+                             void *hip_stream);
+
 /* ---------------------------------------------------------------- convolutional gridding
  * A step beyond the paper, which places visibilities on their nearest cell with no convolution
  * kernel (Section 6.2.4) and names a gridding kernel against aliasing as planned work (Sections 7
@@ -347,7 +367,8 @@ enum {
     BLINK_KERNEL_CONV_CORRECTION = 8, /* grid-correction table of the convolutional path */
     BLINK_KERNEL_AVERAGE = 9,      /* image averages (blink_image_average) */
     BLINK_KERNEL_CORRECT = 10,     /* visibility corrections (blink_image_batch_corrected) */
-    BLINK_KERNEL_COUNT = 11
+    BLINK_KERNEL_CORRELATE = 11,   /* correlator (blink_correlate) */
+    BLINK_KERNEL_COUNT = 12
 };
 
 /* Enable (nonzero) or disable timing; either way the recorded launches are discarded. */

@@ -21,7 +21,7 @@ PLANS_PATH = os.path.join(PKG, "plans_gfx950.json")     # autotuned execution pl
 BLINK_OK, BLINK_ERR_ARG, BLINK_ERR_SIZE, BLINK_ERR_NOMEM, BLINK_ERR_HIP, BLINK_ERR_STATE = range(6)
 WEIGHT_NATURAL, WEIGHT_UNIFORM = 0, 1
 KERNELS = ("bin", "grid", "grid_colfft", "dense_colfft", "weights", "row_fft", "desc_prep", "persistent",
-           "conv_correction", "average", "correct")
+           "conv_correction", "average", "correct", "correlate")
 AVG_TIME, AVG_CHANNEL, AVG_POL = 1, 2, 4   # BLINK_KERNEL_* ids
 DESC_BAD = 1
 
@@ -95,6 +95,8 @@ def lib() -> ctypes.CDLL:
     L.blink_image_batch_corrected.restype = i32
     L.blink_image_batch_corrected.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32,
                                               ctypes.POINTER(Corrections), P, P, P, P, sz, P]
+    L.blink_correlate.restype = i32
+    L.blink_correlate.argtypes = [P, P, i32, i32, i32, i32, i32, i32, P, P, P]
     L.blink_plan_options.restype = i32
     L.blink_plan_options.argtypes = [i32, i32, P, P, P, P]
     L.blink_get_plan.restype = i32
@@ -524,6 +526,29 @@ class Context:
                                                _ptr(n_out), _ptr(ws), ws.numel(), self._stream(stream))
         _check(st, self.handle, "blink_image_batch_corrected")
         return {"images": out, "weight_sum": weight_sum, "n_out": n_out}
+
+    def blink_correlate(self, volt, n_int: int, n_favg: int = 1, pol_mode: int = 4, autos: bool = False, out=None,
+                        autos_out=None, stream=None):
+        """Correlator: volt int8 device tensor [S][F][A][2][2] (re, im). Returns dict(vis complex64
+        [T][C][pol_mode][B], autos complex64 [T][C][A][4] or None)."""
+        torch = self._torch()
+        self._require("volt", volt, torch.int8)
+        if volt.dim() != 5 or tuple(volt.shape[3:]) != (2, 2):
+            raise ValueError(f"volt must be [S][F][A][2][2], got {tuple(volt.shape)}")
+        S, F, A = (int(x) for x in volt.shape[:3])
+        T, C, B = S // int(n_int), F // int(n_favg), A * (A - 1) // 2
+        dev = volt.device
+        if out is None:
+            out = torch.empty((T, C, pol_mode, B), dtype=torch.complex64, device=dev)
+        self._require("out", out, torch.complex64, (T, C, pol_mode, B))
+        if autos and autos_out is None:
+            autos_out = torch.empty((T, C, A, 4), dtype=torch.complex64, device=dev)
+        if autos_out is not None:
+            self._require("autos_out", autos_out, torch.complex64, (T, C, A, 4))
+        st = lib().blink_correlate(self.handle, _ptr(volt), S, F, A, int(n_int), int(n_favg), int(pol_mode), _ptr(out),
+                                   _ptr(autos_out), self._stream(stream))
+        _check(st, self.handle, "blink_correlate")
+        return {"vis": out, "autos": autos_out}
 
     def blink_image_average(self, images, axes: int, out=None, stream=None):
         """Average float32 images [T][C][P][N][N] over the axes in `axes` (AVG_TIME | AVG_CHANNEL |

@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libblink.so")
 # (source, extra defines): split.hip is built once per split precision (1 = FP16, 2 = BF16).
-UNITS = [("kernels.hip", []), ("persistent.hip", []), ("api.hip", []),
+UNITS = [("kernels.hip", []), ("persistent.hip", []), ("api.hip", []), ("correlate.hip", []),
          ("split.hip", ["-DBLINK_SPLIT_PREC=1"]), ("split.hip", ["-DBLINK_SPLIT_PREC=2"])]
 SOURCES = sorted({os.path.join(CSRC, f) for f, _ in UNITS})
 

@@ -731,6 +731,45 @@ blink_status blink_image_batch_corrected(blink_ctx ctx, const blink_cf32* vis, c
                      corr, images, weight_sum, n_out, workspace, workspace_bytes, hip_stream);
 }
 
+blink_status blink_correlate(blink_ctx ctx, const int8_t* volt, int S, int F, int A, int n_int, int n_favg,
+                             int pol_mode, blink_cf32* vis, blink_cf32* autos, void* hip_stream) {
+  if (!ctx) return BLINK_ERR_ARG;
+  if (S < 0 || F < 0 || n_int < 1 || n_favg < 1 || (pol_mode != 2 && pol_mode != 4))
+    return fail(ctx, BLINK_ERR_ARG, "bad correlator arguments (S=%d F=%d n_int=%d n_favg=%d pol_mode=%d)", S, F, n_int,
+                n_favg, pol_mode);
+  if (A < 4 || A > 256 || A % 4 != 0)
+    return fail(ctx, BLINK_ERR_ARG, "the correlator takes 4 .. 256 antennas in multiples of 4 (A=%d)", A);
+  if (S % n_int != 0 || F % n_favg != 0)
+    return fail(ctx, BLINK_ERR_ARG, "n_int=%d must divide S=%d and n_favg=%d must divide F=%d", n_int, S, n_favg, F);
+  if ((long long)n_int * n_favg > 65535 || S / n_int > 65535 || F / n_favg > 65535)
+    return fail(ctx, BLINK_ERR_ARG, "n_int n_favg above 65535 or more than 65535 intervals or channels");
+  if (S == 0 || F == 0) return BLINK_OK;
+  if (!volt || !vis) return fail(ctx, BLINK_ERR_ARG, "null voltage or visibility pointer");
+  if (reinterpret_cast<uintptr_t>(volt) % 16 != 0)
+    return fail(ctx, BLINK_ERR_ARG, "the voltage array must be 16-byte aligned");
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)hip_stream;
+  blink::CorrelateArgs ca{};
+  ca.volt = volt;
+  ca.S = S;
+  ca.F = F;
+  ca.A = A;
+  ca.n_int = n_int;
+  ca.n_favg = n_favg;
+  ca.pol_mode = pol_mode;
+  ca.n_slabs = (2 * A + 31) / 32;
+  ca.vis = (float2*)vis;
+  ca.autos = (float2*)autos;
+  hipError_t e;
+  {
+    KernelTimer kt(ctx, BLINK_KERNEL_CORRELATE, s);
+    e = blink::launch_correlate(ca, s);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "correlator kernel");
+  return BLINK_OK;
+}
+
 blink_status blink_image_batch_conv_workspace_size(int T, int C, int P, int B, int grid_n, int kernel_width,
                                                    int precision, size_t* bytes) {
   if (!bytes || T < 0 || C < 0 || P < 1 || B < 0) return BLINK_ERR_ARG;

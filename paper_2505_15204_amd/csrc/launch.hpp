@@ -125,6 +125,22 @@ struct CorrArgs {
 };
 hipError_t launch_correct_vis(const CorrArgs& a, hipStream_t s);
 
+// Correlator (Section 4, Eq. 3; Section 6.2.2): volt complex int8 [S][F][A][2 pols] (re, im);
+// vis complex64 [T][C][pol_mode][B] (B = A (A - 1) / 2, b = i (i - 1) / 2 + j, i > j; products
+// XX, XY, YX, YY for pol_mode 4, XX, YY for 2), autos complex64 [T][C][A][4] or null;
+// T = S / n_int, C = F / n_favg. The caller has checked 4 <= A <= 256, A % 4 == 0, the
+// divisibility, n_int n_favg <= 65535 and T, C <= 65535.
+struct CorrelateArgs {
+  const int8_t* volt;
+  int S, F, A, n_int, n_favg, pol_mode;
+  int n_slabs;              // ceil(2A / 32)
+  int C;                    // set by the launcher
+  float2* vis;
+  float2* autos;
+};
+size_t correlate_lds_bytes(int A);
+hipError_t launch_correlate(const CorrelateArgs& a, hipStream_t s);
+
 // Averages of images [T][C][P][N][N] over the axes in `axes` (1 time, 2 channel, 4 pol).
 hipError_t launch_image_average(const float* in, int T, int C, int P, int logn, int axes, float* out, hipStream_t s);
 
