@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 
 METRIC = "dirty images/sec (1024² grid, 8128 baselines) and % HBM roofline; MFMA vs FP32"
 HBM_PEAK_GBS = 8000.0
+INT8_PEAK_TOPS = 5000.0     # dense int8 matrix-core peak of the MI355X
 
 
 def log(msg):
@@ -149,6 +150,40 @@ def profiled(ctx, torch, fn, steps):
     prof = ctx.profile_read()
     ctx.profile_enable(False)
     return prof, ms
+
+
+def bench_correlator(ctx, torch, steps, warmup):
+    """The correlator on the high-time-resolution shape: 128 tiles x 2 pols, 3072 fine channels of
+    10 kHz averaged by 4 into 768 output channels of 40 kHz, 100 us samples integrated over 20 ms
+    (n_int = 200); a step correlates 10 intervals (0.2 s of data, 3.1 GB of int8 voltages)."""
+    A, F, n_int, n_favg, T = 128, 3072, 200, 4, 10
+    S = n_int * T
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(30)
+    volt = torch.randint(-128, 128, (S, F, A, 2, 2), generator=gen, device="cuda:0", dtype=torch.int8)
+    C, B, K = F // n_favg, A * (A - 1) // 2, n_int * n_favg
+    out = {"workload": "correlator: 128 tiles x 2 pols, 3072 x 10 kHz fine channels -> 768 x 40 kHz, 100 us samples, "
+                       "20 ms integrations; a step is 10 integrations (0.2 s of data)",
+           "input_bytes_per_step": S * F * A * 4}
+    for mode in (4, 2):
+        vis = torch.empty((T, C, mode, B), dtype=torch.complex64, device="cuda:0")
+        ms = timed(torch, lambda i: ctx.blink_correlate(volt, n_int, n_favg, mode, out=vis), steps, warmup) / steps
+        # algorithmic work: every needed product of every pair over K terms, 8 integer ops per
+        # complex multiply-accumulate; bytes: read the voltages once, write the visibilities
+        ops = T * C * (B * mode) * K * 8
+        nbytes = S * F * A * 4 + T * C * mode * B * 8
+        out[f"pol_mode_{mode}"] = {
+            "ms_per_step": round(ms, 4),
+            "data_seconds_per_second": round(0.2 / (ms / 1e3), 2),
+            "achieved_TOP_s": round(ops / (ms / 1e3) / 1e12, 1),
+            "frac_int8_mfma": round(ops / (ms / 1e3) / 1e12 / INT8_PEAK_TOPS, 4),
+            "achieved_GB_s": round(nbytes / (ms / 1e3) / 1e9, 1),
+            "frac_hbm": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"correlator pol_mode {mode}: {ms:.3f} ms per 0.2 s of data, "
+            f"{ops / (ms / 1e3) / 1e12:.0f} TOP/s, {nbytes / (ms / 1e3) / 1e9:.0f} GB/s")
+        del vis
+    del volt
+    return out
 
 
 def bench_precision_workload(ctx, torch, blink, synth, steps, warmup):
@@ -393,6 +428,7 @@ def main():
             "frac_hbm": round(moved / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
         log(f"Stokes I + band average of {C * P} images: {ms:.3f} ms "
             f"({moved / (ms / 1e3) / 1e9:.0f} GB/s)")
+        forms["correlator"] = bench_correlator(ctx, torch, 5, 2)
         forms["precision-4096"] = bench_precision_workload(ctx, torch, blink, synth, 3, 1)
         forms["uneven"] = bench_uneven(ctx, torch, blink, synth, 3)
 
