@@ -7,13 +7,15 @@
 //   (re, im)_r . (re, im)_c = sum Xr[r] Xr[c] + Xi[r] Xi[c]       = Re R[r][c]
 //   (im, ~re)_r . (re, im)_c = sum Xi[r] Xr[c] + (~Xr[r]) Xi[c]  = Im R[r][c] - sum Xi[c]
 // with ~x = -x - 1 the bitwise complement (exact in int8, unlike -x for x = -128); the per-input
-// sum of Xi over K is added back at the end. Each 32 x 32 output tile therefore needs two
+// sum of Xi over K is added back at the end. Both byte layouts are staged in LDS (planes P and
+// Q), so the products read their operands directly. Each 32 x 32 output tile therefore needs two
 // int32 accumulators and two v_mfma_i32_32x32x32_i8 per 16 terms, all exact
 // (|R| <= 2 K 128^2 < 2^31 for K <= 65535). Only the tiles on or below the diagonal are
-// formed. A workgroup owns up to 12 tiles (three per wave) of one (interval, channel) and keeps
-// their accumulators in registers over all of K; K is staged through LDS in chunks of 64 terms
-// (each input's 128 bytes contiguous), and the global loads of the next chunk are issued before
-// the current chunk's matrix products.
+// formed. A workgroup owns up to 12 tiles (three per wave, along tile rows so that a row's
+// operands are read once per step) of one (interval, channel) and keeps their accumulators in
+// registers over all of K; K is staged through LDS in chunks of 64 terms (each
+// input's 128 bytes contiguous), and the global loads of the next chunk are issued before the
+// current chunk's matrix products.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -35,19 +37,31 @@ constexpr int kTilesPerGroup = kTilesPerWave * kWaves;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kItemsPerSlab = 4 * (kKc / 8);   // (8-input group, 8-term octet) pairs per 32-input slab
 
-// Tile tau of the lower triangle in row order: (a, b), b <= a, tau = a (a + 1) / 2 + b.
+// Tile tau of the lower triangle in row order: (a, b), b <= a, tau = a (a + 1) / 2 + b (at most
+// 16 tile rows).
 __device__ __forceinline__ void tile_of(int tau, int& a, int& b) {
-  int r = (int)((sqrt(8.0 * tau + 1.0) - 1.0) * 0.5);
-  while (r * (r + 1) / 2 > tau) --r;
+  int r = 0;
   while ((r + 1) * (r + 2) / 2 <= tau) ++r;
   a = r;
   b = tau - r * (r + 1) / 2;
 }
 
-// (re, im) byte pairs -> (im, ~re)
-__device__ __forceinline__ int swap_complement(int x) {
-  const unsigned u = (unsigned)x;
-  return (int)(((u >> 8) & 0x00ff00ffu) | ((~u << 8) & 0xff00ff00u));
+// x / K rounded once to float, for an integer |x| < 2^32 and K <= 65535, inv = 1/K rounded to
+// double. qd = x inv is within 2^-52 (relative) of the quotient q; q is either a float rounding
+// midpoint itself or at least 2^-49 (relative) away from every midpoint (a nonzero difference of
+// two fractions with denominators K and 2^e), so (float)qd rounds q correctly except on an exact
+// midpoint, which is detected exactly (m K == x has at most 41 significant bits) and resolved to
+// the even neighbour. This is the value of (float)((double)x / K).
+__device__ __forceinline__ float mean_rn(double x, double K, double inv) {
+  const double qd = x * inv;
+  const float f = (float)qd;
+  const unsigned bits = __float_as_uint(f);
+  if ((bits & 1u) && qd != (double)f) {
+    const float g = __uint_as_float(fabs(qd) > fabs((double)f) ? bits + 1 : bits - 1);
+    const double m = 0.5 * ((double)f + (double)g);
+    if (m * K == x) return g;
+  }
+  return f;
 }
 
 // One staging item: 16 bytes (8 inputs, re and im) for each of 8 consecutive terms.
@@ -58,11 +72,12 @@ struct Staged {
 // ITEMS: staging items per thread, n_slabs * kItemsPerSlab / kThreads rounded up (1 for up to 128
 // antennas, 2 for up to 256).
 template <int ITEMS>
-__global__ __launch_bounds__(kThreads, 2) void k_correlate(CorrelateArgs a) {
+__global__ __launch_bounds__(kThreads, ITEMS <= 1 ? 2 : 1) void k_correlate(CorrelateArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int IP = a.n_slabs * kTile;               // padded input count
-  unsigned char* x = lds;                         // [IP][kRow]: (re, im) pairs, terms contiguous
-  int* colsum = reinterpret_cast<int*>(lds + (size_t)IP * kRow);   // [IP]: sum of Xi over K
+  unsigned char* x = lds;                         // plane P [IP][kRow]: (re, im) pairs, terms contiguous
+  unsigned char* xq = lds + (size_t)IP * kRow;    // plane Q [IP][kRow]: (im, ~re) pairs
+  int* colsum = reinterpret_cast<int*>(lds + (size_t)2 * IP * kRow);   // [IP]: sum of Xi over K
   __shared__ unsigned s_need;                     // bit s: slab s is used by this workgroup
 
   const int group = blockIdx.x, c = blockIdx.y, t = blockIdx.z;
@@ -100,13 +115,18 @@ __global__ __launch_bounds__(kThreads, 2) void k_correlate(CorrelateArgs a) {
   __syncthreads();
   const unsigned need = s_need;
 
-  // item -> (slab, 8-input group v < 4, term octet o < kKc / 8)
+  // item -> (8-input group rg, term octet o): consecutive items are consecutive input groups, so
+  // the lanes of a wave read whole (sample, channel) records (coalesced)
+  const int n_groups = a.n_slabs * 4;
   auto item_rows = [&](int item, int& slab, int& row0, int& o) {
-    slab = item / kItemsPerSlab;
-    const int rest = item % kItemsPerSlab;
-    row0 = slab * kTile + (rest / (kKc / 8)) * 8;
-    o = rest % (kKc / 8);
+    const int rg = item % n_groups;
+    o = item / n_groups;
+    row0 = rg * 8;
+    slab = rg / 4;
   };
+  // LDS position of term octet o of input row: octets are XOR-swizzled by the row's input group
+  // so that the transposed stores of a wave (many groups, one octet) spread over the banks
+  auto octet_at = [](int row, int o) { return 16 * (o ^ ((row >> 3) & 7)); };
   // global loads of one chunk's items of this thread (unused slabs, inputs past 2A and terms
   // past K are not loaded and stage zeros)
   auto load = [&](int k0, Staged (&st)[ITEMS]) {
@@ -133,8 +153,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_correlate(CorrelateArgs a) {
       }
     }
   };
-  // transpose: row row0 + r gets the (re, im) pairs of its 8 terms as one 16-byte vector; the
-  // imaginary parts are summed per row in registers (a thread stages the same rows every chunk)
+  // transpose: row row0 + r gets the (re, im) pairs of its 8 terms as one 16-byte vector in P and
+  // the (im, ~re) pairs in Q (byte permutes of two loaded words each); the imaginary parts are
+  // summed per row in registers (a thread stages the same rows every chunk)
   int isums[ITEMS][8];
 #pragma unroll
   for (int m = 0; m < ITEMS; ++m)
@@ -149,7 +170,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_correlate(CorrelateArgs a) {
       if (!(item < n_items && ((need >> slab) & 1u))) continue;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        unsigned d[4];
+        // v_perm_b32 byte selectors (0-3: bytes of the second source, 4-7: of the first): row r's
+        // (re, im) pair is bytes j, j + 1 of its word, j = 2 (r % 2)
+        const unsigned j = 2u * (r % 2);
+        const unsigned sel_p = j | (j + 1) << 8 | (j + 4) << 16 | (j + 5) << 24;
+        const unsigned sel_q = (j + 1) | j << 8 | (j + 5) << 16 | (j + 4) << 24;
+        unsigned d[4], e[4];
         int isum = isums[m][r];
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
@@ -157,42 +183,52 @@ __global__ __launch_bounds__(kThreads, 2) void k_correlate(CorrelateArgs a) {
           const uint4& w1 = st[m].w[2 * h + 1];
           const unsigned a0 = r < 2 ? w0.x : r < 4 ? w0.y : r < 6 ? w0.z : w0.w;
           const unsigned a1 = r < 2 ? w1.x : r < 4 ? w1.y : r < 6 ? w1.z : w1.w;
-          const unsigned sh = 16 * (r % 2);
-          d[h] = ((a0 >> sh) & 0xffffu) | (((a1 >> sh) & 0xffffu) << 16);
+          d[h] = __builtin_amdgcn_perm(a1, a0, sel_p);                 // (re, im) of terms 2h, 2h + 1
+          e[h] = __builtin_amdgcn_perm(a1, a0, sel_q) ^ 0xff00ff00u;   // (im, ~re)
           isum = __builtin_amdgcn_sdot4((int)d[h], 0x01000100, isum, false);   // the two im bytes
         }
-        *reinterpret_cast<uint4*>(x + (size_t)(row0 + r) * kRow + 16 * o) = make_uint4(d[0], d[1], d[2], d[3]);
+        const size_t at = (size_t)(row0 + r) * kRow + octet_at(row0 + r, o);
+        *reinterpret_cast<uint4*>(x + at) = make_uint4(d[0], d[1], d[2], d[3]);
+        *reinterpret_cast<uint4*>(xq + at) = make_uint4(e[0], e[1], e[2], e[3]);
         isums[m][r] = isum;
       }
     }
   };
 
-  Staged st[ITEMS];
-  load(0, st);
-  for (int k0 = 0; k0 < K; k0 += kKc) {
+  // one chunk: stage the registers st into LDS, request the next chunk into st (answered during
+  // this chunk's products), then the products
+  auto chunk = [&](int k0, Staged (&st)[ITEMS]) {
     store(st);
     __syncthreads();
-    if (k0 + kKc < K) load(k0 + kKc, st);          // answered during this chunk's products
+    if (k0 + kKc < K) load(k0 + kKc, st);
+    // the wave's tiles run along tile rows (row order), so the row operands A and As are read
+    // once per tile row and step and reused by the following tiles of that row
 #pragma unroll
-    for (int u = 0; u < kTilesPerWave; ++u) {
-      if (!tv[u]) continue;
-      const unsigned char* pa = x + (size_t)(ta[u] * kTile + n) * kRow + 16 * g;
-      const unsigned char* pb = x + (size_t)(tb[u] * kTile + n) * kRow + 16 * g;
+    for (int kk = 0; kk < 2 * kKc; kk += 32) {
+      const int q = kk / 16 + g;                    // this lane's term octet of the step
+      v4i A = {}, As = {};
+      int cur = -1;
 #pragma unroll
-      for (int kk = 0; kk < 2 * kKc; kk += 32) {
-        const v4i A = *reinterpret_cast<const v4i*>(pa + kk);
-        const v4i B = *reinterpret_cast<const v4i*>(pb + kk);
-        v4i As;
-        As.x = swap_complement(A.x);
-        As.y = swap_complement(A.y);
-        As.z = swap_complement(A.z);
-        As.w = swap_complement(A.w);
+      for (int u = 0; u < kTilesPerWave; ++u) {
+        if (!tv[u]) continue;
+        if (ta[u] != cur) {
+          cur = ta[u];
+          const int rowa = cur * kTile + n;
+          const size_t oa = (size_t)rowa * kRow + octet_at(rowa, q);
+          A = *reinterpret_cast<const v4i*>(x + oa);
+          As = *reinterpret_cast<const v4i*>(xq + oa);
+        }
+        const int rowb = tb[u] * kTile + n;
+        const v4i B = *reinterpret_cast<const v4i*>(x + (size_t)rowb * kRow + octet_at(rowb, q));
         re[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B, re[u], 0, 0, 0);
         im[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(As, B, im[u], 0, 0, 0);
       }
     }
     __syncthreads();   // the chunk's operands are read before the next chunk overwrites them
-  }
+  };
+  Staged st[ITEMS];
+  load(0, st);
+  for (int k0 = 0; k0 < K; k0 += kKc) chunk(k0, st);
 #pragma unroll
   for (int m = 0; m < ITEMS; ++m) {
     const int item = (int)threadIdx.x + m * kThreads;
@@ -206,7 +242,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_correlate(CorrelateArgs a) {
   __syncthreads();
 
   // Output: element v of the lane is R[32 a + 8 (v / 4) + 4 g + v % 4][32 b + n].
-  const double count = (double)K;
+  const double count = (double)K, inv = 1.0 / count;
   const long B = (long)a.A * (a.A - 1) / 2;
 #pragma unroll
   for (int u = 0; u < kTilesPerWave; ++u) {
@@ -219,8 +255,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_correlate(CorrelateArgs a) {
       if (ri >= in2 || ci >= in2) continue;
       const int i = ri / 2, p = ri % 2, j = ci / 2, q = ci % 2;
       if (i < j) continue;
-      const float vr = (float)((double)re[u][v] / count);
-      const float vi = (float)(((double)im[u][v] + (double)csum) / count);
+      const float vr = mean_rn((double)re[u][v], count, inv);
+      const float vi = mean_rn((double)im[u][v] + (double)csum, count, inv);
       if (i == j) {
         if (a.autos) a.autos[(((size_t)t * a.C + c) * a.A + i) * 4 + 2 * p + q] = make_float2(vr, vi);
         continue;
@@ -239,7 +275,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_correlate(CorrelateArgs a) {
 
 size_t correlate_lds_bytes(int A) {
   const int slabs = (2 * A + kTile - 1) / kTile;
-  return (size_t)slabs * kTile * (kRow + sizeof(int));
+  return (size_t)slabs * kTile * (2 * kRow + sizeof(int));
 }
 
 hipError_t launch_correlate(const CorrelateArgs& a, hipStream_t s) {

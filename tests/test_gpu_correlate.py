@@ -113,3 +113,22 @@ def test_correlate_argument_errors(torch, ctx):
     flat = torch.zeros(4 * 2 * 8 * 4 + 16, dtype=torch.int8, device="cuda:0")
     with pytest.raises(blink.BlinkError):
         ctx.blink_correlate(flat[2:2 + 4 * 2 * 8 * 4].view(4, 2, 8, 2, 2), 2, 1)   # not 16-byte aligned
+
+
+def test_correlate_rounds_exact_midpoint_to_even(torch, ctx):
+    """A mean that is exactly halfway between two floats: XX of baseline (1, 0) sums to
+    3 (2^24 + 1) over K = 6144 terms, so V = 16777217 / 2048 = 8192 + 2^-11, the midpoint of
+    8192 and 8192 + 2^-10; rounded to even it is 8192 on both sides."""
+    S, F, A, n_int, n_favg = 2048, 3, 4, 2048, 3
+    volt = np.zeros((S, F, A, 2, 2), dtype=np.int8)
+    volt[:, :, 0, 0] = (64, 64)
+    volt[:, :, 1, 0] = (64, 64)
+    for s in range(3):                        # three terms of 64 * 62 + 65 * 65 = 8193
+        volt[s, 0, 0, 0] = (64, 65)
+        volt[s, 0, 1, 0] = (62, 65)
+    say("blink_correlate exact rounding midpoint, K=6144")
+    res = ctx.blink_correlate(torch.from_numpy(volt).to("cuda:0"), n_int, n_favg, 4, autos=True)
+    ref = oracle.correlate(volt, n_int, n_favg, 4)
+    assert ref["vis"][0, 0, 0, 0].real == np.float32(8192.0)
+    assert np.array_equal(res["vis"].cpu().numpy(), ref["vis"])
+    assert np.array_equal(res["autos"].cpu().numpy(), ref["autos"])
