@@ -268,6 +268,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the split-precision and uneven-batch measurements beside the headline")
     ap.add_argument("--form-steps", type=int, default=20, help="steps per split-precision form measurement")
+    ap.add_argument("--only-correlator", action="store_true",
+                    help="only measure the correlator form (for profiling it alone); prints its JSON")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy (read + write of this many MiB) --steps times; used "
                          "to scale the HBM byte counters")
@@ -295,6 +297,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
                           "launches": args.steps}), flush=True)
+        return
+    if args.only_correlator:
+        ctx = blink.Context(0)
+        print(json.dumps({"form": "correlator", **bench_correlator(ctx, torch, args.steps, args.warmup)}), flush=True)
+        ctx.close()
         return
     spec = synth.spec_vcs()
     T, C, P, B, N = spec.T, spec.C, spec.P, spec.B, spec.grid_n

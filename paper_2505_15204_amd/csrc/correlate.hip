@@ -80,7 +80,14 @@ __global__ __launch_bounds__(kThreads, ITEMS <= 1 ? 2 : 1) void k_correlate(Corr
   int* colsum = reinterpret_cast<int*>(lds + (size_t)2 * IP * kRow);   // [IP]: sum of Xi over K
   __shared__ unsigned s_need;                     // bit s: slab s is used by this workgroup
 
-  const int group = blockIdx.x, c = blockIdx.y, t = blockIdx.z;
+  // Workgroups are dispatched to the 8 XCDs in turn (workgroup w to XCD w % 8): the n_groups
+  // workgroups of one (interval, channel) pair are w, w + 8, ..., so they share one XCD's L2 and
+  // the voltages they all stage are read from HBM once.
+  const long w = blockIdx.x, span = 8L * a.n_groups;
+  const int group = (int)((w % span) / 8);
+  const long pair = (w / span) * 8 + w % 8;
+  if (pair >= (long)a.T * a.C) return;             // padding workgroups of the last span
+  const int t = (int)(pair / a.C), c = (int)(pair % a.C);
   const int ntiles = a.n_slabs * (a.n_slabs + 1) / 2;
   const int tau0 = group * kTilesPerGroup;
   const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
@@ -282,9 +289,14 @@ hipError_t launch_correlate(const CorrelateArgs& a, hipStream_t s) {
   const int T = a.S / a.n_int, C = a.F / a.n_favg;
   if (T == 0 || C == 0) return hipSuccess;
   const int ntiles = a.n_slabs * (a.n_slabs + 1) / 2;
-  dim3 grid((unsigned)((ntiles + kTilesPerGroup - 1) / kTilesPerGroup), (unsigned)C, (unsigned)T);
+  const int n_groups = (ntiles + kTilesPerGroup - 1) / kTilesPerGroup;
+  const long n_wg = 8L * n_groups * (((long)T * C + 7) / 8);
+  if (n_wg > 0x7fffffffL) return hipErrorInvalidValue;
   CorrelateArgs b = a;
   b.C = C;
+  b.T = T;
+  b.n_groups = n_groups;
+  const unsigned grid = (unsigned)n_wg;
   const size_t lds_bytes = correlate_lds_bytes(a.A);
   const int items = (a.n_slabs * kItemsPerSlab + kThreads - 1) / kThreads;
   const void* fn = items <= 1 ? reinterpret_cast<const void*>(k_correlate<1>)

@@ -134,7 +134,7 @@ struct CorrelateArgs {
   const int8_t* volt;
   int S, F, A, n_int, n_favg, pol_mode;
   int n_slabs;              // ceil(2A / 32)
-  int C;                    // set by the launcher
+  int C, T, n_groups;       // set by the launcher
   float2* vis;
   float2* autos;
 };
