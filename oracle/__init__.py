@@ -60,6 +60,10 @@ def load(path: str):
     L.blink_ref_correct_vis.argtypes = [P, P, P, i32, i32, i32, i32, P, i32, f64, f64, P]
     L.blink_ref_correlate.restype = i32
     L.blink_ref_correlate.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P]
+    L.blink_ref_dispersion_delays.restype = i32
+    L.blink_ref_dispersion_delays.argtypes = [P, i32, f64, P, i32, P]
+    L.blink_ref_dedisperse.restype = i32
+    L.blink_ref_dedisperse.argtypes = [P, i32, i32, i32, P, i32, i32, P]
     L.blink_ref_max_threads.restype = i32
     L.blink_ref_max_threads.argtypes = []
     L.blink_ref_es_kernel.restype = f64
@@ -229,6 +233,27 @@ class Oracle:
             raise ValueError(f"blink_ref_correlate failed with code {rc}")
         return {"vis": vis, "autos": autos}
 
+    def dispersion_delays(self, freq_hz, dt_s, dms):
+        """Integer delays [n_dm][C] (samples of dt_s) of dispersion measures dms at channels freq_hz."""
+        fr = _c(freq_hz, np.float64)
+        d = _c(np.atleast_1d(dms), np.float64)
+        out = np.empty((d.shape[0], fr.shape[0]), dtype=np.int32)
+        rc = self.L.blink_ref_dispersion_delays(_ptr(fr), fr.shape[0], float(dt_s), _ptr(d), d.shape[0], _ptr(out))
+        if rc != 0:
+            raise ValueError(f"blink_ref_dispersion_delays failed with code {rc}")
+        return out
+
+    def dedisperse(self, images, delays, t_out):
+        """De-dispersed images [n_dm][t_out][N][N] (float64) of images [T][C][N][N] (float32)."""
+        a = _c(images, np.float32)
+        T, C, N, _ = a.shape
+        dl = _c(delays, np.int32)
+        out = np.empty((dl.shape[0], int(t_out), N, N), dtype=np.float64)
+        rc = self.L.blink_ref_dedisperse(_ptr(a), T, C, N, _ptr(dl), dl.shape[0], int(t_out), _ptr(out))
+        if rc != 0:
+            raise ValueError(f"blink_ref_dedisperse failed with code {rc}")
+        return out
+
     def max_threads(self) -> int:
         return int(self.L.blink_ref_max_threads())
 
@@ -336,6 +361,14 @@ def image_batch_corrected(*a, **k):
 
 def correlate(*a, **k):
     return default().correlate(*a, **k)
+
+
+def dispersion_delays(*a, **k):
+    return default().dispersion_delays(*a, **k)
+
+
+def dedisperse(*a, **k):
+    return default().dedisperse(*a, **k)
 
 
 def max_threads() -> int:

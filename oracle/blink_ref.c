@@ -556,3 +556,59 @@ int blink_ref_correlate(const int8_t *volt, int S, int F, int A, int n_int, int 
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------------------------
+ * Incoherent de-dispersion of image cubes (the FRB search that the images feed, Sections 1, 3 and
+ * 10; Table 1 gives a DM of 600 pc cm^-3 and tens of seconds of dispersive delay over the MWA
+ * band). A pulse of dispersion measure DM reaches channel frequency f later than the highest
+ * channel f_ref by k_DM DM (f^-2 - f_ref^-2), k_DM = 4148.808 s MHz^2 cm^3 / pc (the cold-plasma
+ * dispersion constant; frequencies in MHz). In samples of length dt the delay is rounded to the
+ * nearest integer; the de-dispersed image at output step t is the mean over channels of the
+ * channel images at steps t + delay(c).
+ * ------------------------------------------------------------------------------------------ */
+#define K_DM_S_MHZ2 4148.808
+
+int blink_ref_dispersion_delays(const double *freq_hz, int C, double dt_s, const double *dm, int n_dm,
+                                int32_t *delays)
+{
+    if (C < 1 || n_dm < 0 || !(dt_s > 0.0) || !freq_hz || (n_dm > 0 && (!dm || !delays))) return 1;
+    double f_ref = freq_hz[0];
+    for (int c = 1; c < C; ++c)
+        if (freq_hz[c] > f_ref) f_ref = freq_hz[c];
+    const double ref_mhz = f_ref / 1.0e6;
+    for (int k = 0; k < n_dm; ++k) {
+        if (!(dm[k] >= 0.0)) return 1;
+        for (int c = 0; c < C; ++c) {
+            const double f_mhz = freq_hz[c] / 1.0e6;
+            const double delay_s = K_DM_S_MHZ2 * dm[k] * (1.0 / (f_mhz * f_mhz) - 1.0 / (ref_mhz * ref_mhz));
+            delays[(size_t)k * C + c] = (int32_t)nearbyint(delay_s / dt_s);
+        }
+    }
+    return 0;
+}
+
+int blink_ref_dedisperse(const float *images, int T, int C, int grid_n, const int32_t *delays, int n_dm,
+                         int t_out, double *out)
+{
+    if (T < 0 || C < 1 || grid_n < 1 || n_dm < 0 || t_out < 0 || !images || (n_dm > 0 && (!delays || !out)))
+        return 1;
+    const size_t NN = (size_t)grid_n * grid_n;
+    for (int k = 0; k < n_dm; ++k)
+        for (int c = 0; c < C; ++c) {
+            const int32_t d = delays[(size_t)k * C + c];
+            if (d < 0 || (long)t_out + d > T) return 1;
+        }
+    for (int k = 0; k < n_dm; ++k) {
+        for (int t = 0; t < t_out; ++t) {
+            double *o = out + ((size_t)k * t_out + t) * NN;
+            for (size_t i = 0; i < NN; ++i) o[i] = 0.0;
+            for (int c = 0; c < C; ++c) {
+                const int ts = t + delays[(size_t)k * C + c];
+                const float *in = images + ((size_t)ts * C + c) * NN;
+                for (size_t i = 0; i < NN; ++i) o[i] += (double)in[i];
+            }
+            for (size_t i = 0; i < NN; ++i) o[i] /= (double)C;
+        }
+    }
+    return 0;
+}

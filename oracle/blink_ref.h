@@ -131,6 +131,15 @@ int blink_ref_image_average(const float *images, int T, int C, int P, int grid_n
 int blink_ref_correlate(const int8_t *volt, int S, int F, int A, int n_int, int n_favg, int pol_mode,
                         float *vis, float *autos);
 
+/* Incoherent de-dispersion (the FRB search the images feed; Sections 1, 3, 10, Table 1).
+ * delays [n_dm][C] = nearbyint(4148.808 s MHz^2 cm^3/pc x dm x (f^-2 - f_ref^-2) / dt), f in MHz,
+ * f_ref the highest channel frequency; out [n_dm][t_out][N][N] (double) = mean over c of
+ * images[t + delay(c)][c] for images float [T][C][N][N]; every t_out + delay must be <= T. */
+int blink_ref_dispersion_delays(const double *freq_hz, int C, double dt_s, const double *dm, int n_dm,
+                                int32_t *delays);
+int blink_ref_dedisperse(const float *images, int T, int C, int grid_n, const int32_t *delays, int n_dm,
+                         int t_out, double *out);
+
 /* Number of threads blink_ref_image_batch would use for n_threads <= 0. */
 int blink_ref_max_threads(void);
 

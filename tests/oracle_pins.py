@@ -592,10 +592,55 @@ def pin_correlate_averaging_groups(O):
         assert not res["vis"][:, :, 1, b].any()
 
 
+# ----------------------------------------------------------------------------- de-dispersion
+
+def pin_dispersion_delays_worked(O):
+    """Delays against the hand-worked values of tests/golden/dispersion_delays.txt."""
+    for ln in open(os.path.join(GOLDEN, "dispersion_delays.txt")):
+        ln = ln.strip()
+        if not ln or ln.startswith("#"):
+            continue
+        f, fr, dm, dt, want = ln.split()
+        got = O.dispersion_delays(np.array([float(f), float(fr)]), float(dt), [float(dm)])
+        assert got[0, 0] == int(want) and got[0, 1] == 0, (ln, got)
+
+
+def pin_dedisperse_dm0_is_channel_mean(O):
+    """At DM 0 every delay is 0 and de-dispersion is the channel average (numpy's mean)."""
+    g = np.random.default_rng(80)
+    imgs = g.normal(size=(5, 6, 4, 4)).astype(np.float32)
+    d = O.dispersion_delays(150e6 + 1e6 * np.arange(6), 0.05, [0.0])
+    assert not d.any()
+    out = O.dedisperse(imgs, d, 5)
+    assert np.abs(out[0] - imgs.astype(np.float64).mean(axis=1)).max() <= 1e-12
+
+
+def pin_dedisperse_recovers_pulse(O):
+    """A pulse of amplitude 3 at pixel (1, 2), dispersed with DM 4 over 6 channels (140 .. 165 MHz,
+    50 ms steps: up to 5 steps of delay), is recovered in full at its arrival step at DM 4 and
+    nowhere else; at the other trial DMs it is smeared."""
+    C, T, N = 6, 40, 4
+    freq = 140e6 + 5e6 * np.arange(C)
+    dms = [0.0, 2.0, 4.0, 6.0]
+    d = O.dispersion_delays(freq, 0.05, dms)
+    assert len({tuple(r) for r in d}) == 4 and d[2].max() >= 3
+    t0 = 3
+    imgs = np.zeros((T, C, N, N), dtype=np.float32)
+    for c in range(C):
+        imgs[t0 + d[2, c], c, 1, 2] = 3.0
+    t_out = T - int(d.max())
+    out = O.dedisperse(imgs, d, t_out)
+    assert out[2, t0, 1, 2] == 3.0
+    assert np.count_nonzero(out[2]) == 1
+    for k in (0, 1, 3):
+        assert out[k].max() < 3.0
+
+
 EXTRA_PINS = [pin_image_average, pin_es_kernel_values, pin_es_transform, pin_conv_width1_is_nearest_cell,
               pin_conv_hermitian, pin_conv_matches_direct_transform, pin_conv_batch_consistency,
               pin_corrections_identity, pin_corrections_undo_gains, pin_corrections_phase_centre,
-              pin_correlate_matrix_product, pin_correlate_quarter_turns, pin_correlate_averaging_groups]
+              pin_correlate_matrix_product, pin_correlate_quarter_turns, pin_correlate_averaging_groups,
+              pin_dispersion_delays_worked, pin_dedisperse_dm0_is_channel_mean, pin_dedisperse_recovers_pulse]
 
 
 PINS = [pin_cell_worked, pin_tiny_grid, pin_ifft1d_bruteforce, pin_ifft2d_bruteforce,

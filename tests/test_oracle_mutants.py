@@ -61,6 +61,13 @@ MUTANTS = {
     "cmac_channel_groups_wrong": ("for (int f = c * n_favg; f < (c + 1) * n_favg; ++f)",
                                   "for (int f = c; f < c + n_favg; ++f)"),
     "cmac_baseline_order": ("const long b = (long)i * (i - 1) / 2 + j;", "const long b = (long)j * (j - 1) / 2 + i;"),
+    # de-dispersion
+    "dd_delay_sign": ("(1.0 / (f_mhz * f_mhz) - 1.0 / (ref_mhz * ref_mhz))",
+                      "(1.0 / (ref_mhz * ref_mhz) - 1.0 / (f_mhz * f_mhz))"),
+    "dd_delay_not_in_samples": ("nearbyint(delay_s / dt_s)", "nearbyint(delay_s)"),
+    "dd_reference_lowest": ("if (freq_hz[c] > f_ref) f_ref = freq_hz[c];", "if (freq_hz[c] < f_ref) f_ref = freq_hz[c];"),
+    "dd_no_shift": ("const int ts = t + delays[(size_t)k * C + c];", "const int ts = t;"),
+    "dd_sum_not_mean": ("for (size_t i = 0; i < NN; ++i) o[i] /= (double)C;", "(void)C;"),
 }
 
 
