@@ -192,6 +192,34 @@ def bench_correlator(ctx, torch, steps, warmup):
     return out
 
 
+def bench_dedispersion(ctx, torch, blink, steps, warmup):
+    """Incoherent de-dispersion of a Stokes I cube shaped like the paper's FRB case (Table 1: 512^2
+    images, 768 x 40 kHz channels): 40 steps of 50 ms, 16 trial DMs 0 .. 10 pc cm^-3."""
+    import numpy as np
+    T, C, N, dt = 40, 768, 512, 0.05
+    freq = 139.0e6 + 40.0e3 * (np.arange(C) + 0.5)
+    dms = np.linspace(0.0, 10.0, 16)
+    delays = blink.dispersion_delays(freq, dt, dms)
+    t_out = T - int(delays.max())
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(40)
+    cube = torch.randn((T, C, N, N), generator=gen, device="cuda:0", dtype=torch.float32)
+    out = torch.empty((len(dms), t_out, N, N), dtype=torch.float32, device="cuda:0")
+    ws = torch.empty(blink.dedisperse_workspace_size(C, len(dms)), dtype=torch.uint8, device="cuda:0")
+    ms = timed(torch, lambda i: ctx.blink_dedisperse(cube, delays, t_out, out=out, workspace=ws), steps, warmup) / steps
+    # bytes of the direct method: every output image reads its C delayed channel images once
+    nbytes = len(dms) * t_out * (C + 1) * N * N * 4
+    res = {"workload": f"de-dispersion: {T} x 50 ms steps, {C} x 40 kHz channels from 139 MHz, {N}^2 Stokes I "
+                       f"images, {len(dms)} trial DMs 0 .. 10 pc cm^-3 (max delay {int(delays.max())} steps)",
+           "ms": round(ms, 3), "dedispersed_images_per_s": round(len(dms) * t_out / (ms / 1e3), 1),
+           "bytes_direct_method": nbytes, "achieved_GB_s": round(nbytes / (ms / 1e3) / 1e9, 1),
+           "frac_hbm": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"de-dispersion: {ms:.2f} ms for {len(dms)} x {t_out} images, {nbytes / (ms / 1e3) / 1e9:.0f} GB/s")
+    del cube, out, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_precision_workload(ctx, torch, blink, synth, steps, warmup):
     """The 4096^2 precision workload (10 time steps x 256 channels x 1 pol) in every FFT form;
     a step images one time step (256 images) into a one-step ring buffer."""
@@ -442,6 +470,7 @@ def main():
         log(f"Stokes I + band average of {C * P} images: {ms:.3f} ms "
             f"({moved / (ms / 1e3) / 1e9:.0f} GB/s)")
         forms["correlator"] = bench_correlator(ctx, torch, 5, 2)
+        forms["dedispersion"] = bench_dedispersion(ctx, torch, blink, 3, 1)
         forms["precision-4096"] = bench_precision_workload(ctx, torch, blink, synth, 3, 1)
         forms["uneven"] = bench_uneven(ctx, torch, blink, synth, 3)
 

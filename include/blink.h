@@ -235,6 +235,32 @@ enum { BLINK_AVG_TIME = 1, BLINK_AVG_CHANNEL = 2, BLINK_AVG_POL = 4 };
 blink_status blink_image_average(blink_ctx ctx, const float *images, int T, int C, int P, int grid_n,
                                  int axes, float *out, void *hip_stream);
 
+/* ---------------------------------------------------------------- de-dispersion
+ * The first step of the FRB search the images feed (Sections 1, 3 and 10; Table 1: DM up to 600
+ * pc cm^-3, tens of seconds of dispersive delay over the band): incoherent de-dispersion of image
+ * cubes. A pulse of dispersion measure DM reaches channel frequency f later than the highest
+ * channel f_ref by 4148.808 s MHz^2 cm^3/pc x DM x (f^-2 - f_ref^-2) (frequencies in MHz; the
+ * cold-plasma dispersion constant), rounded to whole time steps of dt seconds.
+ *
+ * blink_dispersion_delays (host only): delays [n_dm][C] int32 of the trial DMs dm[n_dm] >= 0 for
+ * channel frequencies freq_hz[C] (Hz) and step dt_s > 0. */
+blink_status blink_dispersion_delays(const double *freq_hz, int C, double dt_s, const double *dm, int n_dm,
+                                     int32_t *delays);
+
+/* Workspace bytes of blink_dedisperse for C channels and n_dm trials (the delay table). */
+blink_status blink_dedisperse_workspace_size(int C, int n_dm, size_t *bytes);
+
+/* out[k][t] = mean over channels c of images[t + delays[k][c]][c], t < t_out, for device images
+ * float [T][C][N][N] (e.g. a Stokes I cube from blink_image_average) and device out float
+ * [n_dm][t_out][N][N]. delays is a HOST array [n_dm][C] (blink_dispersion_delays); every delay
+ * must satisfy 0 <= d <= T - t_out, else ERR_ARG before any device work. The table is copied
+ * into the workspace (hipMemcpyAsync from the host array; the call returns once it is staged).
+ * Sums are FP64 in channel order, divided by C and rounded once. grid_n a power of two 8 .. 4096;
+ * n_dm, t_out <= 65535. */
+blink_status blink_dedisperse(blink_ctx ctx, const float *images, int T, int C, int grid_n,
+                              const int32_t *delays, int n_dm, int t_out, float *out, void *workspace,
+                              size_t workspace_bytes, void *hip_stream);
+
 /* ---------------------------------------------------------------- uneven batches
  * Section 6.2.4 grids many fine channels and integration intervals in parallel on one GPU and
  * transforms all grids at once. blink_image_batch_desc does this for images that differ in grid
@@ -368,7 +394,8 @@ enum {
     BLINK_KERNEL_AVERAGE = 9,      /* image averages (blink_image_average) */
     BLINK_KERNEL_CORRECT = 10,     /* visibility corrections (blink_image_batch_corrected) */
     BLINK_KERNEL_CORRELATE = 11,   /* correlator (blink_correlate) */
-    BLINK_KERNEL_COUNT = 12
+    BLINK_KERNEL_DEDISPERSE = 12,  /* de-dispersion (blink_dedisperse) */
+    BLINK_KERNEL_COUNT = 13
 };
 
 /* Enable (nonzero) or disable timing; either way the recorded launches are discarded. */

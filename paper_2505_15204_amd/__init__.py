@@ -21,7 +21,7 @@ PLANS_PATH = os.path.join(PKG, "plans_gfx950.json")     # autotuned execution pl
 BLINK_OK, BLINK_ERR_ARG, BLINK_ERR_SIZE, BLINK_ERR_NOMEM, BLINK_ERR_HIP, BLINK_ERR_STATE = range(6)
 WEIGHT_NATURAL, WEIGHT_UNIFORM = 0, 1
 KERNELS = ("bin", "grid", "grid_colfft", "dense_colfft", "weights", "row_fft", "desc_prep", "persistent",
-           "conv_correction", "average", "correct", "correlate")
+           "conv_correction", "average", "correct", "correlate", "dedisperse")
 AVG_TIME, AVG_CHANNEL, AVG_POL = 1, 2, 4   # BLINK_KERNEL_* ids
 DESC_BAD = 1
 
@@ -97,6 +97,12 @@ def lib() -> ctypes.CDLL:
                                               ctypes.POINTER(Corrections), P, P, P, P, sz, P]
     L.blink_correlate.restype = i32
     L.blink_correlate.argtypes = [P, P, i32, i32, i32, i32, i32, i32, P, P, P]
+    L.blink_dispersion_delays.restype = i32
+    L.blink_dispersion_delays.argtypes = [P, i32, f64, P, i32, P]
+    L.blink_dedisperse_workspace_size.restype = i32
+    L.blink_dedisperse_workspace_size.argtypes = [i32, i32, ctypes.POINTER(sz)]
+    L.blink_dedisperse.restype = i32
+    L.blink_dedisperse.argtypes = [P, P, i32, i32, i32, P, i32, i32, P, P, sz, P]
     L.blink_plan_options.restype = i32
     L.blink_plan_options.argtypes = [i32, i32, P, P, P, P]
     L.blink_get_plan.restype = i32
@@ -176,6 +182,25 @@ def image_batch_corrected_workspace_size(T: int, C: int, P: int, B: int, grid_n:
     _check(lib().blink_image_batch_corrected_workspace_size(T, C, P, B, grid_n, weighting, precision,
                                                             ctypes.byref(n)),
            what="blink_image_batch_corrected_workspace_size")
+    return n.value
+
+
+def dispersion_delays(freq_hz, dt_s: float, dms):
+    """Integer delays [n_dm][C] (int32 NumPy, steps of dt_s) of the trial DMs at channel frequencies
+    freq_hz (host arrays; blink_dispersion_delays)."""
+    import numpy as np
+    fr = np.ascontiguousarray(freq_hz, dtype=np.float64)
+    dm = np.ascontiguousarray(np.atleast_1d(dms), dtype=np.float64)
+    out = np.empty((dm.shape[0], fr.shape[0]), dtype=np.int32)
+    _check(lib().blink_dispersion_delays(fr.ctypes.data_as(ctypes.c_void_p), fr.shape[0], float(dt_s),
+                                         dm.ctypes.data_as(ctypes.c_void_p), dm.shape[0],
+                                         out.ctypes.data_as(ctypes.c_void_p)), what="blink_dispersion_delays")
+    return out
+
+
+def dedisperse_workspace_size(C: int, n_dm: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().blink_dedisperse_workspace_size(C, n_dm, ctypes.byref(n)), what="blink_dedisperse_workspace_size")
     return n.value
 
 
@@ -549,6 +574,28 @@ class Context:
                                    _ptr(autos_out), self._stream(stream))
         _check(st, self.handle, "blink_correlate")
         return {"vis": out, "autos": autos_out}
+
+    def blink_dedisperse(self, images, delays, t_out: int, out=None, workspace=None, stream=None):
+        """De-disperse images float32 device [T][C][N][N] with the host delay table delays int32
+        [n_dm][C]; returns out float32 [n_dm][t_out][N][N]."""
+        import numpy as np
+        torch = self._torch()
+        self._require("images", images, torch.float32)
+        if images.dim() != 4 or images.shape[2] != images.shape[3]:
+            raise ValueError(f"images must be [T][C][N][N], got {tuple(images.shape)}")
+        T, C, N = int(images.shape[0]), int(images.shape[1]), int(images.shape[2])
+        dl = np.ascontiguousarray(delays, dtype=np.int32)
+        if dl.ndim != 2 or dl.shape[1] != C:
+            raise ValueError(f"delays must be [n_dm][{C}], got {dl.shape}")
+        n_dm = dl.shape[0]
+        if out is None:
+            out = torch.empty((n_dm, int(t_out), N, N), dtype=torch.float32, device=images.device)
+        self._require("out", out, torch.float32, (n_dm, int(t_out), N, N))
+        ws = self._workspace(dedisperse_workspace_size(C, n_dm), workspace)
+        st = lib().blink_dedisperse(self.handle, _ptr(images), T, C, N, dl.ctypes.data_as(ctypes.c_void_p), n_dm,
+                                    int(t_out), _ptr(out), _ptr(ws), ws.numel(), self._stream(stream))
+        _check(st, self.handle, "blink_dedisperse")
+        return out
 
     def blink_image_average(self, images, axes: int, out=None, stream=None):
         """Average float32 images [T][C][P][N][N] over the axes in `axes` (AVG_TIME | AVG_CHANNEL |

@@ -770,6 +770,65 @@ blink_status blink_correlate(blink_ctx ctx, const int8_t* volt, int S, int F, in
   return BLINK_OK;
 }
 
+blink_status blink_dispersion_delays(const double* freq_hz, int C, double dt_s, const double* dm, int n_dm,
+                                     int32_t* delays) {
+  if (C < 1 || n_dm < 0 || !(dt_s > 0.0) || !std::isfinite(dt_s) || !freq_hz || (n_dm > 0 && (!dm || !delays)))
+    return BLINK_ERR_ARG;
+  double f_ref = 0.0;
+  for (int c = 0; c < C; ++c) {
+    if (!(freq_hz[c] > 0.0) || !std::isfinite(freq_hz[c])) return BLINK_ERR_ARG;
+    f_ref = freq_hz[c] > f_ref ? freq_hz[c] : f_ref;
+  }
+  const double ref_mhz = f_ref / 1.0e6;
+  constexpr double kDispersion = 4148.808;   // s MHz^2 cm^3 / pc
+  for (int k = 0; k < n_dm; ++k) {
+    if (!(dm[k] >= 0.0) || !std::isfinite(dm[k])) return BLINK_ERR_ARG;
+    for (int c = 0; c < C; ++c) {
+      const double f_mhz = freq_hz[c] / 1.0e6;
+      const double steps = kDispersion * dm[k] * (1.0 / (f_mhz * f_mhz) - 1.0 / (ref_mhz * ref_mhz)) / dt_s;
+      if (!(steps < 2.0e9)) return BLINK_ERR_ARG;
+      delays[(size_t)k * C + c] = (int32_t)std::nearbyint(steps);
+    }
+  }
+  return BLINK_OK;
+}
+
+blink_status blink_dedisperse_workspace_size(int C, int n_dm, size_t* bytes) {
+  if (!bytes || C < 1 || n_dm < 0) return BLINK_ERR_ARG;
+  *bytes = align_up((size_t)C * (size_t)n_dm * sizeof(int32_t));
+  return BLINK_OK;
+}
+
+blink_status blink_dedisperse(blink_ctx ctx, const float* images, int T, int C, int grid_n, const int32_t* delays,
+                              int n_dm, int t_out, float* out, void* workspace, size_t workspace_bytes,
+                              void* hip_stream) {
+  if (!ctx) return BLINK_ERR_ARG;
+  const int logn = log2_exact(grid_n);
+  if (logn < 0) return fail(ctx, BLINK_ERR_SIZE, "grid_n=%d unsupported", grid_n);
+  if (T < 0 || C < 1 || n_dm < 0 || t_out < 0 || t_out > T || n_dm > 65535 || t_out > 65535)
+    return fail(ctx, BLINK_ERR_ARG, "bad de-dispersion sizes (T=%d C=%d n_dm=%d t_out=%d)", T, C, n_dm, t_out);
+  if (n_dm == 0 || t_out == 0) return BLINK_OK;
+  if (!images || !delays || !out || !workspace) return fail(ctx, BLINK_ERR_ARG, "null pointer");
+  const size_t table = (size_t)C * (size_t)n_dm * sizeof(int32_t);
+  if (workspace_bytes < table)
+    return fail(ctx, BLINK_ERR_SIZE, "workspace of %zu bytes is smaller than the delay table (%zu)", workspace_bytes,
+                table);
+  for (size_t i = 0; i < (size_t)C * n_dm; ++i)
+    if (delays[i] < 0 || (long long)delays[i] > (long long)T - t_out)
+      return fail(ctx, BLINK_ERR_ARG, "delay %d of entry %zu outside 0 .. T - t_out = %d", delays[i], i, T - t_out);
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e = hipMemcpyAsync(workspace, delays, table, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "delay table copy");
+  {
+    KernelTimer kt(ctx, BLINK_KERNEL_DEDISPERSE, s);
+    e = blink::launch_dedisperse(images, C, logn, (const int*)workspace, n_dm, t_out, out, s);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "de-dispersion kernel");
+  return BLINK_OK;
+}
+
 blink_status blink_image_batch_conv_workspace_size(int T, int C, int P, int B, int grid_n, int kernel_width,
                                                    int precision, size_t* bytes) {
   if (!bytes || T < 0 || C < 0 || P < 1 || B < 0) return BLINK_ERR_ARG;

@@ -210,6 +210,38 @@ hipError_t launch_correct_vis(const CorrArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- de-dispersion
+// out[k][t] = mean over c of in[t + delay[k][c]][c], four pixels per thread, FP64 sums in channel
+// order (then one division by C and one rounding to float).
+__global__ __launch_bounds__(256) void k_dedisperse(const float4* __restrict__ in, int C, long nn4,
+                                                    const int* __restrict__ delays, int t_out,
+                                                    float4* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn4) return;
+  const int t = blockIdx.y, k = blockIdx.z;
+  const int* dk = delays + (size_t)k * C;
+  double sx = 0.0, sy = 0.0, sz = 0.0, sw = 0.0;
+  for (int c = 0; c < C; ++c) {
+    const float4 v = in[((size_t)(t + dk[c]) * C + c) * nn4 + i];
+    sx += v.x;
+    sy += v.y;
+    sz += v.z;
+    sw += v.w;
+  }
+  const double cd = (double)C;
+  out[((size_t)k * t_out + t) * nn4 + i] = make_float4((float)(sx / cd), (float)(sy / cd), (float)(sz / cd),
+                                                       (float)(sw / cd));
+}
+
+hipError_t launch_dedisperse(const float* in, int C, int logn, const int* delays, int n_dm, int t_out, float* out,
+                             hipStream_t s) {
+  const long nn4 = (1L << (2 * logn)) / 4;
+  if (n_dm <= 0 || t_out <= 0) return hipSuccess;
+  dim3 grid((unsigned)((nn4 + 255) / 256), (unsigned)t_out, (unsigned)n_dm);
+  k_dedisperse<<<grid, 256, 0, s>>>((const float4*)in, C, nn4, delays, t_out, (float4*)out);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_image_average(const float4* __restrict__ in, int T, int C, int P, long nn4,
                                                        int axes, float4* __restrict__ out) {
   const int To = (axes & 1) ? 1 : T, Co = (axes & 2) ? 1 : C, Po = (axes & 4) ? 1 : P;

@@ -141,6 +141,12 @@ struct CorrelateArgs {
 size_t correlate_lds_bytes(int A);
 hipError_t launch_correlate(const CorrelateArgs& a, hipStream_t s);
 
+// De-dispersion: out [n_dm][t_out][N][N] = mean over c of in[t + delays[k][c]][c] for images
+// in [T][C][N][N]; delays (device, [n_dm][C]) are checked by the caller (0 <= d <= T - t_out),
+// t_out and n_dm <= 65535.
+hipError_t launch_dedisperse(const float* in, int C, int logn, const int* delays, int n_dm, int t_out, float* out,
+                             hipStream_t s);
+
 // Averages of images [T][C][P][N][N] over the axes in `axes` (1 time, 2 channel, 4 pol).
 hipError_t launch_image_average(const float* in, int T, int C, int P, int logn, int axes, float* out, hipStream_t s);
 

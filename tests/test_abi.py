@@ -149,3 +149,21 @@ def test_corrections_argument_checks(L):
     assert call(blink.Corrections(dummy, 1, 0.0, 0.0), B=0) == blink.BLINK_ERR_ARG
     s = blink.image_batch_corrected_workspace_size(1, 2, 2, 8128, 1024)
     assert s >= blink.image_batch_workspace_size(1, 2, 2, 8128, 1024) + 2 * 2 * 8128 * 8
+
+
+def test_dispersion_delays_on_the_host(L):
+    """blink_dispersion_delays runs on the host and matches the oracle's table; bad arguments fail."""
+    import numpy as np
+
+    import oracle
+    f = 139.0e6 + 40.0e3 * (np.arange(768) + 0.5)
+    dms = [0.0, 2.97, 100.0, 600.0]
+    assert np.array_equal(blink.dispersion_delays(f, 0.02, dms), oracle.dispersion_delays(f, 0.02, dms))
+    for bad in ((f, 0.0, dms), (f, 0.02, [-1.0]), (-f, 0.02, dms)):
+        with pytest.raises(blink.BlinkError):
+            blink.dispersion_delays(*bad)
+    assert blink.dedisperse_workspace_size(768, 4) >= 768 * 4 * 4
+    dummy = ctypes.c_void_p(0x1000)
+    d = np.zeros((1, 4), dtype=np.int32)
+    assert L.blink_dedisperse(None, dummy, 4, 4, 64, d.ctypes.data_as(ctypes.c_void_p), 1, 2, dummy, dummy, 1 << 20,
+                              None) == blink.BLINK_ERR_ARG
