@@ -218,14 +218,34 @@ __device__ __forceinline__ void stage_load_lds(float2 (&v)[R], const float2* buf
   }
 }
 
+// Synchronisation between two LDS passes of the transforms. When the T threads of a transform
+// lie within one wavefront (T <= 64 with transforms at multiples of T), only that wavefront reads
+// what it wrote: the LDS unit performs one wavefront's instructions in issue order, so fences at
+// wavefront scope (which keep the compiler from moving memory operations across) replace the
+// workgroup barrier, and the wavefronts of a workgroup are free to run their LDS passes and
+// butterflies out of step. Larger transforms span wavefronts and take the workgroup barrier.
+template <int T>
+__device__ __forceinline__ void stage_sync() {
+  if constexpr (T <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Full inverse FFT of one transform per group of T threads.
 // On entry v[m] holds element tid + m*T (the first stage's input order); `buf` is this
 // transform's padded LDS buffer and `tw` the twiddle table of N in the layout above (LDS or
 // global). Every thread of the block must call this (it contains block barriers); threads with
-// active == false take part in the barriers only and touch no memory. On return the caller's
-// `sink(e, value)` has been called for every output element e this thread owns (natural order,
-// each element exactly once across the T threads); when the last stage writes back to LDS
-// instead (ToLds = true) the result is in buf at pad(e) and the block is synchronised.
+// active == false take part in the barriers only and touch no memory. The passes between stages
+// are separated by stage_sync, so the caller's last LDS writes before the call must already be
+// visible to the transform's threads, and the caller separates a later reuse of buf by other
+// threads with a barrier of its own. On return the caller's `sink(e, value)` has been called for
+// every output element e this thread owns (natural order, each element exactly once across the T
+// threads); when the last stage writes back to LDS instead (ToLds = true) the result is in buf at
+// pad(e) and the block is synchronised.
 template <int LOGN, bool ToLds, class Sink>
 __device__ __forceinline__ void fft_inverse(float2 (&v)[FftPlan<LOGN>::R], float2* buf,
                                             const float2* __restrict__ tw, int tid, Sink sink,
@@ -235,7 +255,7 @@ __device__ __forceinline__ void fft_inverse(float2 (&v)[FftPlan<LOGN>::R], float
   if (active) stage_compute<N, R, T, 1, P::R0>(v, tid, tw);
   if constexpr (P::NST == 1) {
     if constexpr (ToLds) {
-      __syncthreads();
+      stage_sync<T>();
       if (active) stage_store_lds<N, R, T, 1, P::R0>(v, buf, tid);
       __syncthreads();
     } else {
@@ -245,9 +265,9 @@ __device__ __forceinline__ void fft_inverse(float2 (&v)[FftPlan<LOGN>::R], float
       }
     }
   } else {
-    __syncthreads();                       // the caller's loads of buf are complete
+    stage_sync<T>();                       // the caller's loads of buf are complete
     if (active) stage_store_lds<N, R, T, 1, P::R0>(v, buf, tid);
-    __syncthreads();
+    stage_sync<T>();
     if (active) {
       stage_load_lds<N, R, T, P::R1>(v, buf, tid);
       stage_compute<N, R, T, P::R0, P::R1>(v, tid, tw);
@@ -255,7 +275,7 @@ __device__ __forceinline__ void fft_inverse(float2 (&v)[FftPlan<LOGN>::R], float
     constexpr int Q1 = R / P::R1;
     if constexpr (P::NST == 2) {
       if constexpr (ToLds) {
-        __syncthreads();
+        stage_sync<T>();
         if (active) stage_store_lds<N, R, T, P::R0, P::R1>(v, buf, tid);
         __syncthreads();
       } else {
@@ -267,9 +287,9 @@ __device__ __forceinline__ void fft_inverse(float2 (&v)[FftPlan<LOGN>::R], float
         }
       }
     } else {
-      __syncthreads();
+      stage_sync<T>();
       if (active) stage_store_lds<N, R, T, P::R0, P::R1>(v, buf, tid);
-      __syncthreads();
+      stage_sync<T>();
       constexpr int NS2 = P::R0 * P::R1;
       if (active) {
         stage_load_lds<N, R, T, P::R2>(v, buf, tid);
@@ -277,7 +297,7 @@ __device__ __forceinline__ void fft_inverse(float2 (&v)[FftPlan<LOGN>::R], float
       }
       constexpr int Q2 = R / P::R2;
       if constexpr (ToLds) {
-        __syncthreads();
+        stage_sync<T>();
         if (active) stage_store_lds<N, R, T, NS2, P::R2>(v, buf, tid);
         __syncthreads();
       } else {
