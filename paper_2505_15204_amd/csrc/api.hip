@@ -1363,7 +1363,8 @@ blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32* vis, co
   int col[4], row[4];
   const int nc = blink::col_strip_options(logn, weighting != 0, col);
   const int nr = blink::row_block_options(logn, row);
-  const int groups[] = {16, 32, 64, 128, 256};
+  const int groups[] = {16, 24, 32, 48, 64, 96, 128, 256};
+  constexpr int n_groups = (int)(sizeof(groups) / sizeof(groups[0]));
   double best = 1e300;
   auto best_plan = saved;
   blink_status result = BLINK_OK;
@@ -1389,7 +1390,7 @@ blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32* vis, co
   };
   // every (group, strip width, row block) with one strip per column workgroup, then 2, 4, .. 16
   // strips per workgroup on the best of those
-  for (int gi = 0; gi < 5 && result == BLINK_OK; ++gi) {
+  for (int gi = 0; gi < n_groups && result == BLINK_OK; ++gi) {
     for (int ci = 0; ci < nc && result == BLINK_OK; ++ci) {
       for (int ri = 0; ri < nr && result == BLINK_OK; ++ri) {
         p.col_strip = col[ci];

@@ -206,19 +206,22 @@ __device__ __forceinline__ void block_add_to_global(int val, int* s_tmp, int* ds
 // spectrum: Hi[y][strip*S + c]. With REAL0, column 0 of strip 0 keeps only its real part (the
 // transform of the Hermitian part of column 0; the imaginary slot is the Nyquist column's, empty).
 // Thread t handles column t % S of rows t / S + j * NT / S, so when NT / S is a multiple of 16
-// every address is one base plus compile-time steps.
-template <int LOGN, int S, int NT, bool REAL0 = true>
-__device__ __forceinline__ void store_strip(const float2* sbuf, int strip, float2* __restrict__ Hi) {
+// every address is one base plus compile-time steps. With ZERO every cell read is cleared behind
+// the read (the cells at pad(y) of the S columns: all that gridding and the transforms use), so
+// the strip buffer is zero for the next strip once the caller's following barrier has passed.
+template <int LOGN, int S, int NT, bool REAL0 = true, bool ZERO = false>
+__device__ __forceinline__ void store_strip(float2* sbuf, int strip, float2* __restrict__ Hi) {
   constexpr int N = 1 << LOGN, NP = padded_len(N), HALF = N / 2;
   if constexpr (NT % S == 0 && (NT / S) % 16 == 0 && (S * N) % NT == 0) {
     constexpr int RPI = NT / S, ITER = (S * N) / NT;
     const int c = (int)threadIdx.x % S, y0 = (int)threadIdx.x / S;
-    const float2* src = sbuf + c * NP + pad_index(y0);
+    float2* src = sbuf + c * NP + pad_index(y0);
     float2* dst = Hi + (size_t)y0 * HALF + strip * S + c;
     const bool real_only = REAL0 && strip == 0 && c == 0;
 #pragma unroll
     for (int j = 0; j < ITER; ++j) {
       float2 val = src[pad_offset(j * RPI)];
+      if constexpr (ZERO) src[pad_offset(j * RPI)] = make_float2(0.f, 0.f);
       if (real_only) val.y = 0.f;
       dst[(size_t)j * RPI * HALF] = val;
     }
@@ -226,6 +229,7 @@ __device__ __forceinline__ void store_strip(const float2* sbuf, int strip, float
     for (int i = threadIdx.x; i < S * N; i += NT) {
       const int y = i / S, c = i % S;
       float2 val = sbuf[c * NP + pad_index(y)];
+      if constexpr (ZERO) sbuf[c * NP + pad_index(y)] = make_float2(0.f, 0.f);
       if (REAL0 && strip == 0 && c == 0) val.y = 0.f;
       Hi[(size_t)y * HALF + strip * S + c] = val;
     }
@@ -237,7 +241,7 @@ __device__ __forceinline__ void store_strip(const float2* sbuf, int strip, float
 // block is synchronised before the store. REAL0 keeps only the real part of column 0 of strip 0
 // (nearest-cell gridding leaves the Nyquist column empty); without it column 0 carries
 // (column 0) + i (column N/2) as packed by the gridding.
-template <int LOGN, int S, int PREC, int NT, bool REAL0>
+template <int LOGN, int S, int PREC, int NT, bool REAL0, bool ZERO = false>
 __device__ __forceinline__ void strip_fft_store(float2* sbuf, int strip, float2* __restrict__ Hi,
                                                 const float2* __restrict__ tw, SplitCtx sp) {
   using P = FftPlan<LOGN>;
@@ -254,7 +258,7 @@ __device__ __forceinline__ void strip_fft_store(float2* sbuf, int strip, float2*
     if (active) stage_load_lds<P::N, P::R, T, P::R0>(v, cb, lt);
     fft_inverse<LOGN, true>(v, cb, tw, lt, [](int, float2) {}, active);
   }
-  store_strip<LOGN, S, NT, REAL0>(sbuf, strip, Hi);
+  store_strip<LOGN, S, NT, REAL0, ZERO>(sbuf, strip, Hi);
 }
 
 // ---------------------------------------------------------------- fused grid + column FFT task
@@ -352,8 +356,15 @@ __device__ __forceinline__ void grid_colfft_strips(const float2* __restrict__ V,
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, NP = P::NP;
   constexpr bool SPLIT = PREC != kPrecFp32 && LOGN >= 4;
+  // FP32 with natural weighting clears the strip buffer once here and then behind the reads of
+  // each strip's store (store_strip with ZERO), which saves a pass over LDS and a barrier per strip.
+  constexpr bool ZERO_IN_STORE = !SPLIT && !UNIFORM;
   StripPrefetch<PF> cur, nxt;
-  __syncthreads();   // s_off is visible
+  if constexpr (ZERO_IN_STORE) {
+#pragma unroll 4
+    for (int i = threadIdx.x; i < S * NP; i += NT) sbuf[i] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();   // s_off is visible (and the strip buffer zero)
   prefetch_records<PF, NT>(plc, s_off, strip0, pf_strips, cur);
   prefetch_vis<PF, NT>(V, s_off, strip0, pf_strips, cur);
   prefetch_records<PF, NT>(plc, s_off, strip0 + dstrip, pf_strips, nxt);
@@ -362,15 +373,17 @@ __device__ __forceinline__ void grid_colfft_strips(const float2* __restrict__ V,
   // inside it count past the previous strip's stores instead of draining them.
   __builtin_amdgcn_s_waitcnt(0x0F70);
   for (int strip = strip0; strip < nstrips; strip += dstrip) {
+    if constexpr (!ZERO_IN_STORE) {
 #pragma unroll 4
-    for (int i = threadIdx.x; i < S * NP; i += NT) sbuf[i] = make_float2(0.f, 0.f);
-    if constexpr (UNIFORM)
-      for (int i = threadIdx.x; i < S * N; i += NT) scnt[i] = 0u;
-    if (threadIdx.x == 0) {
-      *s_tmp = 0;
-      if constexpr (SPLIT) *sp.s_max = 0u;
+      for (int i = threadIdx.x; i < S * NP; i += NT) sbuf[i] = make_float2(0.f, 0.f);
+      if constexpr (UNIFORM)
+        for (int i = threadIdx.x; i < S * N; i += NT) scnt[i] = 0u;
+      if (threadIdx.x == 0) {
+        *s_tmp = 0;
+        if constexpr (SPLIT) *sp.s_max = 0u;
+      }
+      __syncthreads();
     }
-    __syncthreads();
 #pragma unroll
     for (int j = 0; j < PF; ++j)
       if (prefetch_slot_used<PF, NT>(s_off, strip, nstrips, j))
@@ -389,8 +402,8 @@ __device__ __forceinline__ void grid_colfft_strips(const float2* __restrict__ V,
     for (int j = 0; j < PF; ++j) cur.r[j] = nxt.r[j];
     prefetch_vis<PF, NT>(V, s_off, strip + dstrip, pf_strips, cur);
     prefetch_records<PF, NT>(plc, s_off, strip + 2 * dstrip, pf_strips, nxt);
-    strip_fft_store<LOGN, S, PREC, NT, true>(sbuf, strip, Hi, tw, sp);
-    __syncthreads();   // the store's reads of the strip buffer are done before it is cleared again
+    strip_fft_store<LOGN, S, PREC, NT, true, ZERO_IN_STORE>(sbuf, strip, Hi, tw, sp);
+    __syncthreads();   // the store's reads (and clears) of the strip buffer are done before it is reused
   }
 }
 
@@ -403,6 +416,9 @@ __device__ __forceinline__ void grid_colfft_strips(const float2* __restrict__ V,
 // split PREC the workgroup is whole waves and `sp` is that form's context (as for the column
 // task, consecutive calls are separated by a workgroup barrier). A non-null `corr` (N values)
 // multiplies pixel (y, x) by corr[y] corr[x] (the convolutional path's grid correction).
+// Pixels are written with non-temporal stores: nothing in the path reads them again, and keeping
+// them out of the caches leaves the last-level cache to the half spectra that the launches of
+// the image group read and write.
 __device__ __forceinline__ float2 hermitian_pair(const float2* __restrict__ h1, const float2* __restrict__ h2, int e,
                                                  int N) {
   const int HALF = N / 2;
@@ -433,14 +449,14 @@ __device__ __forceinline__ void row_task(const float2* __restrict__ H, int rowbl
         const int y1 = 2 * (rowblk * TPB + c);
         float* o1 = ob + (size_t)(2 * c) * N;
         const float cx = corr[e] * scale;
-        o1[e] = z.x * cx * corr[y1];
-        o1[N + e] = z.y * cx * corr[y1 + 1];
+        __builtin_nontemporal_store(z.x * cx * corr[y1], &o1[e]);
+        __builtin_nontemporal_store(z.y * cx * corr[y1 + 1], &o1[N + e]);
       }, sp);
     } else {
       fft_inverse_split<LOGN, PREC, false, false>(sbuf, TPB, tw, load, [&](int c, int e, float2 z) {
         float* o1 = ob + (size_t)(2 * c) * N;
-        o1[e] = z.x * scale;
-        o1[N + e] = z.y * scale;
+        __builtin_nontemporal_store(z.x * scale, &o1[e]);
+        __builtin_nontemporal_store(z.y * scale, &o1[N + e]);
       }, sp);
     }
   } else {
@@ -462,13 +478,13 @@ __device__ __forceinline__ void row_task(const float2* __restrict__ H, int rowbl
       const float s1 = scale * corr[2 * r], s2 = scale * corr[2 * r + 1];
       fft_inverse<LOGN, false>(v, buf, tw, lt, [&](int e, float2 z) {
         const float cx = corr[e];
-        o1[e] = z.x * s1 * cx;
-        o2[e] = z.y * s2 * cx;
+        __builtin_nontemporal_store(z.x * s1 * cx, &o1[e]);
+        __builtin_nontemporal_store(z.y * s2 * cx, &o2[e]);
       }, active);
     } else {
       fft_inverse<LOGN, false>(v, buf, tw, lt, [&](int e, float2 z) {
-        o1[e] = z.x * scale;
-        o2[e] = z.y * scale;
+        __builtin_nontemporal_store(z.x * scale, &o1[e]);
+        __builtin_nontemporal_store(z.y * scale, &o2[e]);
       }, active);
     }
   }
