@@ -11,11 +11,11 @@
 // Q), so the products read their operands directly. Each 32 x 32 output tile therefore needs two
 // int32 accumulators and two v_mfma_i32_32x32x32_i8 per 16 terms, all exact
 // (|R| <= 2 K 128^2 < 2^31 for K <= 65535). Only the tiles on or below the diagonal are
-// formed. A workgroup owns up to 12 tiles (three per wave, along tile rows so that a row's
-// operands are read once per step) of one (interval, channel) and keeps their accumulators in
-// registers over all of K; K is staged through LDS in chunks of 64 terms (each
-// input's 128 bytes contiguous), and the global loads of the next chunk are issued before the
-// current chunk's matrix products.
+// formed. A workgroup of 12 waves owns up to 36 tiles (three per wave, along tile rows so that a
+// row's operands are read once per step) of one (interval, channel), all of them up to 128
+// antennas, so every input is staged once, and keeps their accumulators in registers over all of
+// K; K is staged through LDS in chunks of 64 terms (each input's 128 bytes contiguous), and the
+// global loads of the next chunk are issued before the current chunk's matrix products.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -32,10 +32,11 @@ constexpr int kTile = 32;                 // MFMA tile (inputs)
 constexpr int kKc = 64;                   // terms per LDS chunk
 constexpr int kRow = 2 * kKc + 16;        // LDS row stride in bytes (spreads rows over the banks)
 constexpr int kTilesPerWave = 3;
-constexpr int kWaves = 4;
+constexpr int kWaves = 12;
 constexpr int kTilesPerGroup = kTilesPerWave * kWaves;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kItemsPerSlab = 4 * (kKc / 8);   // (8-input group, 8-term octet) pairs per 32-input slab
+constexpr int kOctets = kKc / 8;               // 8-term octets per chunk
+constexpr int kItemsPerSlab = 4 * kOctets;     // (8-input group, 8-term octet) pairs per 32-input slab
 
 // Tile tau of the lower triangle in row order: (a, b), b <= a, tau = a (a + 1) / 2 + b (at most
 // 16 tile rows).
@@ -69,10 +70,10 @@ struct Staged {
   uint4 w[8];
 };
 
-// ITEMS: staging items per thread, n_slabs * kItemsPerSlab / kThreads rounded up (1 for up to 128
-// antennas, 2 for up to 256).
-template <int ITEMS>
-__global__ __launch_bounds__(kThreads, ITEMS <= 1 ? 2 : 1) void k_correlate(CorrelateArgs a) {
+// A workgroup of 12 waves owns 36 tiles: every tile of one (interval, channel) up to 128 antennas
+// (8 slabs), so each input is staged once per chunk; larger arrays take several workgroups. Each
+// thread stages at most one item (n_slabs * kItemsPerSlab <= 512 items up to 256 antennas).
+__global__ __launch_bounds__(kThreads, 1) void k_correlate(CorrelateArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int IP = a.n_slabs * kTile;               // padded input count
   unsigned char* x = lds;                         // plane P [IP][kRow]: (re, im) pairs, terms contiguous
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(kThreads, ITEMS <= 1 ? 2 : 1) void k_correlate(Corr
   const int t = (int)(pair / a.C), c = (int)(pair % a.C);
   const int ntiles = a.n_slabs * (a.n_slabs + 1) / 2;
   const int tau0 = group * kTilesPerGroup;
-  const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64), lane = (int)threadIdx.x % 64;
   const int n = lane % 32, g = lane / 32;
   int ta[kTilesPerWave], tb[kTilesPerWave], tv[kTilesPerWave];
 #pragma unroll
@@ -122,59 +123,40 @@ __global__ __launch_bounds__(kThreads, ITEMS <= 1 ? 2 : 1) void k_correlate(Corr
   __syncthreads();
   const unsigned need = s_need;
 
-  // item -> (8-input group rg, term octet o): consecutive items are consecutive input groups, so
-  // the lanes of a wave read whole (sample, channel) records (coalesced)
-  const int n_groups = a.n_slabs * 4;
-  auto item_rows = [&](int item, int& slab, int& row0, int& o) {
-    const int rg = item % n_groups;
-    o = item / n_groups;
-    row0 = rg * 8;
-    slab = rg / 4;
-  };
-  // LDS position of term octet o of input row: octets are XOR-swizzled by the row's input group
-  // so that the transposed stores of a wave (many groups, one octet) spread over the banks
-  auto octet_at = [](int row, int o) { return 16 * (o ^ ((row >> 3) & 7)); };
-  // global loads of one chunk's items of this thread (unused slabs, inputs past 2A and terms
-  // past K are not loaded and stage zeros)
-  auto load = [&](int k0, Staged (&st)[ITEMS]) {
+  // item -> (8-input group rg, term octet o): consecutive items are the 8 octets of one input
+  // group, so a global load of a wave reads 128-byte runs (8 groups) of 8 records, and the LDS
+  // rows are stored without a swizzle: with the 144-byte row stride (9 16-byte slots) the 16
+  // lanes of one LDS cycle write rows r and r + 8 of their groups at octets 0..7, slots 9 row + o,
+  // all distinct modulo 16, and the operand reads (16 consecutive rows, one octet) are distinct too
+  const int item = (int)threadIdx.x;
+  const int o = item % kOctets, rg = item / kOctets, row0 = rg * 8, slab = rg / 4;
+  const bool staged = item < n_items && ((need >> slab) & 1u);   // this thread writes rows of P, Q
+  const bool on = staged && row0 < in2;                           // ... and loads voltages for them
+  // global loads of one chunk's item of this thread (unused slabs, inputs past 2A and terms past K
+  // are not loaded and stage zeros). Term k is (sample k / n_favg, fine channel k % n_favg) of the
+  // block: one division per chunk, then the byte offset steps one record per term and over the
+  // other channels' records where a sample ends.
+  auto load = [&](int k0, Staged& st) {
+    const int kb = k0 + 8 * o;
+    int sl = kb / a.n_favg, fl = kb - sl * a.n_favg;
 #pragma unroll
-    for (int m = 0; m < ITEMS; ++m) {
-      const int item = (int)threadIdx.x + m * kThreads;
-      int slab, row0, o;
-      item_rows(item, slab, row0, o);
-      const bool on = item < n_items && ((need >> slab) & 1u) && row0 < in2;
-      // term k = (sample k / n_favg, fine channel k % n_favg) of the block; one division per item
-      const int kb = k0 + 8 * o;
-      int sl = kb / a.n_favg, fl = kb - sl * a.n_favg;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        st[m].w[e] = make_uint4(0, 0, 0, 0);
-        if (on && kb + e < K) {
-          const size_t at = ((size_t)(t * a.n_int + sl) * a.F + (size_t)(c * a.n_favg + fl)) * rec + (size_t)row0 * 2;
-          st[m].w[e] = *reinterpret_cast<const uint4*>(a.volt + at);
-        }
-        if (++fl == a.n_favg) {
-          fl = 0;
-          ++sl;
-        }
+    for (int e = 0; e < 8; ++e) {
+      st.w[e] = make_uint4(0, 0, 0, 0);
+      if (on && kb + e < K) {
+        const size_t at = ((size_t)(t * a.n_int + sl) * a.F + (size_t)(c * a.n_favg + fl)) * rec + (size_t)row0 * 2;
+        st.w[e] = *reinterpret_cast<const uint4*>(a.volt + at);
+      }
+      if (++fl == a.n_favg) {
+        fl = 0;
+        ++sl;
       }
     }
   };
   // transpose: row row0 + r gets the (re, im) pairs of its 8 terms as one 16-byte vector in P and
-  // the (im, ~re) pairs in Q (byte permutes of two loaded words each); the imaginary parts are
-  // summed per row in registers (a thread stages the same rows every chunk)
-  int isums[ITEMS][8];
-#pragma unroll
-  for (int m = 0; m < ITEMS; ++m)
-#pragma unroll
-    for (int r = 0; r < 8; ++r) isums[m][r] = 0;
-  auto store = [&](const Staged (&st)[ITEMS]) {
-#pragma unroll
-    for (int m = 0; m < ITEMS; ++m) {
-      const int item = (int)threadIdx.x + m * kThreads;
-      int slab, row0, o;
-      item_rows(item, slab, row0, o);
-      if (!(item < n_items && ((need >> slab) & 1u))) continue;
+  // the (im, ~re) pairs in Q (byte permutes of two loaded words each); the chunk's imaginary parts
+  // of each row are added to colsum
+  auto store = [&](const Staged& st) {
+    if (staged) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         // v_perm_b32 byte selectors (0-3: bytes of the second source, 4-7: of the first): row r's
@@ -183,28 +165,28 @@ __global__ __launch_bounds__(kThreads, ITEMS <= 1 ? 2 : 1) void k_correlate(Corr
         const unsigned sel_p = j | (j + 1) << 8 | (j + 4) << 16 | (j + 5) << 24;
         const unsigned sel_q = (j + 1) | j << 8 | (j + 5) << 16 | (j + 4) << 24;
         unsigned d[4], e[4];
-        int isum = isums[m][r];
+        int isum = 0;
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
-          const uint4& w0 = st[m].w[2 * h];
-          const uint4& w1 = st[m].w[2 * h + 1];
+          const uint4& w0 = st.w[2 * h];
+          const uint4& w1 = st.w[2 * h + 1];
           const unsigned a0 = r < 2 ? w0.x : r < 4 ? w0.y : r < 6 ? w0.z : w0.w;
           const unsigned a1 = r < 2 ? w1.x : r < 4 ? w1.y : r < 6 ? w1.z : w1.w;
           d[h] = __builtin_amdgcn_perm(a1, a0, sel_p);                 // (re, im) of terms 2h, 2h + 1
           e[h] = __builtin_amdgcn_perm(a1, a0, sel_q) ^ 0xff00ff00u;   // (im, ~re)
           isum = __builtin_amdgcn_sdot4((int)d[h], 0x01000100, isum, false);   // the two im bytes
         }
-        const size_t at = (size_t)(row0 + r) * kRow + octet_at(row0 + r, o);
+        const size_t at = (size_t)(row0 + r) * kRow + 16 * o;
         *reinterpret_cast<uint4*>(x + at) = make_uint4(d[0], d[1], d[2], d[3]);
         *reinterpret_cast<uint4*>(xq + at) = make_uint4(e[0], e[1], e[2], e[3]);
-        isums[m][r] = isum;
+        if (isum) atomicAdd(&colsum[row0 + r], isum);
       }
     }
   };
 
   // one chunk: stage the registers st into LDS, request the next chunk into st (answered during
   // this chunk's products), then the products
-  auto chunk = [&](int k0, Staged (&st)[ITEMS]) {
+  auto chunk = [&](int k0, Staged& st) {
     store(st);
     __syncthreads();
     if (k0 + kKc < K) load(k0 + kKc, st);
@@ -221,32 +203,21 @@ __global__ __launch_bounds__(kThreads, ITEMS <= 1 ? 2 : 1) void k_correlate(Corr
         if (ta[u] != cur) {
           cur = ta[u];
           const int rowa = cur * kTile + n;
-          const size_t oa = (size_t)rowa * kRow + octet_at(rowa, q);
+          const size_t oa = (size_t)rowa * kRow + 16 * q;
           A = *reinterpret_cast<const v4i*>(x + oa);
           As = *reinterpret_cast<const v4i*>(xq + oa);
         }
         const int rowb = tb[u] * kTile + n;
-        const v4i B = *reinterpret_cast<const v4i*>(x + (size_t)rowb * kRow + octet_at(rowb, q));
+        const v4i B = *reinterpret_cast<const v4i*>(x + (size_t)rowb * kRow + 16 * q);
         re[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B, re[u], 0, 0, 0);
         im[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(As, B, im[u], 0, 0, 0);
       }
     }
     __syncthreads();   // the chunk's operands are read before the next chunk overwrites them
   };
-  Staged st[ITEMS];
+  Staged st;
   load(0, st);
   for (int k0 = 0; k0 < K; k0 += kKc) chunk(k0, st);
-#pragma unroll
-  for (int m = 0; m < ITEMS; ++m) {
-    const int item = (int)threadIdx.x + m * kThreads;
-    int slab, row0, o;
-    item_rows(item, slab, row0, o);
-    if (!(item < n_items && ((need >> slab) & 1u))) continue;
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-      if (isums[m][r]) atomicAdd(&colsum[row0 + r], isums[m][r]);
-  }
-  __syncthreads();
 
   // Output: element v of the lane is R[32 a + 8 (v / 4) + 4 g + v % 4][32 b + n].
   const double count = (double)K, inv = 1.0 / count;
@@ -298,16 +269,13 @@ hipError_t launch_correlate(const CorrelateArgs& a, hipStream_t s) {
   b.n_groups = n_groups;
   const unsigned grid = (unsigned)n_wg;
   const size_t lds_bytes = correlate_lds_bytes(a.A);
-  const int items = (a.n_slabs * kItemsPerSlab + kThreads - 1) / kThreads;
-  const void* fn = items <= 1 ? reinterpret_cast<const void*>(k_correlate<1>)
-                              : reinterpret_cast<const void*>(k_correlate<2>);
-  if (items > 2) return hipErrorInvalidValue;
+  if (a.n_slabs * kItemsPerSlab > kThreads) return hipErrorInvalidValue;   // one item per thread
   if (lds_bytes > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_correlate),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
   }
-  if (items <= 1) k_correlate<1><<<grid, kThreads, lds_bytes, s>>>(b);
-  else k_correlate<2><<<grid, kThreads, lds_bytes, s>>>(b);
+  k_correlate<<<grid, kThreads, lds_bytes, s>>>(b);
   return hipGetLastError();
 }
 
