@@ -73,12 +73,19 @@ struct Staged {
 // A workgroup of 12 waves owns 36 tiles: every tile of one (interval, channel) up to 128 antennas
 // (8 slabs), so each input is staged once per chunk; larger arrays take several workgroups. Each
 // thread stages at most one item (n_slabs * kItemsPerSlab <= 512 items up to 256 antennas).
+// With DB (two plane buffers, up to 8 slabs) the staging waves store chunk i + 1 into one buffer
+// while every wave forms chunk i's products from the other: one barrier per chunk, and the other
+// waves' matrix products cover the staging's byte permutes on each SIMD.
+template <bool DB>
 __global__ __launch_bounds__(kThreads, 1) void k_correlate(CorrelateArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int IP = a.n_slabs * kTile;               // padded input count
-  unsigned char* x = lds;                         // plane P [IP][kRow]: (re, im) pairs, terms contiguous
-  unsigned char* xq = lds + (size_t)IP * kRow;    // plane Q [IP][kRow]: (im, ~re) pairs
-  int* colsum = reinterpret_cast<int*>(lds + (size_t)2 * IP * kRow);   // [IP]: sum of Xi over K
+  const size_t plane = (size_t)IP * kRow;
+  unsigned char* x0 = lds;                        // plane P [IP][kRow]: (re, im) pairs, terms contiguous
+  unsigned char* xq0 = lds + plane;               // plane Q [IP][kRow]: (im, ~re) pairs
+  unsigned char* x1 = DB ? lds + 2 * plane : x0;  // second buffer (DB)
+  unsigned char* xq1 = DB ? lds + 3 * plane : xq0;
+  int* colsum = reinterpret_cast<int*>(lds + (DB ? 4 : 2) * plane);   // [IP]: sum of Xi over K
   __shared__ unsigned s_need;                     // bit s: slab s is used by this workgroup
 
   // Workgroups are dispatched to the 8 XCDs in turn (workgroup w to XCD w % 8): the n_groups
@@ -155,7 +162,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_correlate(CorrelateArgs a) {
   // transpose: row row0 + r gets the (re, im) pairs of its 8 terms as one 16-byte vector in P and
   // the (im, ~re) pairs in Q (byte permutes of two loaded words each); the chunk's imaginary parts
   // of each row are added to colsum
-  auto store = [&](const Staged& st) {
+  auto store = [&](const Staged& st, unsigned char* x, unsigned char* xq) {
     if (staged) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
@@ -184,14 +191,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_correlate(CorrelateArgs a) {
     }
   };
 
-  // one chunk: stage the registers st into LDS, request the next chunk into st (answered during
-  // this chunk's products), then the products
-  auto chunk = [&](int k0, Staged& st) {
-    store(st);
-    __syncthreads();
-    if (k0 + kKc < K) load(k0 + kKc, st);
-    // the wave's tiles run along tile rows (row order), so the row operands A and As are read
-    // once per tile row and step and reused by the following tiles of that row
+  // the products of one staged chunk: the wave's tiles run along tile rows (row order), so the
+  // row operands A and As are read once per tile row and step and reused by the following tiles
+  // of that row
+  auto products = [&](const unsigned char* x, const unsigned char* xq) {
 #pragma unroll
     for (int kk = 0; kk < 2 * kKc; kk += 32) {
       const int q = kk / 16 + g;                    // this lane's term octet of the step
@@ -213,11 +216,36 @@ __global__ __launch_bounds__(kThreads, 1) void k_correlate(CorrelateArgs a) {
         im[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(As, B, im[u], 0, 0, 0);
       }
     }
-    __syncthreads();   // the chunk's operands are read before the next chunk overwrites them
   };
   Staged st;
   load(0, st);
-  for (int k0 = 0; k0 < K; k0 += kKc) chunk(k0, st);
+  if constexpr (DB) {
+    // chunk i + 1 (loaded during chunk i - 1) is stored into the free buffer and chunk i + 2
+    // requested before chunk i's products; the barrier closes both the products' reads of one
+    // buffer and the stores into the other
+    store(st, x0, xq0);
+    if (kKc < K) load(kKc, st);
+    __syncthreads();
+    int i = 0;
+    for (int k0 = 0; k0 < K; k0 += kKc, ++i) {
+      if (k0 + kKc < K) {
+        store(st, (i & 1) ? x0 : x1, (i & 1) ? xq0 : xq1);
+        if (k0 + 2 * kKc < K) load(k0 + 2 * kKc, st);
+      }
+      products((i & 1) ? x1 : x0, (i & 1) ? xq1 : xq0);
+      __syncthreads();
+    }
+  } else {
+    // one buffer: stage the registers into LDS, request the next chunk (answered during this
+    // chunk's products), then the products
+    for (int k0 = 0; k0 < K; k0 += kKc) {
+      store(st, x0, xq0);
+      __syncthreads();
+      if (k0 + kKc < K) load(k0 + kKc, st);
+      products(x0, xq0);
+      __syncthreads();   // the chunk's operands are read before the next chunk overwrites them
+    }
+  }
 
   // Output: element v of the lane is R[32 a + 8 (v / 4) + 4 g + v % 4][32 b + n].
   const double count = (double)K, inv = 1.0 / count;
@@ -251,9 +279,12 @@ __global__ __launch_bounds__(kThreads, 1) void k_correlate(CorrelateArgs a) {
 
 }  // namespace
 
+// Two plane buffers when they fit the 160 KB of LDS (up to 8 slabs, 128 antennas), else one.
+static bool correlate_db(int slabs) { return (size_t)slabs * kTile * (4 * kRow + sizeof(int)) <= 160 * 1024; }
+
 size_t correlate_lds_bytes(int A) {
   const int slabs = (2 * A + kTile - 1) / kTile;
-  return (size_t)slabs * kTile * (2 * kRow + sizeof(int));
+  return (size_t)slabs * kTile * ((correlate_db(slabs) ? 4 : 2) * kRow + sizeof(int));
 }
 
 hipError_t launch_correlate(const CorrelateArgs& a, hipStream_t s) {
@@ -270,12 +301,15 @@ hipError_t launch_correlate(const CorrelateArgs& a, hipStream_t s) {
   const unsigned grid = (unsigned)n_wg;
   const size_t lds_bytes = correlate_lds_bytes(a.A);
   if (a.n_slabs * kItemsPerSlab > kThreads) return hipErrorInvalidValue;   // one item per thread
+  const bool db = correlate_db(a.n_slabs);
+  const void* fn = db ? reinterpret_cast<const void*>(k_correlate<true>)
+                      : reinterpret_cast<const void*>(k_correlate<false>);
   if (lds_bytes > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_correlate),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
   }
-  k_correlate<<<grid, kThreads, lds_bytes, s>>>(b);
+  if (db) k_correlate<true><<<grid, kThreads, lds_bytes, s>>>(b);
+  else k_correlate<false><<<grid, kThreads, lds_bytes, s>>>(b);
   return hipGetLastError();
 }
 
