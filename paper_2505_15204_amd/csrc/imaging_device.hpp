@@ -261,53 +261,23 @@ __device__ __forceinline__ void strip_fft_store(float2* sbuf, int strip, float2*
   store_strip<LOGN, S, NT, REAL0, ZERO>(sbuf, strip, Hi);
 }
 
-// ---------------------------------------------------------------- fused grid + column FFT task
-// One strip of S half-spectrum columns of one image: zero the LDS strip, scatter the strip's
-// placements, (uniform) divide by counts and add the strip's occupied cells (column 0 once,
-// columns 1..N/2-1 twice for their mirrors) to *occ_img, inverse FFT every column along v, and
-// store the strip into Hi[y][strip*S + c]. Column 0 is stored as (Re of its transform, 0): the
-// real part is the transform of the column's Hermitian part, and the Nyquist column is empty.
-// Threads beyond S*T of the workgroup only join the barriers. `tw` is the twiddle table for N.
-// PREC selects the FP32 butterflies or the split matrix-core form (split_fft.hpp), which needs a
-// workgroup of whole waves; `sp` holds that form's LDS word for the strip's largest magnitude and
-// the DFT operand table.
-// NT is the workgroup size (a compile-time loop stride).
-template <int LOGN, int S, bool UNIFORM, int PREC, int NT>
-__device__ __forceinline__ void grid_colfft_task(const float2* __restrict__ V, const int2* __restrict__ plc, int o0,
-                                                 int o1, int strip, bool shift, float2* __restrict__ Hi,
-                                                 int* occ_img, const float2* __restrict__ tw, float2* sbuf,
-                                                 unsigned* scnt, int* s_tmp, SplitCtx sp = {}) {
-  using P = FftPlan<LOGN>;
-  constexpr int N = P::N, T = P::T, NP = P::NP;
-  constexpr bool SPLIT = PREC != kPrecFp32 && LOGN >= 4;
-  static_assert(NT >= S * T, "one thread per FFT thread at least");
-#pragma unroll 4
-  for (int i = threadIdx.x; i < S * NP; i += NT) sbuf[i] = make_float2(0.f, 0.f);
-  if constexpr (UNIFORM)
-    for (int i = threadIdx.x; i < S * N; i += NT) scnt[i] = 0u;
-  if (threadIdx.x == 0) {
-    *s_tmp = 0;
-    if constexpr (SPLIT) *sp.s_max = 0u;
-  }
-  __syncthreads();
-  scatter_strip<LOGN, S, true, UNIFORM>(plc, o0, o1, V, strip, NP, shift, sbuf, scnt);
-  __syncthreads();
-  if constexpr (UNIFORM) {
-    int occ = uniform_divide<LOGN, S, true, NT>(sbuf, scnt, NP, strip == 0 ? 1 : 2, 2);
-    block_add_to_global(occ, s_tmp, occ_img);
-    __syncthreads();
-  }
-  strip_fft_store<LOGN, S, PREC, NT, true>(sbuf, strip, Hi, tw, sp);
-}
-
-// ---------------------------------------------------------------- pipelined strips of one image
-// The strips strip0, strip0 + dstrip, ... (< nstrips) of one image, each as grid_colfft_task
-// does it, with the global loads of the placements software-pipelined across strips: the first
-// PF*NT placement records of the strip after next and the visibilities of the next strip are
-// requested before the current strip's column FFT and store, so they arrive while the workgroup
-// computes and the scatter of the next strip starts from registers. Placements beyond the first
-// PF*NT of a strip are loaded in the scatter as in grid_colfft_task. s_off (LDS, nstrips + 1
-// ints) holds the image's strip offsets, copied by the caller before the first barrier.
+// ---------------------------------------------------------------- fused grid + column FFT of strips
+// The strips strip0, strip0 + dstrip, ... (< nstrips) of one image. One strip is S half-spectrum
+// columns: scatter the strip's placements into the zeroed LDS strip, (uniform) divide by counts
+// and add the strip's occupied cells (column 0 once, columns 1..N/2-1 twice for their mirrors) to
+// *occ_img, inverse FFT every column along v, and store the strip into Hi[y][strip*S + c]. Column
+// 0 is stored as (Re of its transform, 0): the real part is the transform of the column's
+// Hermitian part, and the Nyquist column is empty. `tw` is the twiddle table for N. PREC selects
+// the FP32 butterflies or the split matrix-core form (split_fft.hpp), which needs a workgroup of
+// whole waves (threads beyond S*T only join the barriers); `sp` holds that form's LDS word for
+// the strip's largest magnitude and the DFT operand table. NT is the workgroup size.
+//
+// The global loads of the placements are software-pipelined across strips: the first PF*NT
+// placement records of the strip after next and the visibilities of the next strip are requested
+// before the current strip's column FFT and store, so they arrive while the workgroup computes
+// and the scatter of the next strip starts from registers. Placements beyond the first PF*NT of a
+// strip are loaded in the scatter. s_off (LDS, nstrips + 1 ints) holds the image's strip offsets,
+// written by the caller before the first barrier.
 //
 // Every prefetch load of an existing strip is issued unconditionally (slots past the strip's end
 // read record 0 and visibility 0 of the image, in bounds whenever B > 0) and whether a slot holds
@@ -318,6 +288,9 @@ __device__ __forceinline__ void grid_colfft_task(const float2* __restrict__ V, c
 // prefetch is fixed: consuming a prefetched value waits only for the loads before it, never for
 // the previous strip's stores (the memory counter is in order), and those stores drain while the
 // next strip is gridded and transformed.
+// Placement records per thread that the strip loop requests one strip ahead.
+constexpr int kColPrefetch = 2;
+
 template <int PF>
 struct StripPrefetch {
   int2 r[PF];       // placement records of slots threadIdx.x + j*NT of the strip

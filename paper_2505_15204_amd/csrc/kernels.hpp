@@ -48,9 +48,6 @@ struct RowDefault {
   static constexpr int value = cmin(P::N / 2, (256 / P::T) > 0 ? 256 / P::T : 1);
 };
 
-// Placement records per thread that the fused column kernel requests one strip ahead.
-constexpr int kColPrefetch = 2;
-
 // Workgroup size for `work` FFT threads: exact for FP32, whole waves for the split forms.
 __host__ __device__ constexpr int fft_block(int work, int prec) {
   return prec == kPrecFp32 ? work : ((work + 63) / 64) * 64;

@@ -36,6 +36,15 @@ struct PersistLds {
     for (int l = 3; l <= 12; ++l) m = f2(l) > m ? f2(l) : m;
     return m;
   }
+  // strips of the largest count over all grid sizes (the strip offsets staged in LDS)
+  static constexpr int max_strips() {
+    int m = 0;
+    for (int l = 3; l <= 12; ++l) {
+      int c = (1 << l) / 2 / desc_cols(l, BLOCK);
+      m = c > m ? c : m;
+    }
+    return m;
+  }
   static constexpr int max_counts() {
     int m = 0;
     for (int l = 3; l <= 12; ++l) {
@@ -76,10 +85,12 @@ struct Log2<1> {
 };
 
 // `tw` is the twiddle table of N in global memory; with TWL it is first copied to `stw` (LDS)
-// unless the previous job of this workgroup had the same size (*s_tw_logn).
+// unless the previous job of this workgroup had the same size (*s_tw_logn). The strips are
+// gridded and transformed by the batched path's pipelined strip loop (grid_colfft_strips, every
+// strip in turn) from the strip offsets copied to `s_off` (LDS, NBLK + 1 ints).
 template <int LOGN, int BLOCK, bool UNIFORM, int PREC, bool TWL>
 __device__ __noinline__ void image_job(ImageJob j, const float2* __restrict__ tw, float2* sbuf, unsigned* scnt,
-                                       int* s_int, SplitCtx sp, float2* stw, int* s_tw_logn) {
+                                       int* s_int, SplitCtx sp, float2* stw, int* s_tw_logn, int* s_off) {
   constexpr int N = 1 << LOGN;
   constexpr int S = desc_cols(LOGN, BLOCK);
   constexpr int NBLK = (N / 2) / S;         // column strips, and row blocks of S row pairs
@@ -100,11 +111,9 @@ __device__ __noinline__ void image_job(ImageJob j, const float2* __restrict__ tw
   bin_visibilities(j.uvw, j.flags, j.B, j.k, LOGN, LOGS, N / 2, j.plc, j.off, s_kept, j.n_out, nullptr, bsh);
   if (threadIdx.x == 0) *s_occ = 0;
   __syncthreads();                          // placement list and offsets complete; binning scratch free
-  for (int strip = 0; strip < NBLK; ++strip) {
-    grid_colfft_task<LOGN, S, UNIFORM, PREC, BLOCK>(j.V, j.plc, j.off[strip], j.off[strip + 1], strip, j.shift != 0, j.H,
-                                             s_occ, tw, sbuf, scnt, s_tmp, sp);
-    __syncthreads();                        // the next strip reuses the strip buffer
-  }
+  for (int i = threadIdx.x; i <= NBLK; i += BLOCK) s_off[i] = j.off[i];   // visible after the loop's first barrier
+  grid_colfft_strips<LOGN, S, UNIFORM, PREC, BLOCK, kColPrefetch>(j.V, j.plc, s_off, 0, 1, NBLK, j.B > 0 ? NBLK : 0,
+                                                                  j.shift != 0, j.H, s_occ, tw, sbuf, scnt, s_tmp, sp);
   const double W = UNIFORM ? (double)*s_occ : 2.0 * (double)*s_kept;
   if (j.wsum && threadIdx.x == 0) *j.wsum = W;
   const float scale = inverse_weight(W);
@@ -125,6 +134,7 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(DescArgs a) {
   constexpr bool TWL = L::tw_in_lds;
   __shared__ float2 stw[TWL ? tw_size(12) : 1];
   __shared__ int s_tw_logn;
+  __shared__ int s_off[L::max_strips() + 1];
   if (threadIdx.x == 0) s_tw_logn = -1;   // visible after the claim barrier below
   const size_t slot_elems = (size_t)1 << (2 * a.max_logn - 1);
   float2* H = a.H + (size_t)blockIdx.x * slot_elems;
@@ -154,16 +164,16 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(DescArgs a) {
     j.wsum = a.weight_sum ? a.weight_sum + img : nullptr;
     j.shift = a.shift;
     switch (logn) {
-      case 3: image_job<3, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[3], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
-      case 4: image_job<4, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[4], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
-      case 5: image_job<5, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[5], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
-      case 6: image_job<6, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[6], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
-      case 7: image_job<7, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[7], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
-      case 8: image_job<8, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[8], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
-      case 9: image_job<9, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[9], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
-      case 10: image_job<10, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[10], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
-      case 11: image_job<11, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[11], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
-      case 12: image_job<12, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[12], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn); break;
+      case 3: image_job<3, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[3], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
+      case 4: image_job<4, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[4], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
+      case 5: image_job<5, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[5], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
+      case 6: image_job<6, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[6], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
+      case 7: image_job<7, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[7], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
+      case 8: image_job<8, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[8], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
+      case 9: image_job<9, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[9], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
+      case 10: image_job<10, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[10], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
+      case 11: image_job<11, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[11], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
+      case 12: image_job<12, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[12], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
       default: break;
     }
   }
