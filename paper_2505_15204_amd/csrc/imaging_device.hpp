@@ -173,9 +173,9 @@ __device__ __forceinline__ void scatter_strip(const int2* __restrict__ plc, int 
 }
 
 // Uniform weighting: cell mean; returns this thread's occupied-cell count (weighted). NT is the
-// workgroup size (0: read blockDim).
-template <int LOGN, int S, bool PADDED, int NT = 0>
-__device__ __forceinline__ int uniform_divide(float2* sbuf, const unsigned* scnt, int stride, int col_weight0,
+// workgroup size (0: read blockDim). With CLEAR every count read is reset to zero behind the read.
+template <int LOGN, int S, bool PADDED, int NT = 0, bool CLEAR = false>
+__device__ __forceinline__ int uniform_divide(float2* sbuf, unsigned* scnt, int stride, int col_weight0,
                                               int col_weight) {
   constexpr int N = 1 << LOGN;
   const int nt = NT > 0 ? NT : (int)blockDim.x;
@@ -189,16 +189,21 @@ __device__ __forceinline__ int uniform_divide(float2* sbuf, const unsigned* scnt
       p->x *= inv;
       p->y *= inv;
       occ += (col == 0) ? col_weight0 : col_weight;
+      if constexpr (CLEAR) scnt[i] = 0u;
     }
   }
   return occ;
 }
 
-// Adds one value per thread into *dst with a single global atomic per workgroup.
+// Adds one value per thread into *dst with a single global atomic per workgroup. *s_tmp is zero
+// on entry and is zero again once the caller's next barrier has passed.
 __device__ __forceinline__ void block_add_to_global(int val, int* s_tmp, int* dst) {
   if (val) atomicAdd(s_tmp, val);
   __syncthreads();
-  if (threadIdx.x == 0 && *s_tmp) atomicAdd(dst, *s_tmp);
+  if (threadIdx.x == 0) {
+    if (*s_tmp) atomicAdd(dst, *s_tmp);
+    *s_tmp = 0;
+  }
 }
 
 // ---------------------------------------------------------------- strip store
@@ -329,13 +334,17 @@ __device__ __forceinline__ void grid_colfft_strips(const float2* __restrict__ V,
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, NP = P::NP;
   constexpr bool SPLIT = PREC != kPrecFp32 && LOGN >= 4;
-  // FP32 with natural weighting clears the strip buffer once here and then behind the reads of
-  // each strip's store (store_strip with ZERO), which saves a pass over LDS and a barrier per strip.
-  constexpr bool ZERO_IN_STORE = !SPLIT && !UNIFORM;
+  // The FP32 form clears the strip buffer (and the counts of uniform weighting) once here and then
+  // behind the reads of each strip's store (store_strip with ZERO) and of the division by the
+  // counts (uniform_divide with CLEAR), which saves the clearing passes and a barrier per strip.
+  constexpr bool ZERO_IN_STORE = !SPLIT;
   StripPrefetch<PF> cur, nxt;
   if constexpr (ZERO_IN_STORE) {
 #pragma unroll 4
     for (int i = threadIdx.x; i < S * NP; i += NT) sbuf[i] = make_float2(0.f, 0.f);
+    if constexpr (UNIFORM)
+      for (int i = threadIdx.x; i < S * N; i += NT) scnt[i] = 0u;
+    if (threadIdx.x == 0) *s_tmp = 0;
   }
   __syncthreads();   // s_off is visible (and the strip buffer zero)
   prefetch_records<PF, NT>(plc, s_off, strip0, pf_strips, cur);
@@ -366,7 +375,7 @@ __device__ __forceinline__ void grid_colfft_strips(const float2* __restrict__ V,
                                           scnt);
     __syncthreads();
     if constexpr (UNIFORM) {
-      int occ = uniform_divide<LOGN, S, true, NT>(sbuf, scnt, NP, strip == 0 ? 1 : 2, 2);
+      int occ = uniform_divide<LOGN, S, true, NT, ZERO_IN_STORE>(sbuf, scnt, NP, strip == 0 ? 1 : 2, 2);
       block_add_to_global(occ, s_tmp, occ_img);
       __syncthreads();
     }
