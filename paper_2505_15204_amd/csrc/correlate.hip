@@ -47,22 +47,42 @@ __device__ __forceinline__ void tile_of(int tau, int& a, int& b) {
   b = tau - r * (r + 1) / 2;
 }
 
-// x / K rounded once to float, for an integer |x| < 2^32 and K <= 65535, inv = 1/K rounded to
-// double. qd = x inv is within 2^-52 (relative) of the quotient q; q is either a float rounding
-// midpoint itself or at least 2^-49 (relative) away from every midpoint (a nonzero difference of
-// two fractions with denominators K and 2^e), so (float)qd rounds q correctly except on an exact
-// midpoint, which is detected exactly (m K == x has at most 41 significant bits) and resolved to
-// the even neighbour. This is the value of (float)((double)x / K).
-__device__ __forceinline__ float mean_rn(double x, double K, double inv) {
-  const double qd = x * inv;
-  const float f = (float)qd;
-  const unsigned bits = __float_as_uint(f);
-  if ((bits & 1u) && qd != (double)f) {
-    const float g = __uint_as_float(fabs(qd) > fabs((double)f) ? bits + 1 : bits - 1);
-    const double m = 0.5 * ((double)f + (double)g);
-    if (m * K == x) return g;
-  }
-  return f;
+// x / K rounded once to float for an integer |x| < 2^31 and K <= 65535: the value of
+// (float)((double)x / K). Write K = d 2^a with d odd. A quotient q = x / K that is a float
+// rounding midpoint is a dyadic rational, so d divides x. Divisibility by d is one multiply by the
+// inverse of d modulo 2^32: |x| dinv mod 2^32 <= (2^32 - 1) / d exactly when d divides |x|, and
+// the product is then the exact quotient |x| / d, whose conversion to float (round to nearest
+// even) times 2^-a is q correctly rounded. When d does not divide x, q is no midpoint and lies at
+// least 2^-49 (relative) from every midpoint (a nonzero difference of fractions with denominators
+// K and 2^e), while qd = x * (1/K in FP64) is within 2^-52 of q, so (float)qd rounds q correctly.
+// Both ways are computed and one is selected, without branches.
+struct MeanDiv {
+  double inv;        // 1 / K rounded to double
+  unsigned dinv;     // inverse of the odd part d of K modulo 2^32
+  unsigned bound;    // (2^32 - 1) / d
+  float scale;       // 2^-a
+};
+
+__device__ __forceinline__ MeanDiv mean_div(int K) {
+  MeanDiv m;
+  m.inv = 1.0 / (double)K;
+  const int a = __builtin_ctz((unsigned)K);
+  const unsigned d = (unsigned)K >> a;
+  unsigned di = d;                                   // Newton's iteration doubles the correct bits
+  for (int i = 0; i < 5; ++i) di *= 2u - d * di;
+  m.dinv = di;
+  m.bound = 0xffffffffu / d;
+  m.scale = __uint_as_float((unsigned)(127 - a) << 23);
+  return m;
+}
+
+__device__ __forceinline__ float mean_rn(int x, const MeanDiv& m) {
+  const unsigned ax = x < 0 ? 0u - (unsigned)x : (unsigned)x;
+  const unsigned t = ax * m.dinv;
+  const float fq = (float)((double)x * m.inv);
+  const float fe = __uint2float_rn(t) * m.scale;
+  const float fd = x < 0 ? -fe : fe;
+  return t <= m.bound ? fd : fq;
 }
 
 // One staging item: 16 bytes (8 inputs, re and im) for each of 8 consecutive terms.
@@ -248,7 +268,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_correlate(CorrelateArgs a) {
   }
 
   // Output: element v of the lane is R[32 a + 8 (v / 4) + 4 g + v % 4][32 b + n].
-  const double count = (double)K, inv = 1.0 / count;
+  const MeanDiv md = mean_div(K);
   const long B = (long)a.A * (a.A - 1) / 2;
 #pragma unroll
   for (int u = 0; u < kTilesPerWave; ++u) {
@@ -261,8 +281,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_correlate(CorrelateArgs a) {
       if (ri >= in2 || ci >= in2) continue;
       const int i = ri / 2, p = ri % 2, j = ci / 2, q = ci % 2;
       if (i < j) continue;
-      const float vr = mean_rn((double)re[u][v], count, inv);
-      const float vi = mean_rn((double)im[u][v] + (double)csum, count, inv);
+      // Im R = im + csum fits in int32 (|R| <= 2 K 128^2 < 2^31); the sum is formed modulo 2^32
+      const float vr = mean_rn(re[u][v], md);
+      const float vi = mean_rn((int)((unsigned)im[u][v] + (unsigned)csum), md);
       if (i == j) {
         if (a.autos) a.autos[(((size_t)t * a.C + c) * a.A + i) * 4 + 2 * p + q] = make_float2(vr, vi);
         continue;
