@@ -365,9 +365,9 @@ blink_status blink_set_plan(blink_ctx ctx, int grid_n, int weighting, int precis
 
 /* Autotuner: runs blink_image_batch on the caller's problem (same arguments) for every compiled
  * (col_strip, row_block) pair and group sizes 16, 24, 32, 48, 64, 96, 128, 256 with col_loop 1,
- * then col_loop 2, 4, .. 16
- * on the fastest of those; times each with hipEvents on hip_stream and keeps the fastest as the
- * context's plan for (grid_n, weighting, precision). Synchronises with the host. On return
+ * then every group with col_loop 2, 4, .. 16 and the strip width and row block of the fastest of
+ * those; times each with hipEvents on hip_stream and keeps the fastest as the context's plan for
+ * (grid_n, weighting, precision). Synchronises with the host. On return
  * `images` etc. hold a valid result, and col_strip, row_block, group, col_loop and best_ms (any
  * may be NULL) describe the choice. */
 blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32 *vis, const uint8_t *flags,

@@ -1389,7 +1389,8 @@ blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32* vis, co
     }
   };
   // every (group, strip width, row block) with one strip per column workgroup, then 2, 4, .. 16
-  // strips per workgroup on the best of those
+  // strips per workgroup for every group with the best strip width and row block of those (the
+  // best group can change with the strips per workgroup)
   for (int gi = 0; gi < n_groups && result == BLINK_OK; ++gi) {
     for (int ci = 0; ci < nc && result == BLINK_OK; ++ci) {
       for (int ri = 0; ri < nr && result == BLINK_OK; ++ri) {
@@ -1404,10 +1405,13 @@ blink_status blink_autotune_image_batch(blink_ctx ctx, const blink_cf32* vis, co
   if (result == BLINK_OK) {
     const auto first = best_plan;
     const int nstrips = (1 << logn) / 2 / first.col_strip;
-    for (int loop = 2; loop <= 16 && loop <= nstrips && result == BLINK_OK; loop *= 2) {
-      p = first;
-      p.col_loop = loop;
-      time_plan();
+    for (int gi = 0; gi < n_groups && result == BLINK_OK; ++gi) {
+      for (int loop = 2; loop <= 16 && loop <= nstrips && result == BLINK_OK; loop *= 2) {
+        p = first;
+        p.group = groups[gi];
+        p.col_loop = loop;
+        time_plan();
+      }
     }
   }
   (void)hipEventDestroy(e0);
