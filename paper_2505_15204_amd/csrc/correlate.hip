@@ -161,8 +161,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_correlate(CorrelateArgs a) {
   const bool on = staged && row0 < in2;                           // ... and loads voltages for them
   // global loads of one chunk's item of this thread (unused slabs, inputs past 2A and terms past K
   // are not loaded and stage zeros). Term k is (sample k / n_favg, fine channel k % n_favg) of the
-  // block: one division per chunk, then the byte offset steps one record per term and over the
-  // other channels' records where a sample ends.
+  // block; one division per chunk.
   auto load = [&](int k0, Staged& st) {
     const int kb = k0 + 8 * o;
     int sl = kb / a.n_favg, fl = kb - sl * a.n_favg;
