@@ -225,8 +225,8 @@ blink_status blink_image_batch_conv(blink_ctx ctx, const blink_cf32 *vis, const 
                                     size_t workspace_bytes, void *hip_stream);
 
 /* ---------------------------------------------------------------- image averages
- * The paper averages its dirty images over time and over the band (Section 7.1: a long-exposure
- * image over all seconds and the 30.72 MHz band; Section 7.2: all channels of each 20 ms bin).
+ * The paper averages its dirty images over time and over the band (Section 7.2: a long-exposure
+ * image over all seconds and the 30.72 MHz band; Section 7.3: all channels of each 20 ms bin).
  * blink_image_average averages images float [T][C][P][N][N] (device) over every axis set in
  * `axes` and keeps the others: out float [T'][C'][P'][N][N] with T' = 1 if averaged over time,
  * else T (likewise C', P'). Averaging P = 2 (XX, YY) gives Stokes I = (XX + YY) / 2. Sums are

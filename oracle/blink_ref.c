@@ -474,7 +474,7 @@ int blink_ref_image_batch_conv(const float *vis, const uint8_t *flags, const dou
 }
 
 /* ------------------------------------------------------------------------------------------
- * Image averages (Sections 7.1 and 7.2: images are averaged over time and over the band, e.g.
+ * Image averages (Sections 7.2 and 7.3: images are averaged over time and over the band, e.g.
  * all channels of one time bin). images [T][C][P][N][N] float; each axis selected in `axes`
  * (1 time, 2 channel, 4 polarisation) is averaged (its extent becomes 1), the others are kept:
  * out [T'][C'][P'][N][N] double. Over P = 2 (XX, YY) this is Stokes I = (XX + YY) / 2.

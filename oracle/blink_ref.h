@@ -116,7 +116,7 @@ int blink_ref_image_batch_conv(const float *vis, const uint8_t *flags, const dou
                                double pixel_scale, int width, double beta, int shift, double *images,
                                double *weight_sum, int32_t *n_out, int n_threads);
 
-/* Image averages (Sections 7.1, 7.2): images float [T][C][P][N][N]; every axis set in `axes`
+/* Image averages (Sections 7.2, 7.3): images float [T][C][P][N][N]; every axis set in `axes`
  * (1 time, 2 channel, 4 polarisation) is averaged, the others kept; out double [T'][C'][P'][N][N].
  * Over P = 2 (XX, YY) the polarisation average is Stokes I. */
 int blink_ref_image_average(const float *images, int T, int C, int P, int grid_n, int axes, double *out);

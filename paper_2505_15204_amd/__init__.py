@@ -233,6 +233,24 @@ def _ptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def _on_stream(method):
+    """Run an entry method with the caller's `stream` as torch's current stream, so that every
+    tensor the binding allocates for the call (workspace, outputs) belongs to the stream the
+    kernels run on: torch's caching allocator then reuses the workspace, which is freed when the
+    method returns, only behind the work queued on that stream."""
+    import functools
+
+    @functools.wraps(method)
+    def wrapper(self, *args, **kwargs):
+        stream = kwargs.get("stream")
+        if stream is None:
+            return method(self, *args, **kwargs)
+        import torch
+        with torch.cuda.device(self.device), torch.cuda.stream(stream):
+            return method(self, *args, **kwargs)
+    return wrapper
+
+
 class Context:
     """One library context (device tables and error state) on a HIP device."""
 
@@ -314,6 +332,7 @@ class Context:
                 self.set_plan(int(n), int(w), p["col_strip"], p["row_block"], p["group"], precision=int(prec),
                               col_loop=p.get("col_loop", 1))
 
+    @_on_stream
     def autotune_image_batch(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float, weighting: int = 0,
                              precision: int = PREC_FP32, shift: bool = True, out=None, workspace=None, stream=None):
         """Time every compiled plan on this problem and keep the fastest; returns (plan dict, best ms)."""
@@ -364,6 +383,7 @@ class Context:
                 int(weighting), int(precision), int(bool(shift)), _ptr(images), images.numel(), _ptr(weight_sum),
                 _ptr(n_out), _ptr(status), _ptr(ws), ws.numel()], ws
 
+    @_on_stream
     def blink_image_batch_desc(self, desc, vis, uvw_m, flags, images, max_baselines: int, max_grid_n: int,
                                weighting: int = 0, precision: int = PREC_FP32, shift: bool = True, weight_sum=None,
                                n_out=None, status=None, workspace=None, stream=None):
@@ -385,6 +405,7 @@ class Context:
     def set_desc_plan(self, block_threads: int = 512, workgroups: int = 0):
         _check(lib().blink_set_desc_plan(self.handle, block_threads, workgroups), self.handle, "blink_set_desc_plan")
 
+    @_on_stream
     def autotune_desc(self, desc, vis, uvw_m, flags, images, max_baselines: int, max_grid_n: int, weighting: int = 0,
                       precision: int = PREC_FP32, shift: bool = True, workspace=None, stream=None):
         args, ws = self._desc_args(desc, vis, uvw_m, flags, images, weighting, precision, shift, None, None, None,
@@ -437,6 +458,7 @@ class Context:
         return workspace
 
     # -- entry points (same names as the C ABI)
+    @_on_stream
     def blink_grid(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float, weighting: int = 0,
                    want_counts: bool = True, want_cell_idx: bool = True, workspace=None, stream=None):
         """Nearest-cell gridding. vis complex64 [T][C][P][B]; flags uint8 [T][C][B] or None;
@@ -464,6 +486,7 @@ class Context:
         _check(st, self.handle, "blink_grid")
         return {"grids": grids, "counts": counts, "weight_sum": wsum, "cell_idx": cell, "n_out": nout}
 
+    @_on_stream
     def blink_ifft2d(self, grids, weight_sum=None, shift: bool = True, precision: int = PREC_FP32,
                      out=None, workspace=None, stream=None):
         """Dirty images Re(IDFT2(G))/W of complex64 grids [..., N, N]; returns float32 [..., N, N]."""
@@ -486,6 +509,7 @@ class Context:
         _check(st, self.handle, "blink_ifft2d")
         return out
 
+    @_on_stream
     def blink_image_batch(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float,
                           weighting: int = 0, precision: int = PREC_FP32, shift: bool = True, out=None,
                           weight_sum=None, n_out=None, workspace=None, stream=None):
@@ -515,6 +539,7 @@ class Context:
         _check(st, self.handle, "blink_image_batch")
         return {"images": out, "weight_sum": weight_sum, "n_out": n_out}
 
+    @_on_stream
     def blink_image_batch_corrected(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float,
                                     weighting: int = 0, gains=None, l0: float = 0.0, m0: float = 0.0,
                                     precision: int = PREC_FP32, shift: bool = True, out=None, weight_sum=None,
@@ -552,6 +577,7 @@ class Context:
         _check(st, self.handle, "blink_image_batch_corrected")
         return {"images": out, "weight_sum": weight_sum, "n_out": n_out}
 
+    @_on_stream
     def blink_correlate(self, volt, n_int: int, n_favg: int = 1, pol_mode: int = 4, autos: bool = False, out=None,
                         autos_out=None, stream=None):
         """Correlator: volt int8 device tensor [S][F][A][2][2] (re, im). Returns dict(vis complex64
@@ -575,6 +601,7 @@ class Context:
         _check(st, self.handle, "blink_correlate")
         return {"vis": out, "autos": autos_out}
 
+    @_on_stream
     def blink_dedisperse(self, images, delays, t_out: int, out=None, workspace=None, stream=None):
         """De-disperse images float32 device [T][C][N][N] with the host delay table delays int32
         [n_dm][C]; returns out float32 [n_dm][t_out][N][N]."""
@@ -597,6 +624,7 @@ class Context:
         _check(st, self.handle, "blink_dedisperse")
         return out
 
+    @_on_stream
     def blink_image_average(self, images, axes: int, out=None, stream=None):
         """Average float32 images [T][C][P][N][N] over the axes in `axes` (AVG_TIME | AVG_CHANNEL |
         AVG_POL); returns float32 [T'][C'][P'][N][N] (averaged axes have extent 1)."""
@@ -614,6 +642,7 @@ class Context:
         _check(st, self.handle, "blink_image_average")
         return out
 
+    @_on_stream
     def blink_image_batch_conv(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float,
                                kernel_width: int = 8, kernel_beta: float = 18.4, precision: int = PREC_FP32,
                                shift: bool = True, out=None, weight_sum=None, n_out=None, workspace=None,
@@ -655,6 +684,9 @@ class Graph:
 
     def launch(self, stream=None):
         _check(lib().blink_graph_launch(self.handle, self.ctx._stream(stream)), self.ctx.handle, "blink_graph_launch")
+        if stream is not None and self._keep:
+            # the workspace (allocated at capture on another stream) is in use on `stream` now
+            self._keep[0].record_stream(stream)
 
     def close(self):
         if getattr(self, "handle", None):

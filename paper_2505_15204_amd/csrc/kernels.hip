@@ -157,7 +157,7 @@ hipError_t launch_grid_colfft_conv(const ColArgs& a, int n_img, ConvParams cp, i
 
 // ---------------------------------------------------------------- image averages
 // Averages of images [T][C][P][N][N] over the axes in `axes` (1 time, 2 channel, 4 polarisation;
-// Sections 7.1 and 7.2 average over time and over the band, the polarisation average of XX and YY
+// Sections 7.2 and 7.3 average over time and over the band, the polarisation average of XX and YY
 // is Stokes I). One thread per 4 consecutive pixels of one output image, FP64 sums.
 // ---------------------------------------------------------------- visibility corrections
 // Antenna pair (i, j), i > j, of baseline b = i (i - 1) / 2 + j: the lower-triangular order in

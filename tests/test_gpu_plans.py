@@ -122,3 +122,45 @@ def test_autotuner_picks_a_compiled_plan_and_leaves_valid_images(torch, ctx, tmp
         assert ctx.get_plan(1024, 0) == plan
     finally:
         restore(ctx, 1024, 0, default)
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2], ids=["fp32", "split-f16", "split-bf16"])
+def test_benched_plan_full_time_step(torch, ctx, precision):
+    """One full time step of the 1024^2 VCS workload (768 channels x 2 pols, 8128 baselines, 10%
+    flags) under the committed tuned plans, i.e. the launch configuration the benchmark times for
+    each precision form. Sampled channels are checked against the FP64 oracle: weight sums and
+    out-of-grid counts bit-exact; images within 1e-5 (FP32) or, for the split forms, within 1e-3
+    relative L2 and peak error with the same 6-sigma detections."""
+    import paper_2505_15204_amd as blink
+    from image_checks import peak_error, recovery
+    spec = synth.spec_vcs(T=1)
+    with blink.Context(0) as c2:                     # the loaded plans stay in this context
+        c2.load_plans(blink.PLANS_PATH)
+        plan = c2.get_plan(1024, 0, precision)
+        say(f"benched plan, vcs-1024 full time step, precision={precision}: {plan}")
+        assert plan["group"] > 0
+        d = synth.make_problem_device(spec, "cuda:0")
+        res = c2.blink_image_batch(d["vis"], d["flags"], d["uvw_m"], d["freq_hz"], spec.grid_n, spec.pixel_scale,
+                                   0, precision=precision)
+        torch.cuda.synchronize()
+    img = res["images"]
+    assert bool(torch.isfinite(img).all())
+    chans = [0, 1, 23, 24, 383, 766, 767]           # first/last images of the tuned groups of 48
+    ref = oracle.image_batch(d["vis"][:, chans].cpu().numpy(), d["flags"][:, chans].cpu().numpy(),
+                             d["uvw_m"].cpu().numpy(), d["freq_hz"].cpu().numpy()[chans], spec.grid_n,
+                             spec.pixel_scale, 0)
+    assert np.array_equal(res["weight_sum"][:, chans].cpu().numpy(), ref["weight_sum"])
+    assert np.array_equal(res["n_out"][:, chans].cpu().numpy(), ref["n_out"])
+    got = img[:, chans].cpu().numpy()
+    for idx in np.ndindex(1, len(chans), 2):
+        e = rel_l2(got[idx], ref["images"][idx])
+        if precision == 0:
+            assert e <= IMAGE_TOL, (idx, e)
+        else:
+            pk = peak_error(got[idx], ref["images"][idx])
+            missing, spurious = recovery(got[idx], ref["images"][idx])
+            say(f"  {idx}: rel_l2={e:.3e} peak={pk:.3e} missing={len(missing)} spurious={len(spurious)}")
+            assert e <= 1e-3 and pk <= 1e-3 and not missing and not spurious, (idx, e, pk)
+    # every image of the step: natural W = 2 x (unflagged - out of grid), bit-exact
+    kept = (1 - d["flags"][0].to(torch.int64)).sum(-1) - res["n_out"][0].to(torch.int64)
+    assert torch.equal(res["weight_sum"][0], (2 * kept).to(torch.float64)[:, None].expand(-1, 2))
