@@ -12,6 +12,13 @@ pytestmark = pytest.mark.gpu
 IMAGE_TOL = 1e-5
 MIXED_TOL = 1e-3          # split FP16 / BF16 forms: relative L2 and peak error against FP64
 SPLITS = [(1, "split-f16"), (2, "split-bf16")]
+# Two runs of a split form on the same input (a graph replay and an eager call) may differ: the
+# LDS scatter adds a cell's placements in whatever order its atomics land, so grid cells can
+# differ in their last FP32 bit, and the hi + lo rounding of the operands turns such a difference
+# into a different operand error. Each run then lies within the form's own error of the oracle
+# (measured <= 2e-7 for split FP16 and <= 8e-6 for split BF16; the operand-rounding model gives
+# 1.4e-7 and 6.3e-6), so the two runs agree to the sum of those errors.
+REPLAY_TOL = {1: 1e-6, 2: 2e-5}
 
 
 def say(msg):
@@ -280,7 +287,7 @@ def test_split_graph_replays_match_oracle(torch, ctx, batch, prec, pname):
             assert int(status[0]) == 0 and float(junk) == float(junk)
             a, e = images.cpu().numpy(), eager.cpu().numpy()
             for i in range(lay["n_img"]):
-                assert rel_l2(batch.image(a, i), batch.image(e, i)) <= 1e-6, (rep, i)
+                assert rel_l2(batch.image(a, i), batch.image(e, i)) <= REPLAY_TOL[prec], (rep, i)
                 assert float(wsum[i]) == batch.ref[i][1]
                 check_split_image(batch.image(a, i), scale * batch.ref[i][0], f"replay {rep} image {i}")
     finally:
