@@ -148,6 +148,25 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32 *vis, const uint8
                                int32_t *n_out, void *workspace, size_t workspace_bytes,
                                void *hip_stream);
 
+/* ---------------------------------------------------------------- no-allocation variant
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): blink_image_batch with the same arguments, outputs and
+ * results, minus the workspace. Its scratch memory is a fixed device array of
+ * BLINK_STATIC_SCRATCH_BYTES inside the library (each GPU that the library runs on holds one
+ * copy until the process ends), so the call allocates nothing and takes no kernel timing. The
+ * (t, c) pairs are chunked to fit that array: a problem whose single (t, c) pair needs more
+ * (blink_image_batch_workspace_size with T = C = 1 above the limit, e.g. N = 4096) is rejected
+ * with BLINK_ERR_SIZE before anything is queued. Every call on one GPU shares that GPU's array,
+ * from any context: calls that overlap on one GPU (on different streams or host threads) race and
+ * must be serialised by the caller. Nothing in the array needs to start at zero. */
+#define BLINK_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+blink_status blink_image_batch_noalloc(blink_ctx ctx, const blink_cf32 *vis, const uint8_t *flags,
+                                       const double *uvw_m, const double *freq_hz, int T, int C,
+                                       int P, int B, int grid_n, double pixel_scale, int weighting,
+                                       int precision, int shift, float *images, double *weight_sum,
+                                       int32_t *n_out, void *hip_stream);
+
 /* ---------------------------------------------------------------- visibility corrections
  * The corrections the paper applies to the correlator output before imaging (Section 6.2.3):
  * calibration solutions per antenna, then the geometric correction that moves the phase centre to

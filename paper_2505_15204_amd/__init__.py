@@ -32,6 +32,7 @@ DESC_DTYPE = _np.dtype([("vis_offset", "<i8"), ("uvw_offset", "<i8"), ("flag_off
                         ("image_offset", "<i8"), ("freq_hz", "<f8"), ("pixel_scale", "<f8"),
                         ("n_baselines", "<i4"), ("grid_n", "<i4"), ("reserved", "<i4", (2,))])
 assert DESC_DTYPE.itemsize == 64
+STATIC_SCRATCH_BYTES = 64 << 20   # BLINK_STATIC_SCRATCH_BYTES (blink_image_batch_noalloc)
 PREC_FP32 = 0            # BLINK_PREC_FP32: FP32 radix-16 butterflies
 PREC_SPLIT_F16 = 1       # BLINK_PREC_SPLIT_F16: matrix-core radix-16 stages, FP16 hi + lo operands
 PREC_SPLIT_BF16 = 2      # BLINK_PREC_SPLIT_BF16: the same with BF16 operands
@@ -91,6 +92,8 @@ def lib() -> ctypes.CDLL:
     L.blink_image_batch.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32, P, P, P,
                                     P, sz, P]
     L.blink_image_batch_corrected_workspace_size.restype = i32
+    L.blink_image_batch_noalloc.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32, P, P, P, P]
+    L.blink_image_batch_noalloc.restype = i32
     L.blink_image_batch_corrected_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
     L.blink_image_batch_corrected.restype = i32
     L.blink_image_batch_corrected.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32, i32,
@@ -537,6 +540,32 @@ class Context:
                                      _ptr(out), _ptr(weight_sum), _ptr(n_out), _ptr(ws), ws.numel(),
                                      self._stream(stream))
         _check(st, self.handle, "blink_image_batch")
+        return {"images": out, "weight_sum": weight_sum, "n_out": n_out}
+
+    def blink_image_batch_noalloc(self, vis, flags, uvw_m, freq_hz, grid_n: int, pixel_scale: float,
+                                  weighting: int = 0, precision: int = PREC_FP32, shift: bool = True, *, out,
+                                  weight_sum=None, n_out=None, stream=None):
+        """blink_image_batch without a workspace: the library's static scratch array serves instead,
+        so the call allocates no device memory (the caller passes every output, `out` included;
+        weight_sum and n_out may be None). Calls that overlap on one GPU race on that array."""
+        torch = self._torch()
+        T, C, P, B = vis.shape
+        N = int(grid_n)
+        self._require("vis", vis, torch.complex64)
+        if flags is not None:
+            self._require("flags", flags, torch.uint8, (T, C, B))
+        self._require("uvw_m", uvw_m, torch.float64, (T, B, 3))
+        self._require("freq_hz", freq_hz, torch.float64, (C,))
+        self._require("out", out, torch.float32, (T, C, P, N, N))
+        if weight_sum is not None:
+            self._require("weight_sum", weight_sum, torch.float64, (T, C, P))
+        if n_out is not None:
+            self._require("n_out", n_out, torch.int32, (T, C))
+        st = lib().blink_image_batch_noalloc(self.handle, _ptr(vis), _ptr(flags), _ptr(uvw_m), _ptr(freq_hz), T, C,
+                                             P, B, N, float(pixel_scale), int(weighting), int(precision),
+                                             int(bool(shift)), _ptr(out), _ptr(weight_sum), _ptr(n_out),
+                                             self._stream(stream))
+        _check(st, self.handle, "blink_image_batch_noalloc")
         return {"images": out, "weight_sum": weight_sum, "n_out": n_out}
 
     @_on_stream

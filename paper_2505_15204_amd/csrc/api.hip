@@ -16,12 +16,19 @@
 
 constexpr int kPrecForms = 3;   // BLINK_PREC_FP32, BLINK_PREC_SPLIT_F16, BLINK_PREC_SPLIT_BF16
 
+// Scratch memory of blink_image_batch_noalloc: a fixed device array, so that the call allocates
+// nothing. Each device holds its own copy (at its own address) once the library's code is loaded
+// there. Host code never uses this name as a device address: blink_create looks the address up on
+// its device (hipGetSymbolAddress) and keeps it in the context.
+static __device__ __align__(256) unsigned char scratch[BLINK_STATIC_SCRATCH_BYTES];
+
 struct blink_ctx_s {
   int device = 0;
   float2* tw_base = nullptr;      // stage-ordered twiddle tables for N = 8 .. 4096, concatenated,
                                   // then the split forms' DFT operand table
   float2* tw[13] = {};
   const uint4* dft_ops = nullptr;
+  void* scratch = nullptr;        // this device's copy of the static scratch array
   bool broken = false;
   std::string err;
   // execution plan per (log2 N, weighting, precision form): fused-kernel strip width, row
@@ -329,6 +336,14 @@ blink_status blink_create(blink_ctx* out, int hip_device) {
   if (g.err != hipSuccess) {
     delete ctx;
     return BLINK_ERR_HIP;
+  }
+  {
+    void* sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+      delete ctx;
+      return BLINK_ERR_HIP;
+    }
+    ctx->scratch = sp;
   }
   size_t total = 0;
   for (int l = 3; l <= 12; ++l) total += (size_t)blink::twiddle_table_size(l);
@@ -712,6 +727,31 @@ blink_status blink_image_batch(blink_ctx ctx, const blink_cf32* vis, const uint8
                                int32_t* n_out, void* workspace, size_t workspace_bytes, void* hip_stream) {
   return image_batch(ctx, vis, flags, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting, precision, shift,
                      nullptr, images, weight_sum, n_out, workspace, workspace_bytes, hip_stream);
+}
+
+blink_status blink_image_batch_noalloc(blink_ctx ctx, const blink_cf32* vis, const uint8_t* flags,
+                                       const double* uvw_m, const double* freq_hz, int T, int C, int P, int B,
+                                       int grid_n, double pixel_scale, int weighting, int precision, int shift,
+                                       float* images, double* weight_sum, int32_t* n_out, void* hip_stream) {
+  if (!ctx) return BLINK_ERR_ARG;
+  if (!ctx->scratch) return fail(ctx, BLINK_ERR_STATE, "no static scratch address on this context's device");
+  const int logn = log2_exact(grid_n);
+  if (logn >= 0 && P >= 1 && B >= 0 && (weighting == BLINK_WEIGHT_NATURAL || weighting == BLINK_WEIGHT_UNIFORM)) {
+    const ImageLayout one = image_layout(1, P, B, logn, weighting, 1);
+    if (!one.ok || one.total > BLINK_STATIC_SCRATCH_BYTES)
+      return fail(ctx, BLINK_ERR_SIZE,
+                  "one (t,c) pair of N=%d, P=%d, B=%d needs %zu bytes of scratch, more than the %zu bytes of the "
+                  "static scratch of blink_image_batch_noalloc",
+                  grid_n, P, B, one.total, (size_t)BLINK_STATIC_SCRATCH_BYTES);
+  }
+  // Kernel timing is not taken here: recording it may create events.
+  const bool profiling = ctx->profiling;
+  ctx->profiling = false;
+  const blink_status st = image_batch(ctx, vis, flags, uvw_m, freq_hz, T, C, P, B, grid_n, pixel_scale, weighting,
+                                      precision, shift, nullptr, images, weight_sum, n_out, ctx->scratch,
+                                      BLINK_STATIC_SCRATCH_BYTES, hip_stream);
+  ctx->profiling = profiling;
+  return st;
 }
 
 blink_status blink_image_batch_corrected(blink_ctx ctx, const blink_cf32* vis, const uint8_t* flags,
