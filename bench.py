@@ -75,15 +75,21 @@ def kernel_unit_bytes(spec):
     grid_colfft: per image, write the half-spectrum intermediate N x N/2 complex64 (4 N^2 B) and
                  read each visibility once (8 B) plus its placement record (8 B).
     row_fft:     per image, read the intermediate (4 N^2 B) and write the FP32 image (4 N^2 B).
-    bin:         per (t,c) pair, read u, v (16 B) and the flag (1 B) of each baseline and write
-                 ~one placement record (8 B) per baseline.
+    bin:         per (t,c) pair, read the flag (1 B) of each baseline and write at most one
+                 placement record (8 B) per baseline (one per kept visibility in the half plane,
+                 two for the few on the u = 0 column); u, v (16 B per baseline) are shared by the
+                 C channels of a time step, so each pair is charged 16 B / C of them.
     """
-    N, B = spec.grid_n, spec.B
+    N, B, C = spec.grid_n, spec.B, spec.C
     return {
         "grid_colfft": ("image", 4 * N * N + 16 * B),
         "row_fft": ("image", 8 * N * N),
-        "bin": ("pair", 25 * B),
+        "bin": ("pair", 9 * B + (16 * B) // C),
     }
+
+
+# The last-level cache (AMD Infinity Cache, "MALL") of the MI355X: 256 MB in front of HBM.
+MALL_BYTES = 256 * 10**6
 
 
 def cpu_baseline(d, spec, budget_s):
@@ -232,6 +238,8 @@ def bench_precision_workload(ctx, torch, blink, synth, steps, warmup):
                      dtype=torch.uint8, device="cuda:0")
     out = {"workload": "precision-4096: 8128 baselines, 256 channels (every third VCS channel), 1 pol, "
                        "10 time steps, 4096^2 grid, 1 arcmin, natural weighting", "images_per_step": C * P}
+    # images kept for the error check against the FP64 oracle (made in the CPU-baseline leg)
+    samples = {"t": (steps - 1) % T, "channels": PRECISION_SAMPLE_CHANNELS, "images": {}}
     for name, prec in FORMS:
         def step(i, prec=prec):
             t = i % T
@@ -239,9 +247,94 @@ def bench_precision_workload(ctx, torch, blink, synth, steps, warmup):
                                   spec.pixel_scale, 0, precision=prec, out=images, workspace=ws)
         ms = timed(torch, step, steps, warmup)
         out[name] = {"images_per_s": round(steps * C * P / (ms / 1e3), 1), "ms_per_step": round(ms / steps, 3)}
+        samples["images"][name] = images[0, list(samples["channels"]), 0].cpu().numpy()
     for name, _ in FORMS[1:]:
         out[name]["vs_fp32"] = round(out[name]["images_per_s"] / out["fp32"]["images_per_s"], 4)
+    t = samples["t"]
+    samples["inputs"] = {"vis": d["vis"][t:t + 1].cpu().numpy(), "flags": d["flags"][t:t + 1].cpu().numpy(),
+                         "uvw_m": d["uvw_m"][t:t + 1].cpu().numpy(), "freq_hz": d["freq_hz"].cpu().numpy(),
+                         "grid_n": N, "pixel_scale": spec.pixel_scale}
     del d, images, ws
+    torch.cuda.empty_cache()
+    return out, samples
+
+
+# channels of the 4096^2 precision workload whose images are compared with the FP64 oracle
+PRECISION_SAMPLE_CHANNELS = (0, 127, 255)
+
+
+def precision_errors(samples):
+    """Per-image error of every FFT form against the FP64 oracle on the sampled 4096^2 images:
+    relative L2, peak-pixel relative error and the 6-sigma detections missing / spurious. Runs in
+    the CPU-baseline leg (it times the oracle on these images as well)."""
+    import numpy as np
+
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from image_checks import local_maxima, peak_error, recovery, rel_l2, robust_sigma
+
+    inp = samples["inputs"]
+    ch = list(samples["channels"])
+    t0 = time.perf_counter()
+    ref = oracle.image_batch(inp["vis"][:, ch], inp["flags"][:, ch], inp["uvw_m"], inp["freq_hz"][ch],
+                             inp["grid_n"], inp["pixel_scale"], 0, n_threads=oracle.max_threads())["images"]
+    dt = time.perf_counter() - t0
+    out = {"time_step": samples["t"], "channels": ch, "oracle_seconds": round(dt, 2),
+           "oracle_threads": oracle.max_threads()}
+    for name, imgs in samples["images"].items():
+        per = []
+        for j in range(len(ch)):
+            r = ref[0, j, 0]
+            missing, spurious = recovery(imgs[j], r)
+            per.append({"rel_l2": float(f"{rel_l2(imgs[j], r):.3e}"), "peak_err": float(f"{peak_error(imgs[j], r):.3e}"),
+                        "oracle_6sigma_maxima": len(local_maxima(r, 6.0 * robust_sigma(r))),
+                        "missing_6sigma": len(missing), "spurious_6sigma": len(spurious)})
+        out[name] = per
+        log(f"precision-4096 {name}: rel_l2 " + ", ".join(f"{p['rel_l2']:.2e}" for p in per) +
+            "; peak " + ", ".join(f"{p['peak_err']:.2e}" for p in per) +
+            f"; 6-sigma missing/spurious {sum(p['missing_6sigma'] for p in per)}/"
+            f"{sum(p['spurious_6sigma'] for p in per)}")
+    return out
+
+
+def bench_phase2(ctx, torch, blink, synth, steps, warmup):
+    """The Phase II shape: 144 tiles (10296 baselines), 2 pols, 3072 x 10 kHz channels from 185 MHz,
+    20 time steps of 1 ms, 2048^2 at 0.75 arcmin, uniform weighting. A step images one time step
+    (6144 images) in four calls of 768 channels into a ring of 1536 images."""
+    spec = synth.spec_phase2()
+    T, C, P, B, N = spec.T, spec.C, spec.P, spec.B, spec.grid_n
+    log(f"Phase II workload {spec.name}: T={T} C={C} P={P} B={B} N={N}, uniform")
+    d = synth.make_problem_device(spec, "cuda:0")
+    CH = 768
+    images = torch.empty((1, CH, P, N, N), dtype=torch.float32, device="cuda:0")
+    wsum = torch.empty((1, CH, P), dtype=torch.float64, device="cuda:0")
+    nout = torch.empty((1, CH), dtype=torch.int32, device="cuda:0")
+    ws = torch.empty(blink.image_batch_workspace_size(1, CH, P, B, N, 1), dtype=torch.uint8, device="cuda:0")
+
+    def step(i):
+        t = i % T
+        for c0 in range(0, C, CH):
+            ctx.blink_image_batch(d["vis"][t:t + 1, c0:c0 + CH], d["flags"][t:t + 1, c0:c0 + CH], d["uvw_m"][t:t + 1],
+                                  d["freq_hz"][c0:c0 + CH], N, spec.pixel_scale, 1, out=images, weight_sum=wsum,
+                                  n_out=nout, workspace=ws)
+    ms = timed(torch, step, steps, warmup)
+    n_img = steps * C * P
+    value = n_img / (ms / 1e3)
+    prof, _ = profiled(ctx, torch, step, 1)
+    kernels = kernel_table(prof, {"image": C * P, "pair": C}, kernel_unit_bytes(spec))
+    per_image = 12 * N * N + 8 * B + B // P
+    out = {"workload": "phase2-2048: 144 tiles (10296 cross baselines), 2 pols, 3072 x 10 kHz channels from 185 MHz, "
+                       "20 x 1 ms time steps, 2048^2 FP32 grid, 0.75 arcmin pixels, uniform weighting, 10% flags; "
+                       "one step = one time step = 6144 images in 4 calls of 768 channels",
+           "images_per_step": C * P, "steps": steps, "images_per_s": round(value, 1),
+           "ms_per_step": round(ms / steps, 3), "plan": ctx.get_plan(N, 1),
+           "path_roofline": {"bytes_per_image_model": per_image,
+                             "achieved_GB_s": round(value * per_image / 1e9, 1),
+                             "frac_hbm": round(value * per_image / 1e9 / HBM_PEAK_GBS, 4)},
+           "kernels": kernels}
+    log(f"Phase II: {value:.0f} images/s ({ms / steps:.2f} ms per time step), "
+        f"{value * per_image / 1e9:.0f} GB/s on the 12 N^2 + 9 B model")
+    del d, images, ws, wsum, nout
     torch.cuda.empty_cache()
     return out
 
@@ -390,6 +483,29 @@ def main():
     roof = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["achieved_GB_s"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": kernels[dom]["frac_hbm"],
             "traffic": counter_traffic("vcs1024_fp32", dom, plan)}
+    # The half spectra of one image group (group x 4 N^2 bytes) are written by the column launch and
+    # read by the row launch; when they fit the 256 MB last-level cache they are served from it, and
+    # the byte counters (which sit above that cache) count those hits as HBM traffic. The same steps
+    # with a group whose half spectra exceed the cache give the kernels' rates from DRAM.
+    h_group = plan["group"] * 4 * N * N
+    big = max(plan["group"], 1)
+    while big * 4 * N * N <= 1.5 * MALL_BYTES:
+        big += max(plan["group"], 1)
+    ctx.set_plan(N, 0, plan["col_strip"], plan["row_block"], big, col_loop=plan["col_loop"])
+    bprof, bms = profiled(ctx, torch, step, min(args.steps, 10))
+    ctx.set_plan(N, 0, plan["col_strip"], plan["row_block"], plan["group"], col_loop=plan["col_loop"])
+    bk = kernel_table(bprof, {"image": min(args.steps, 10) * C * P, "pair": min(args.steps, 10) * C}, ub)
+    roof["last_level_cache"] = {
+        "note": f"a group's half spectra ({plan['group']} images x {4 * N * N >> 20} MiB = {h_group >> 20} MiB) fit "
+                f"the {MALL_BYTES // 10**6} MB Infinity Cache between the column and the row launch; the byte "
+                f"counters count its hits, so this fraction includes reads served from that cache",
+        "group_beyond_cache": big,
+        "half_spectra_MiB": (big * 4 * N * N) >> 20,
+        "frac_hbm": {k: bk[k]["frac_hbm"] for k in ("grid_colfft", "row_fft") if k in bk},
+        "images_per_s": round(min(args.steps, 10) * C * P / (bms / 1e3), 1)}
+    log(f"groups of {big} (half spectra beyond the cache): row kernel at "
+        f"{bk.get('row_fft', {}).get('frac_hbm', 0):.3f} of HBM, column kernel at "
+        f"{bk.get('grid_colfft', {}).get('frac_hbm', 0):.3f}")
     per_image = 12 * N * N + 8 * B + B // P
     path = {"bytes_per_image_model": per_image,
             "achieved_GB_s": round(value * per_image / 1e9, 1),
@@ -397,6 +513,7 @@ def main():
             "kernel_timing_pass_ms": round(prof_ms, 3)}
 
     forms = None
+    precision_samples = None
     if not args.no_forms:
         # The split-precision matrix-core forms on the same workload and buffers (MFMA vs FP32).
         forms = {"vcs-1024": {"fp32": {"images_per_s": round(value, 1)}}}
@@ -471,14 +588,19 @@ def main():
             f"({moved / (ms / 1e3) / 1e9:.0f} GB/s)")
         forms["correlator"] = bench_correlator(ctx, torch, 5, 2)
         forms["dedispersion"] = bench_dedispersion(ctx, torch, blink, 3, 1)
-        forms["precision-4096"] = bench_precision_workload(ctx, torch, blink, synth, 3, 1)
+        forms["precision-4096"], precision_samples = bench_precision_workload(ctx, torch, blink, synth, 3, 1)
         forms["uneven"] = bench_uneven(ctx, torch, blink, synth, 3)
+        forms["phase2-2048"] = bench_phase2(ctx, torch, blink, synth, 2, 1)
 
     cpu = None
     if not args.no_cpu_baseline:
         log(f"CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         cpu = cpu_baseline(d, spec, args.cpu_seconds)
         log(f"CPU oracle: {cpu['value']} images/s on {cpu['cores']} threads")
+        if forms is not None:
+            # the oracle on the sampled 4096^2 images: per-image errors of every FFT form
+            log("FP64 oracle on the sampled 4096^2 precision images")
+            forms["precision-4096"]["errors_vs_fp64_oracle"] = precision_errors(precision_samples)
 
     out = {
         "metric": METRIC,
