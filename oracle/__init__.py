@@ -56,6 +56,8 @@ def load(path: str):
     L.blink_ref_image_batch_c128.restype = i32
     L.blink_ref_image_batch_c128.argtypes = [P, P, P, P, i32, i32, i32, i32, i32, f64, i32, i32,
                                              P, P, P, P, P, i32]
+    L.blink_ref_dft.restype = i32
+    L.blink_ref_dft.argtypes = [P, P, P, i32, i32, f64, i32, f64, i32, i32, P, P, P]
     L.blink_ref_correct_vis.restype = i32
     L.blink_ref_correct_vis.argtypes = [P, P, P, i32, i32, i32, i32, P, i32, f64, f64, P]
     L.blink_ref_correlate.restype = i32
@@ -133,6 +135,27 @@ class Oracle:
             raise ValueError(f"blink_ref_grid failed with code {rc}")
         return {"grid": g, "counts": counts, "cell_idx": cell, "weight_sum": W.value,
                 "n_out": nout.value}
+
+    def dft(self, vis, flags, uvw, freq_hz, grid_n, pixel_scale, snap=False, shift=True):
+        """Direct transform of one (t,c): vis complex [P][B] (or [B]), flags [B] or None, uvw [B][3];
+        natural weighting; nearest cells with snap, exact positions without. Returns
+        dict(images float64 [P][N][N], weight_sum float, n_out int)."""
+        vis = np.asarray(vis)
+        if vis.ndim == 1:
+            vis = vis[None]
+        P, B = vis.shape
+        v = _c(vis, np.complex64)
+        f = None if flags is None else _c(flags, np.uint8)
+        u = _c(uvw, np.float64)
+        N = int(grid_n)
+        img = np.empty((P, N, N), dtype=np.float64)
+        W = ctypes.c_double()
+        nout = ctypes.c_int32()
+        rc = self.L.blink_ref_dft(_ptr(v), _ptr(f), _ptr(u), P, B, float(freq_hz), N, float(pixel_scale),
+                                 int(bool(snap)), int(bool(shift)), _ptr(img), ctypes.byref(W), ctypes.byref(nout))
+        if rc != 0:
+            raise ValueError(f"blink_ref_dft failed with code {rc}")
+        return {"images": img, "weight_sum": W.value, "n_out": nout.value}
 
     def ifft1d(self, x):
         a = _c(x, np.complex128).copy()
@@ -333,6 +356,10 @@ def cells_per_metre(*a, **k):
 
 def grid(*a, **k):
     return default().grid(*a, **k)
+
+
+def dft(*a, **k):
+    return default().dft(*a, **k)
 
 
 def ifft1d(*a, **k):

@@ -118,6 +118,57 @@ int blink_ref_grid(const float *vis, const uint8_t *flags, const double *uvw, in
                     cell_idx, weight_sum, n_out);
 }
 
+/* Section 4: the dirty image as the direct inverse transform of the samples, one baseline at a
+ * time; the kept set and W follow the nearest-cell rules of grid_one. */
+int blink_ref_dft(const float *vis, const uint8_t *flags, const double *uvw, int P, int B,
+                  double freq_hz, int grid_n, double pixel_scale, int snap, int shift,
+                  double *image, double *weight_sum, int32_t *n_out)
+{
+    if (!is_pow2(grid_n) || P < 1 || B < 0 || (B > 0 && (!vis || !uvw)) || !image || !weight_sum || !n_out)
+        return 1;
+    const int N = grid_n;
+    const size_t NN = (size_t)N * N;
+    memset(image, 0, sizeof(double) * NN * (size_t)P);
+    const double k = blink_ref_cells_per_metre(freq_hz, N, pixel_scale);
+    const double half = (double)(N / 2);
+    const double two_pi = 2.0 * M_PI;
+    int64_t kept = 0;
+    int32_t outside = 0;
+    for (int b = 0; b < B; ++b) {
+        if (flags && flags[b])
+            continue;
+        double xu = uvw[3 * (size_t)b + 0] * k;
+        double xv = uvw[3 * (size_t)b + 1] * k;
+        double ru = nearbyint(xu), rv = nearbyint(xv);
+        if (!(fabs(ru) < half) || !(fabs(rv) < half)) {     /* NaN is outside too */
+            ++outside;
+            continue;
+        }
+        ++kept;
+        const double a = snap ? ru : xu;
+        const double c = snap ? rv : xv;
+        for (int p = 0; p < P; ++p) {
+            const double re = (double)vis[2 * ((size_t)p * B + b)];
+            const double im = (double)vis[2 * ((size_t)p * B + b) + 1];
+            double *img = image + NN * (size_t)p;
+            for (int y = 0; y < N; ++y) {
+                const double Y = shift ? (double)(y - N / 2) : (double)y;
+                for (int x = 0; x < N; ++x) {
+                    const double X = shift ? (double)(x - N / 2) : (double)x;
+                    const double phase = two_pi * (a * X + c * Y) / (double)N;
+                    img[(size_t)y * N + x] += 2.0 * (re * cos(phase) - im * sin(phase));
+                }
+            }
+        }
+    }
+    const double W = (double)(2 * kept);    /* the kept visibilities and their mirrors */
+    for (size_t i = 0; i < NN * (size_t)P; ++i)
+        image[i] = W > 0.0 ? image[i] / W : 0.0;
+    *weight_sum = W;
+    *n_out = outside;
+    return 0;
+}
+
 /* Textbook iterative radix-2 decimation-in-time FFT with the + sign of the inverse transform
  * (the image side of Eq. 4's exp(-i2pi(ul+vm))). Twiddles cos/sin(2 pi j / n) from libm. */
 int blink_ref_ifft1d(double *a, int n)

@@ -82,6 +82,19 @@ int blink_ref_image_batch_c128(const double *vis, const uint8_t *flags, const do
                                double *weight_sum, int32_t *n_out, int32_t *cell_idx,
                                int32_t *counts, int n_threads);
 
+/* Direct Fourier transform of one (time, channel): the dirty image of Section 4 (Eq. 4 inverted on
+ * the sampled (u, v), Eq. 5) summed baseline by baseline, with no grid and no FFT. Keep rule and
+ * natural weighting as in blink_ref_grid (W = 2 x kept); each kept visibility and its Hermitian
+ * mirror contribute
+ *   I[p][y][x] += 2 Re( V[p][b] exp(+2 pi i (a_b X + c_b Y) / N) ) / W,
+ * X = x - N/2, Y = y - N/2 when shifted (X = x, Y = y otherwise), where (a_b, c_b) is the nearest
+ * cell (nearbyint(u k), nearbyint(v k)) when snap != 0 (the gridded image's value, reached by a
+ * different route) and the exact position (u k, v k) in cells when snap == 0 (the ungridded
+ * transform). vis complex64 [P][B]; image out double [P][N][N]; W = 0 gives a zero image. */
+int blink_ref_dft(const float *vis, const uint8_t *flags, const double *uvw, int P, int B,
+                  double freq_hz, int grid_n, double pixel_scale, int snap, int shift,
+                  double *image, double *weight_sum, int32_t *n_out);
+
 /* Visibility corrections before gridding (Section 6.2.3): for baseline b = (i, j), i > j,
  * b = i (i - 1) / 2 + j, and channel c with frequency f,
  *   V' = J[c][p][i] V conj(J[c][p][j]) exp(+2 pi i (f/c) (u l0 + v m0 + w (n0 - 1))),

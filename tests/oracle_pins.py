@@ -252,6 +252,41 @@ def pin_ungridded_bound(O):
     assert np.abs(img - Id).max() < 0.5 * bound.max()
 
 
+def pin_direct_dft(O):
+    """The oracle's direct transform (a sum over baselines, no grid, no FFT): at the snapped cells it
+    equals the gridded image (grid + FFT + shift + 1/W) to rounding; at the exact positions it equals
+    it at the phase centre and stays within the half-cell bound elsewhere; a point source placed on
+    a pixel centre images to exactly its flux there when nothing is snapped."""
+    for seed, N, shift in ((11, 32, True), (12, 64, True), (13, 32, False)):
+        vis, flags, uvw, f, N, dl = small_problem(seed, B=200, N=N, P=2, extent=0.6)
+        res = O.image_batch(vis[None, None], flags[None, None], uvw[None], np.array([f]), N, dl, shift=shift)
+        d = O.dft(vis, flags, uvw, f, N, dl, snap=True, shift=shift)
+        assert d["weight_sum"] == res["weight_sum"][0, 0, 0] and d["n_out"] == res["n_out"][0, 0]
+        for p in range(2):
+            img = res["images"][0, 0, p]
+            assert np.abs(d["images"][p] - img).max() <= 1e-12 * np.abs(img).max(), (seed, p)
+    vis, flags, uvw, f, N, dl = small_problem(14, B=250, N=64, extent=0.4)
+    img = O.image_batch(vis[None, None], flags[None, None], uvw[None], np.array([f]), N, dl)["images"][0, 0, 0]
+    d = O.dft(vis, flags, uvw, f, N, dl, snap=False)
+    Id, W = d["images"][0], d["weight_sum"]
+    k = (f / C_LIGHT) * (N * dl)
+    keep = (flags == 0) & (np.abs(np.rint(uvw[:, 0] * k)) < N // 2) & (np.abs(np.rint(uvw[:, 1] * k)) < N // 2)
+    X = np.abs(np.arange(N) - N // 2)
+    bound = (2.0 / W) * np.abs(vis[0][keep]).astype(np.float64).sum() * np.pi * (X[None, :] + X[:, None]) / N
+    c = N // 2
+    assert abs(img[c, c] - Id[c, c]) <= 1e-12 * abs(Id[c, c])
+    assert np.all(np.abs(img - Id) <= bound + 1e-12)
+    assert np.abs(img - Id).max() > 1e-6          # snapping is visible away from the centre
+    # a 3 Jy source at (l, m) = (5 dl, -3 dl), unsnapped: exactly 3 at pixel (N/2 + 5, N/2 - 3)
+    l0, m0, S = 5 * dl, -3 * dl, 3.0
+    src = (S * np.exp(-2j * np.pi * (uvw[:, 0] * l0 + uvw[:, 1] * m0) * f / C_LIGHT)).astype(np.complex64)
+    src64 = S * np.exp(-2j * np.pi * (uvw[:, 0] * l0 + uvw[:, 1] * m0) * f / C_LIGHT)
+    d = O.dft(src, flags, uvw, f, N, dl, snap=False)["images"][0]
+    err = (2.0 / W) * np.abs(src.astype(np.complex128) - src64)[keep].sum()   # complex64 rounding of V
+    assert abs(d[c - 3, c + 5] - S) <= err + 1e-12
+    assert np.unravel_index(np.argmax(d), d.shape) == (c - 3, c + 5)
+
+
 def pin_point_source_centre(O):
     """V = 1 (a unit source at the phase centre): the dirty beam, 1 at the centre, <= 1, even."""
     vis, flags, uvw, f, N, dl = small_problem(8, B=300, N=64)
@@ -636,7 +671,7 @@ def pin_dedisperse_recovers_pulse(O):
         assert out[k].max() < 3.0
 
 
-EXTRA_PINS = [pin_image_average, pin_es_kernel_values, pin_es_transform, pin_conv_width1_is_nearest_cell,
+EXTRA_PINS = [pin_direct_dft, pin_image_average, pin_es_kernel_values, pin_es_transform, pin_conv_width1_is_nearest_cell,
               pin_conv_hermitian, pin_conv_matches_direct_transform, pin_conv_batch_consistency,
               pin_corrections_identity, pin_corrections_undo_gains, pin_corrections_phase_centre,
               pin_correlate_matrix_product, pin_correlate_quarter_turns, pin_correlate_averaging_groups,

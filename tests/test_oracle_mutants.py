@@ -31,6 +31,12 @@ MUTANTS = {
     "mirror_cell_wrong": ("size_t c2 = (size_t)mod_n(-iv, N) * N + mod_n(-iu, N);",
                           "size_t c2 = (size_t)mod_n(-iv, N) * N + mod_n(iu, N);"),
     "butterfly_sign": ("y[0] = x[0] - tr; y[1] = x[1] - ti;", "y[0] = x[0] + tr; y[1] = x[1] - ti;"),
+    # direct transform
+    "dft_phase_sign": ("img[(size_t)y * N + x] += 2.0 * (re * cos(phase) - im * sin(phase));",
+                       "img[(size_t)y * N + x] += 2.0 * (re * cos(phase) + im * sin(phase));"),
+    "dft_axes_swapped": ("const double phase = two_pi * (a * X + c * Y) / (double)N;",
+                         "const double phase = two_pi * (a * Y + c * X) / (double)N;"),
+    "dft_snap_ignored": ("const double a = snap ? ru : xu;", "const double a = xu;"),
     # convolutional gridding
     "conv_mirror_not_conjugated": ("spread(g, N, -xu, -xv, width, beta, re, -im);",
                                    "spread(g, N, -xu, -xv, width, beta, re, im);"),
