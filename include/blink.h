@@ -113,6 +113,34 @@ blink_status blink_ifft2d_workspace_size(int n_img, int grid_n, int precision, s
 blink_status blink_image_batch_workspace_size(int T, int C, int P, int B, int grid_n,
                                               int weighting, int precision, size_t *bytes);
 
+/* One problem of one entry point, for the single workspace query blink_workspace_size. The
+ * fields an entry point does not take are ignored. */
+enum {
+    BLINK_ENTRY_GRID = 0,                  /* T, C, B, grid_n */
+    BLINK_ENTRY_IFFT2D = 1,                /* n_img, grid_n, precision */
+    BLINK_ENTRY_IMAGE_BATCH = 2,           /* T, C, P, B, grid_n, weighting, precision */
+    BLINK_ENTRY_IMAGE_BATCH_CORRECTED = 3, /* T, C, P, B, grid_n, weighting, precision */
+    BLINK_ENTRY_IMAGE_BATCH_CONV = 4,      /* T, C, P, B, grid_n, kernel_width, precision */
+    BLINK_ENTRY_IMAGE_BATCH_DESC = 5,      /* n_img, max_baselines, grid_n (the largest), workgroups */
+    BLINK_ENTRY_DEDISPERSE = 6             /* C, n_dm */
+};
+typedef struct {
+    int entry;                 /* BLINK_ENTRY_* */
+    int T, C, P, B;            /* time steps, channels, polarisations, baselines */
+    int n_img;                 /* grids (ifft2d) or described images (desc) */
+    int grid_n;                /* N; for desc the largest N */
+    int weighting, precision;  /* BLINK_WEIGHT_*, BLINK_PREC_* */
+    int kernel_width;          /* conv: support W in cells */
+    int max_baselines;         /* desc: most visibilities of one image */
+    int workgroups;            /* desc: persistent workgroups (0 = the query's default, 512) */
+    int n_dm;                  /* dedisperse: trial dispersion measures */
+} blink_problem;
+
+/* Workspace bytes of the entry point p->entry for problem *p: the same value as that entry
+ * point's *_workspace_size query. ctx may be NULL. BLINK_ERR_ARG for a NULL p or bytes or an
+ * unknown entry, otherwise the per-entry query's status. */
+blink_status blink_workspace_size(blink_ctx ctx, const blink_problem *p, size_t *bytes);
+
 /* Gridding only (Section 6.2.4; Section 4 Eq. 5). Places every unflagged, in-grid visibility
  * and its Hermitian mirror on the nearest cell of an N x N grid per (t, c, p).
  *   grids      out [T][C][P][N][N], natural: cell sums; uniform: cell means

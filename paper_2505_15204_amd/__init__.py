@@ -47,6 +47,16 @@ class BlinkError(RuntimeError):
         self.status = status
 
 
+class Problem(ctypes.Structure):
+    """blink_problem: one entry point's problem for the single workspace query."""
+    _fields_ = [(n, ctypes.c_int) for n in ("entry", "T", "C", "P", "B", "n_img", "grid_n", "weighting", "precision",
+                                            "kernel_width", "max_baselines", "workgroups", "n_dm")]
+
+
+ENTRY_GRID, ENTRY_IFFT2D, ENTRY_IMAGE_BATCH, ENTRY_IMAGE_BATCH_CORRECTED, ENTRY_IMAGE_BATCH_CONV, \
+    ENTRY_IMAGE_BATCH_DESC, ENTRY_DEDISPERSE = range(7)
+
+
 class Corrections(ctypes.Structure):
     """blink_corrections: per-antenna factors (device pointer or None), antennas, phase centre."""
     _fields_ = [("gains", ctypes.c_void_p), ("n_ant", ctypes.c_int), ("l0", ctypes.c_double),
@@ -79,6 +89,8 @@ def lib() -> ctypes.CDLL:
     L.blink_last_error.restype = ctypes.c_char_p
     L.blink_last_error.argtypes = [P]
     L.blink_grid_workspace_size.restype = i32
+    L.blink_workspace_size.restype = i32
+    L.blink_workspace_size.argtypes = [P, ctypes.POINTER(Problem), ctypes.POINTER(sz)]
     L.blink_grid_workspace_size.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz)]
     L.blink_ifft2d_workspace_size.restype = i32
     L.blink_ifft2d_workspace_size.argtypes = [i32, i32, i32, ctypes.POINTER(sz)]
@@ -156,6 +168,14 @@ def _check(st: int, ctx=None, what: str = ""):
     if st != BLINK_OK:
         detail = lib().blink_last_error(ctx).decode() if ctx else ""
         raise BlinkError(st, f"{what}: {status_string(st)}" + (f" ({detail})" if detail else ""))
+
+
+def workspace_size(entry: int, **fields) -> int:
+    """Workspace bytes of an entry point (ENTRY_*) for the problem given by blink_problem's fields."""
+    p = Problem(entry=entry, **fields)
+    n = ctypes.c_size_t()
+    _check(lib().blink_workspace_size(None, ctypes.byref(p), ctypes.byref(n)), None, what="blink_workspace_size")
+    return n.value
 
 
 def grid_workspace_size(T: int, C: int, B: int, grid_n: int) -> int:

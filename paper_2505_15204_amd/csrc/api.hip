@@ -413,6 +413,27 @@ blink_status blink_grid_workspace_size(int T, int C, int B, int grid_n, size_t* 
   return BLINK_OK;
 }
 
+blink_status blink_workspace_size(blink_ctx, const blink_problem* p, size_t* bytes) {
+  if (!p || !bytes) return BLINK_ERR_ARG;
+  switch (p->entry) {
+    case BLINK_ENTRY_GRID: return blink_grid_workspace_size(p->T, p->C, p->B, p->grid_n, bytes);
+    case BLINK_ENTRY_IFFT2D: return blink_ifft2d_workspace_size(p->n_img, p->grid_n, p->precision, bytes);
+    case BLINK_ENTRY_IMAGE_BATCH:
+      return blink_image_batch_workspace_size(p->T, p->C, p->P, p->B, p->grid_n, p->weighting, p->precision, bytes);
+    case BLINK_ENTRY_IMAGE_BATCH_CORRECTED:
+      return blink_image_batch_corrected_workspace_size(p->T, p->C, p->P, p->B, p->grid_n, p->weighting,
+                                                        p->precision, bytes);
+    case BLINK_ENTRY_IMAGE_BATCH_CONV:
+      return blink_image_batch_conv_workspace_size(p->T, p->C, p->P, p->B, p->grid_n, p->kernel_width,
+                                                   p->precision, bytes);
+    case BLINK_ENTRY_IMAGE_BATCH_DESC:
+      return blink_desc_workspace_size(p->n_img, p->max_baselines, p->grid_n, p->workgroups > 0 ? p->workgroups : 512,
+                                       bytes);
+    case BLINK_ENTRY_DEDISPERSE: return blink_dedisperse_workspace_size(p->C, p->n_dm, bytes);
+    default: return BLINK_ERR_ARG;
+  }
+}
+
 blink_status blink_ifft2d_workspace_size(int n_img, int grid_n, int precision, size_t* bytes) {
   if (!bytes || n_img < 0) return BLINK_ERR_ARG;
   if (!valid_precision(precision)) return BLINK_ERR_ARG;

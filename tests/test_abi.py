@@ -91,6 +91,30 @@ def test_workspace_sizes(L):
         blink.image_batch_workspace_size(1, 1, 1, 10, 64, precision=5)
 
 
+def test_single_workspace_query_matches_each_entry(L):
+    assert blink.workspace_size(blink.ENTRY_GRID, T=2, C=3, B=100, grid_n=64) == blink.grid_workspace_size(2, 3, 100, 64)
+    assert blink.workspace_size(blink.ENTRY_IFFT2D, n_img=5, grid_n=256, precision=1) == \
+        blink.ifft2d_workspace_size(5, 256, 1)
+    for w in (0, 1):
+        for prec in (0, 2):
+            kw = dict(T=1, C=4, P=2, B=8128, grid_n=1024, weighting=w, precision=prec)
+            assert blink.workspace_size(blink.ENTRY_IMAGE_BATCH, **kw) == \
+                blink.image_batch_workspace_size(1, 4, 2, 8128, 1024, w, prec)
+            assert blink.workspace_size(blink.ENTRY_IMAGE_BATCH_CORRECTED, **kw) == \
+                blink.image_batch_corrected_workspace_size(1, 4, 2, 8128, 1024, w, prec)
+    assert blink.workspace_size(blink.ENTRY_IMAGE_BATCH_CONV, T=1, C=2, P=2, B=8128, grid_n=1024, kernel_width=8) == \
+        blink.image_batch_conv_workspace_size(1, 2, 2, 8128, 1024, 8)
+    assert blink.workspace_size(blink.ENTRY_IMAGE_BATCH_DESC, n_img=10, max_baselines=100, grid_n=256,
+                                workgroups=4) == blink.desc_workspace_size(10, 100, 256, 4)
+    assert blink.workspace_size(blink.ENTRY_DEDISPERSE, C=768, n_dm=4) == blink.dedisperse_workspace_size(768, 4)
+    with pytest.raises(blink.BlinkError) as ei:
+        blink.workspace_size(99, T=1)
+    assert ei.value.status == blink.BLINK_ERR_ARG
+    with pytest.raises(blink.BlinkError) as ei:
+        blink.workspace_size(blink.ENTRY_IMAGE_BATCH, T=1, C=1, P=1, B=10, grid_n=96)
+    assert ei.value.status == blink.BLINK_ERR_SIZE
+
+
 def test_desc_workspace_and_validation(L):
     s = blink.desc_workspace_size(10, 100, 256, 4)
     assert s >= 4 * 2 * 100 * 8 + 4 * 256 * 128 * 8
