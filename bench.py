@@ -395,6 +395,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the split-precision and uneven-batch measurements beside the headline")
     ap.add_argument("--form-steps", type=int, default=20, help="steps per split-precision form measurement")
+    ap.add_argument("--forms", default="all",
+                    help="comma-separated subset of the forms measured beside the headline: split, conv, "
+                         "corrected, average, correlator, dedispersion, precision, uneven, phase2 (default all)")
     ap.add_argument("--only-correlator", action="store_true",
                     help="only measure the correlator form (for profiling it alone); prints its JSON")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -514,90 +517,104 @@ def main():
 
     forms = None
     precision_samples = None
+    known = ("split", "conv", "corrected", "average", "correlator", "dedispersion", "precision", "uneven", "phase2")
+    want = set(known) if args.forms == "all" else {f.strip() for f in args.forms.split(",") if f.strip()}
+    if want - set(known):
+        print(f"unknown forms {sorted(want - set(known))}; known: {', '.join(known)}", file=sys.stderr)
+        sys.exit(2)
     if not args.no_forms:
-        # The split-precision matrix-core forms on the same workload and buffers (MFMA vs FP32).
         forms = {"vcs-1024": {"fp32": {"images_per_s": round(value, 1)}}}
         fs = min(args.form_steps, T)
-        for name, prec in FORMS[1:]:
-            def fstep(i, prec=prec):
+        if "split" in want:
+            # The split-precision matrix-core forms on the same workload and buffers (MFMA vs FP32).
+            for name, prec in FORMS[1:]:
+                def fstep(i, prec=prec):
+                    t = i % T
+                    ctx.blink_image_batch(d["vis"][t:t + 1], d["flags"][t:t + 1], d["uvw_m"][t:t + 1], d["freq_hz"], N,
+                                          spec.pixel_scale, 0, precision=prec, out=images, weight_sum=wsum, n_out=nout,
+                                          workspace=ws)
+                ms = timed(torch, fstep, fs, 2)
+                fprof, _ = profiled(ctx, torch, fstep, fs)
+                fk = kernel_table(fprof, {"image": fs * C * P, "pair": fs * C}, ub)
+                v = fs * C * P / (ms / 1e3)
+                forms["vcs-1024"][name] = {"images_per_s": round(v, 1), "vs_fp32": round(v / value, 4),
+                                           "plan": ctx.get_plan(N, 0, prec),
+                                           "kernels": {k: fk[k] for k in ("grid_colfft", "row_fft") if k in fk}}
+                log(f"{name}: {v:.0f} images/s ({v / value:.3f} x FP32)")
+        if "conv" in want:
+            # Convolutional gridding (W = 8, beta = 18.4) on the same workload, FP32.
+            cws = torch.empty(blink.image_batch_conv_workspace_size(1, C, P, B, N, 8), dtype=torch.uint8, device="cuda:0")
+
+            def cstep(i):
                 t = i % T
-                ctx.blink_image_batch(d["vis"][t:t + 1], d["flags"][t:t + 1], d["uvw_m"][t:t + 1], d["freq_hz"], N,
-                                      spec.pixel_scale, 0, precision=prec, out=images, weight_sum=wsum, n_out=nout,
-                                      workspace=ws)
-            ms = timed(torch, fstep, fs, 2)
-            fprof, _ = profiled(ctx, torch, fstep, fs)
-            fk = kernel_table(fprof, {"image": fs * C * P, "pair": fs * C}, ub)
+                ctx.blink_image_batch_conv(d["vis"][t:t + 1], d["flags"][t:t + 1], d["uvw_m"][t:t + 1], d["freq_hz"], N,
+                                           spec.pixel_scale, 8, 18.4, out=images, weight_sum=wsum, n_out=nout,
+                                           workspace=cws)
+            ms = timed(torch, cstep, fs, 2)
+            cprof, _ = profiled(ctx, torch, cstep, fs)
+            ck = kernel_table(cprof, {"image": fs * C * P, "pair": fs * C}, ub)
             v = fs * C * P / (ms / 1e3)
-            forms["vcs-1024"][name] = {"images_per_s": round(v, 1), "vs_fp32": round(v / value, 4),
-                                       "plan": ctx.get_plan(N, 0, prec),
-                                       "kernels": {k: fk[k] for k in ("grid_colfft", "row_fft") if k in fk}}
-            log(f"{name}: {v:.0f} images/s ({v / value:.3f} x FP32)")
-        # Convolutional gridding (W = 8, beta = 18.4) on the same workload, FP32.
-        cws = torch.empty(blink.image_batch_conv_workspace_size(1, C, P, B, N, 8), dtype=torch.uint8, device="cuda:0")
+            forms["vcs-1024"]["conv_w8_fp32"] = {"images_per_s": round(v, 1), "vs_fp32": round(v / value, 4),
+                                                 "kernel": "exponential of semicircle, W = 8, beta = 18.4",
+                                                 "kernels": {k: ck[k] for k in ("bin", "grid_colfft", "row_fft") if k in ck}}
+            log(f"conv W=8: {v:.0f} images/s ({v / value:.3f} x nearest-cell FP32)")
+            del cws
+        if "corrected" in want:
+            # Pre-gridding corrections (per-antenna solutions + phase-centre rotation) on the same workload.
+            gen = torch.Generator(device="cuda:0")
+            gen.manual_seed(20)
+            amp = 0.5 + torch.rand((C, P, spec.n_tiles), generator=gen, device="cuda:0", dtype=torch.float64)
+            pha = 2 * torch.pi * torch.rand((C, P, spec.n_tiles), generator=gen, device="cuda:0", dtype=torch.float64)
+            gains = torch.polar(amp, pha).to(torch.complex64)
+            xws = torch.empty(blink.image_batch_corrected_workspace_size(1, C, P, B, N), dtype=torch.uint8,
+                              device="cuda:0")
 
-        def cstep(i):
-            t = i % T
-            ctx.blink_image_batch_conv(d["vis"][t:t + 1], d["flags"][t:t + 1], d["uvw_m"][t:t + 1], d["freq_hz"], N,
-                                       spec.pixel_scale, 8, 18.4, out=images, weight_sum=wsum, n_out=nout,
-                                       workspace=cws)
-        ms = timed(torch, cstep, fs, 2)
-        cprof, _ = profiled(ctx, torch, cstep, fs)
-        ck = kernel_table(cprof, {"image": fs * C * P, "pair": fs * C}, ub)
-        v = fs * C * P / (ms / 1e3)
-        forms["vcs-1024"]["conv_w8_fp32"] = {"images_per_s": round(v, 1), "vs_fp32": round(v / value, 4),
-                                             "kernel": "exponential of semicircle, W = 8, beta = 18.4",
-                                             "kernels": {k: ck[k] for k in ("bin", "grid_colfft", "row_fft") if k in ck}}
-        log(f"conv W=8: {v:.0f} images/s ({v / value:.3f} x nearest-cell FP32)")
-        del cws
-        # Pre-gridding corrections (per-antenna solutions + phase-centre rotation) on the same workload.
-        gen = torch.Generator(device="cuda:0")
-        gen.manual_seed(20)
-        amp = 0.5 + torch.rand((C, P, spec.n_tiles), generator=gen, device="cuda:0", dtype=torch.float64)
-        pha = 2 * torch.pi * torch.rand((C, P, spec.n_tiles), generator=gen, device="cuda:0", dtype=torch.float64)
-        gains = torch.polar(amp, pha).to(torch.complex64)
-        xws = torch.empty(blink.image_batch_corrected_workspace_size(1, C, P, B, N), dtype=torch.uint8,
-                          device="cuda:0")
-
-        def xstep(i):
-            t = i % T
-            ctx.blink_image_batch_corrected(d["vis"][t:t + 1], d["flags"][t:t + 1], d["uvw_m"][t:t + 1],
-                                            d["freq_hz"], N, spec.pixel_scale, 0, gains=gains, l0=0.02, m0=-0.015,
-                                            out=images, weight_sum=wsum, n_out=nout, workspace=xws)
-        ms = timed(torch, xstep, fs, 2)
-        xprof, _ = profiled(ctx, torch, xstep, fs)
-        xub = dict(ub, correct=("pair", P * B * 16 + 24 * B // C + P * spec.n_tiles * 8))
-        xk = kernel_table(xprof, {"image": fs * C * P, "pair": fs * C}, xub)
-        v = fs * C * P / (ms / 1e3)
-        forms["vcs-1024"]["corrected_fp32"] = {
-            "images_per_s": round(v, 1), "vs_fp32": round(v / value, 4),
-            "corrections": "per-antenna complex solutions [C][P][128] and phase-centre rotation (l0, m0) = "
-                           "(0.02, -0.015) with the w term",
-            "kernels": {k: xk[k] for k in ("correct", "grid_colfft", "row_fft") if k in xk}}
-        log(f"corrected: {v:.0f} images/s ({v / value:.3f} x FP32)")
-        del xws, gains
-        # Stokes I + band average of one time step's images (1536 images -> 1), HBM-bound.
-        avg_out = torch.empty((1, 1, 1, N, N), dtype=torch.float32, device="cuda:0")
-        ms = timed(torch, lambda i: ctx.blink_image_average(images, blink.AVG_CHANNEL | blink.AVG_POL, out=avg_out),
-                   10, 2) / 10
-        moved = (C * P + 1) * 4 * N * N
-        forms["vcs-1024"]["stokes_i_band_average"] = {
-            "images_in": C * P, "ms": round(ms, 4), "bytes": moved,
-            "achieved_GB_s": round(moved / (ms / 1e3) / 1e9, 1),
-            "frac_hbm": round(moved / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
-        log(f"Stokes I + band average of {C * P} images: {ms:.3f} ms "
-            f"({moved / (ms / 1e3) / 1e9:.0f} GB/s)")
-        forms["correlator"] = bench_correlator(ctx, torch, 5, 2)
-        forms["dedispersion"] = bench_dedispersion(ctx, torch, blink, 3, 1)
-        forms["precision-4096"], precision_samples = bench_precision_workload(ctx, torch, blink, synth, 3, 1)
-        forms["uneven"] = bench_uneven(ctx, torch, blink, synth, 3)
-        forms["phase2-2048"] = bench_phase2(ctx, torch, blink, synth, 2, 1)
+            def xstep(i):
+                t = i % T
+                ctx.blink_image_batch_corrected(d["vis"][t:t + 1], d["flags"][t:t + 1], d["uvw_m"][t:t + 1],
+                                                d["freq_hz"], N, spec.pixel_scale, 0, gains=gains, l0=0.02, m0=-0.015,
+                                                out=images, weight_sum=wsum, n_out=nout, workspace=xws)
+            ms = timed(torch, xstep, fs, 2)
+            xprof, _ = profiled(ctx, torch, xstep, fs)
+            xub = dict(ub, correct=("pair", P * B * 16 + 24 * B // C + P * spec.n_tiles * 8))
+            xk = kernel_table(xprof, {"image": fs * C * P, "pair": fs * C}, xub)
+            v = fs * C * P / (ms / 1e3)
+            forms["vcs-1024"]["corrected_fp32"] = {
+                "images_per_s": round(v, 1), "vs_fp32": round(v / value, 4),
+                "corrections": "per-antenna complex solutions [C][P][128] and phase-centre rotation (l0, m0) = "
+                               "(0.02, -0.015) with the w term",
+                "kernels": {k: xk[k] for k in ("correct", "grid_colfft", "row_fft") if k in xk}}
+            log(f"corrected: {v:.0f} images/s ({v / value:.3f} x FP32)")
+            del xws, gains
+        if "average" in want:
+            # Stokes I + band average of one time step's images (1536 images -> 1), HBM-bound.
+            avg_out = torch.empty((1, 1, 1, N, N), dtype=torch.float32, device="cuda:0")
+            ms = timed(torch, lambda i: ctx.blink_image_average(images, blink.AVG_CHANNEL | blink.AVG_POL, out=avg_out),
+                       10, 2) / 10
+            moved = (C * P + 1) * 4 * N * N
+            forms["vcs-1024"]["stokes_i_band_average"] = {
+                "images_in": C * P, "ms": round(ms, 4), "bytes": moved,
+                "achieved_GB_s": round(moved / (ms / 1e3) / 1e9, 1),
+                "frac_hbm": round(moved / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+            log(f"Stokes I + band average of {C * P} images: {ms:.3f} ms "
+                f"({moved / (ms / 1e3) / 1e9:.0f} GB/s)")
+        if "correlator" in want:
+            forms["correlator"] = bench_correlator(ctx, torch, 5, 2)
+        if "dedispersion" in want:
+            forms["dedispersion"] = bench_dedispersion(ctx, torch, blink, 3, 1)
+        if "precision" in want:
+            forms["precision-4096"], precision_samples = bench_precision_workload(ctx, torch, blink, synth, 3, 1)
+        if "uneven" in want:
+            forms["uneven"] = bench_uneven(ctx, torch, blink, synth, 3)
+        if "phase2" in want:
+            forms["phase2-2048"] = bench_phase2(ctx, torch, blink, synth, 2, 1)
 
     cpu = None
     if not args.no_cpu_baseline:
         log(f"CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         cpu = cpu_baseline(d, spec, args.cpu_seconds)
         log(f"CPU oracle: {cpu['value']} images/s on {cpu['cores']} threads")
-        if forms is not None:
+        if precision_samples is not None:
             # the oracle on the sampled 4096^2 images: per-image errors of every FFT form
             log("FP64 oracle on the sampled 4096^2 precision images")
             forms["precision-4096"]["errors_vs_fp64_oracle"] = precision_errors(precision_samples)
