@@ -246,12 +246,16 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
   const int lane = threadIdx.x & 63, n = lane & 31, g = lane >> 5, w = threadIdx.x >> 6;
   const int total = ntrans * NB;
 
-  // The butterfly of batch h of this lane, and whether it exists.
+  // The butterfly of batch h of this lane, and whether it exists. A lane without one gets
+  // butterfly 0 (which always exists), so its loads need no branch (their values are discarded):
+  // loads under a branch would each wait for their data before the next is issued.
   auto bfly = [&](int h, int& c, int& b) {
     const int beta = 64 * w + 32 * h + n;
-    c = beta / NB;
-    b = beta % NB;
-    return beta < total;
+    const bool exists = beta < total;
+    const int bs = exists ? beta : 0;
+    c = bs / NB;
+    b = bs % NB;
+    return exists;
   };
   // LDS address of input i of butterfly b of transform c (element b + q NB, q = split_in_q(g, i)):
   // one base plus a compile-time offset when NB is a multiple of 16.
@@ -297,8 +301,9 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
     act[h] = bfly(h, cc[h], bb[h]);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      if constexpr (FromBuf) x[h][i] = act[h] ? buf[in_addr(cc[h], bb[h], i)] : make_float2(0.f, 0.f);
-      else x[h][i] = act[h] ? load(cc[h], bb[h] + split_in_q(g, i) * NB) : make_float2(0.f, 0.f);
+      if constexpr (FromBuf) x[h][i] = buf[in_addr(cc[h], bb[h], i)];
+      else x[h][i] = load(cc[h], bb[h] + split_in_q(g, i) * NB);
+      if (!act[h]) x[h][i] = make_float2(0.f, 0.f);
     }
   }
   float u = 1.f;
@@ -340,7 +345,8 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const int q = split_in_q(g, i);
-          const float2 v = act[h] ? buf[in_addr(cc[h], bb[h], i)] : make_float2(0.f, 0.f);
+          float2 v = buf[in_addr(cc[h], bb[h], i)];
+          if (!act[h]) v = make_float2(0.f, 0.f);
           x[h][i] = cmul(v, stage_twiddle<NS>(tw, k, q));
         }
       }
