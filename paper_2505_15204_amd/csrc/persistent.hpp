@@ -60,19 +60,47 @@ struct PersistLds {
 static_assert(sizeof(BinShared) <= sizeof(float2) * PersistLds<512>::max_f2(), "binning scratch aliases the strip");
 
 // ---------------------------------------------------------------- one image in one workgroup
+// A job is a separate (non-inlined) function. Its pointer arguments carry their address space
+// (global memory or LDS) in their types: through plain pointers every access in the job would be
+// a flat instruction, which also waits on the LDS counter and needs 64-bit addresses per lane.
+typedef __attribute__((address_space(1))) const float2 gc_float2;
+typedef __attribute__((address_space(1))) const double gc_double;
+typedef __attribute__((address_space(1))) const uint8_t gc_u8;
+typedef __attribute__((address_space(1))) const uint4 gc_uint4;
+typedef __attribute__((address_space(1))) int2 g_int2;
+typedef __attribute__((address_space(1))) int g_int;
+typedef __attribute__((address_space(1))) float2 g_float2;
+typedef __attribute__((address_space(1))) float g_float;
+typedef __attribute__((address_space(1))) int32_t g_i32;
+typedef __attribute__((address_space(1))) double g_double;
+typedef __attribute__((address_space(3))) float2 l_float2;
+typedef __attribute__((address_space(3))) unsigned l_u32;
+typedef __attribute__((address_space(3))) int l_int;
+
 struct ImageJob {
-  const float2* V;          // visibilities of the image
-  const double* uvw;        // its baselines' uvw
-  const uint8_t* flags;     // its flags or null
+  gc_float2* V;             // visibilities of the image
+  gc_double* uvw;           // its baselines' uvw
+  gc_u8* flags;             // its flags or null
   int B;
   double k;                 // cells per metre
-  int2* plc;                // this workgroup's placement list
-  int* off;                 // this workgroup's strip offsets
-  float2* H;                // this workgroup's intermediate slot
-  float* out;               // the image
-  int32_t* n_out;           // its out-of-grid count or null
-  double* wsum;             // its weight sum or null
+  g_int2* plc;              // this workgroup's placement list
+  g_int* off;               // this workgroup's strip offsets
+  g_float2* H;              // this workgroup's intermediate slot
+  g_float* out;             // the image
+  g_i32* n_out;             // its out-of-grid count or null
+  g_double* wsum;           // its weight sum or null
   int shift;
+};
+
+// The LDS arrays of the persistent kernel that a job uses.
+struct JobLds {
+  l_float2* sbuf;           // strip / row-block buffer (also the binning scratch)
+  l_u32* scnt;              // uniform weighting's counts
+  l_int* s_int;             // [0] block reduction word, [1] kept count, [2] occupancy
+  l_u32* s_max;             // the split form's largest magnitude
+  l_float2* stw;            // twiddle table copy (TWL)
+  l_int* s_tw_logn;         // size whose table stw holds
+  l_int* s_off;             // strip offsets
 };
 
 template <int S>
@@ -89,13 +117,29 @@ struct Log2<1> {
 // gridded and transformed by the batched path's pipelined strip loop (grid_colfft_strips, every
 // strip in turn) from the strip offsets copied to `s_off` (LDS, NBLK + 1 ints).
 template <int LOGN, int BLOCK, bool UNIFORM, int PREC, bool TWL>
-__device__ __noinline__ void image_job(ImageJob j, const float2* __restrict__ tw, float2* sbuf, unsigned* scnt,
-                                       int* s_int, SplitCtx sp, float2* stw, int* s_tw_logn, int* s_off) {
+__device__ __noinline__ void image_job(ImageJob j, gc_float2* gtw, gc_uint4* gops, JobLds lds) {
   constexpr int N = 1 << LOGN;
   constexpr int S = desc_cols(LOGN, BLOCK);
   constexpr int NBLK = (N / 2) / S;         // column strips, and row blocks of S row pairs
   constexpr int LOGS = Log2<S>::value;
   static_assert((1 << LOGS) == S, "strip width is a power of two");
+  const float2* tw = (const float2*)gtw;
+  float2* sbuf = (float2*)lds.sbuf;
+  unsigned* scnt = (unsigned*)lds.scnt;
+  int* s_int = (int*)lds.s_int;
+  float2* stw = (float2*)lds.stw;
+  int* s_tw_logn = (int*)lds.s_tw_logn;
+  int* s_off = (int*)lds.s_off;
+  const SplitCtx sp{(unsigned*)lds.s_max, (const uint4*)gops};
+  const float2* V = (const float2*)j.V;
+  const double* uvw = (const double*)j.uvw;
+  const uint8_t* flags = (const uint8_t*)j.flags;
+  int2* plc = (int2*)j.plc;
+  int* off = (int*)j.off;
+  float2* H = (float2*)j.H;
+  float* out = (float*)j.out;
+  int32_t* n_out = (int32_t*)j.n_out;
+  double* wsum = (double*)j.wsum;
   int* s_tmp = s_int;
   int* s_kept = s_int + 1;
   int* s_occ = s_int + 2;
@@ -108,17 +152,17 @@ __device__ __noinline__ void image_job(ImageJob j, const float2* __restrict__ tw
     }
     tw = stw;
   }
-  bin_visibilities(j.uvw, j.flags, j.B, j.k, LOGN, LOGS, N / 2, j.plc, j.off, s_kept, j.n_out, nullptr, bsh);
+  bin_visibilities(uvw, flags, j.B, j.k, LOGN, LOGS, N / 2, plc, off, s_kept, n_out, nullptr, bsh);
   if (threadIdx.x == 0) *s_occ = 0;
   __syncthreads();                          // placement list and offsets complete; binning scratch free
-  for (int i = threadIdx.x; i <= NBLK; i += BLOCK) s_off[i] = j.off[i];   // visible after the loop's first barrier
-  grid_colfft_strips<LOGN, S, UNIFORM, PREC, BLOCK, kColPrefetch>(j.V, j.plc, s_off, 0, 1, NBLK, j.B > 0 ? NBLK : 0,
-                                                                  j.shift != 0, j.H, s_occ, tw, sbuf, scnt, s_tmp, sp);
+  for (int i = threadIdx.x; i <= NBLK; i += BLOCK) s_off[i] = off[i];   // visible after the loop's first barrier
+  grid_colfft_strips<LOGN, S, UNIFORM, PREC, BLOCK, kColPrefetch>(V, plc, s_off, 0, 1, NBLK, j.B > 0 ? NBLK : 0,
+                                                                  j.shift != 0, H, s_occ, tw, sbuf, scnt, s_tmp, sp);
   const double W = UNIFORM ? (double)*s_occ : 2.0 * (double)*s_kept;
-  if (j.wsum && threadIdx.x == 0) *j.wsum = W;
+  if (wsum && threadIdx.x == 0) *wsum = W;
   const float scale = inverse_weight(W);
   for (int rb = 0; rb < NBLK; ++rb) {
-    row_task<LOGN, S, PREC>(j.H, rb, scale, j.out, tw, sbuf, sp);
+    row_task<LOGN, S, PREC>(H, rb, scale, out, tw, sbuf, sp);
     __syncthreads();
   }
 }
@@ -151,29 +195,32 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(DescArgs a) {
     const blink_image_desc d = a.desc[img];
     const int logn = 31 - __clz(d.grid_n);
     ImageJob j;
-    j.V = a.vis + d.vis_offset;
-    j.uvw = a.uvw + 3 * d.uvw_offset;
-    j.flags = a.flags ? a.flags + d.flag_offset : nullptr;
+    j.V = (gc_float2*)(a.vis + d.vis_offset);
+    j.uvw = (gc_double*)(a.uvw + 3 * d.uvw_offset);
+    j.flags = a.flags ? (gc_u8*)(a.flags + d.flag_offset) : nullptr;
     j.B = d.n_baselines;
     j.k = (d.freq_hz / kSpeedOfLight) * ((double)d.grid_n * d.pixel_scale);
-    j.plc = plc;
-    j.off = off;
-    j.H = H;
-    j.out = a.images + d.image_offset;
-    j.n_out = a.n_out ? a.n_out + img : nullptr;
-    j.wsum = a.weight_sum ? a.weight_sum + img : nullptr;
+    j.plc = (g_int2*)plc;
+    j.off = (g_int*)off;
+    j.H = (g_float2*)H;
+    j.out = (g_float*)(a.images + d.image_offset);
+    j.n_out = a.n_out ? (g_i32*)(a.n_out + img) : nullptr;
+    j.wsum = a.weight_sum ? (g_double*)(a.weight_sum + img) : nullptr;
     j.shift = a.shift;
+    const JobLds lds{(l_float2*)sbuf, (l_u32*)scnt, (l_int*)s_int, (l_u32*)&s_max, (l_float2*)stw,
+                     (l_int*)&s_tw_logn, (l_int*)s_off};
+    gc_uint4* ops = (gc_uint4*)a.dft_ops;
     switch (logn) {
-      case 3: image_job<3, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[3], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
-      case 4: image_job<4, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[4], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
-      case 5: image_job<5, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[5], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
-      case 6: image_job<6, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[6], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
-      case 7: image_job<7, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[7], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
-      case 8: image_job<8, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[8], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
-      case 9: image_job<9, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[9], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
-      case 10: image_job<10, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[10], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
-      case 11: image_job<11, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[11], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
-      case 12: image_job<12, BLOCK, UNIFORM, PREC, TWL>(j, a.tw[12], sbuf, scnt, s_int, SplitCtx{&s_max, a.dft_ops}, stw, &s_tw_logn, s_off); break;
+      case 3: image_job<3, BLOCK, UNIFORM, PREC, TWL>(j, (gc_float2*)a.tw[3], ops, lds); break;
+      case 4: image_job<4, BLOCK, UNIFORM, PREC, TWL>(j, (gc_float2*)a.tw[4], ops, lds); break;
+      case 5: image_job<5, BLOCK, UNIFORM, PREC, TWL>(j, (gc_float2*)a.tw[5], ops, lds); break;
+      case 6: image_job<6, BLOCK, UNIFORM, PREC, TWL>(j, (gc_float2*)a.tw[6], ops, lds); break;
+      case 7: image_job<7, BLOCK, UNIFORM, PREC, TWL>(j, (gc_float2*)a.tw[7], ops, lds); break;
+      case 8: image_job<8, BLOCK, UNIFORM, PREC, TWL>(j, (gc_float2*)a.tw[8], ops, lds); break;
+      case 9: image_job<9, BLOCK, UNIFORM, PREC, TWL>(j, (gc_float2*)a.tw[9], ops, lds); break;
+      case 10: image_job<10, BLOCK, UNIFORM, PREC, TWL>(j, (gc_float2*)a.tw[10], ops, lds); break;
+      case 11: image_job<11, BLOCK, UNIFORM, PREC, TWL>(j, (gc_float2*)a.tw[11], ops, lds); break;
+      case 12: image_job<12, BLOCK, UNIFORM, PREC, TWL>(j, (gc_float2*)a.tw[12], ops, lds); break;
       default: break;
     }
   }
