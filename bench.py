@@ -352,15 +352,19 @@ def bench_uneven(ctx, torch, blink, synth, reps):
     uvw = torch.from_numpy(lay["uvw_ext"]).to(dev)
     images = torch.empty(lay["images_len"], dtype=torch.float32, device=dev)
     n_img = lay["n_img"]
-    ws = torch.empty(blink.desc_workspace_size(n_img, lay["max_b"], lay["max_n"], 512), dtype=torch.uint8,
+    ws = torch.empty(blink.desc_workspace_size(n_img, lay["max_b"], lay["max_n"], 1024), dtype=torch.uint8,
                      device=dev)
     model = int(sum(12 * int(n) ** 2 + 9 * int(b) for n, b in zip(lay["grid_n"], lay["n_baselines"])))
     sizes = {int(n): int((lay["grid_n"] == n).sum()) for n in sorted(set(lay["grid_n"].tolist()))}
     out = {"workload": "uneven: 4096 images, f = 70-300 MHz, N = 512 / 1024 / 2048 below 120 / 200 MHz / above, "
                        "pixel scale per channel so every baseline fits, 70-100% of 8128 baselines per image",
-           "images": n_img, "images_per_size": sizes, "bytes_model_total": model,
-           "desc_plan": ctx.get_desc_plan()}
+           "images": n_img, "images_per_size": sizes, "bytes_model_total": model}
     for name, prec in FORMS:
+        # the descriptor autotuner picks the mode (one launch, or one per size), block and workgroups
+        plan, tune_ms = ctx.autotune_desc(desc, vis, uvw, None, images, lay["max_b"], lay["max_n"], precision=prec,
+                                          workspace=ws)
+        log(f"uneven {name}: autotuned plan {plan} ({tune_ms:.2f} ms)")
+
         def run(i, prec=prec):
             ctx.blink_image_batch_desc(desc, vis, uvw, None, images, lay["max_b"], lay["max_n"], precision=prec,
                                        workspace=ws)
@@ -371,7 +375,7 @@ def bench_uneven(ctx, torch, blink, synth, reps):
         finally:
             g.close()
         gbs = model / (ms / 1e3) / 1e9
-        out[name] = {"images_per_s": round(n_img / (ms / 1e3), 1), "ms_per_batch": round(ms, 3),
+        out[name] = {"desc_plan": plan, "images_per_s": round(n_img / (ms / 1e3), 1), "ms_per_batch": round(ms, 3),
                      "graph_images_per_s": round(n_img / (gms / 1e3), 1), "graph_ms_per_batch": round(gms, 3),
                      "model_GB_s": round(gbs, 1), "frac_hbm_model": round(gbs / HBM_PEAK_GBS, 4)}
     for name, _ in FORMS[1:]:
