@@ -35,9 +35,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# sources of the batched imaging kernels (the correlator and the uneven-batch kernel are built
-# from their own files and do not change the imaging kernels' code)
-IMAGING_SOURCES_EXCLUDED = ("correlate.hip", "persistent.hip", "persistent.hpp")
+# device sources of the batched FP32 imaging kernels (the host code in api.hip, the correlator, the
+# uneven-batch kernel and the split forms' instantiation unit do not change their code; the launch
+# configuration is checked separately through the plan)
+IMAGING_KERNEL_SOURCES = ("conv_device.hpp", "fft_device.hpp", "imaging_device.hpp", "kernels.hip", "kernels.hpp",
+                          "launch.hpp", "split_fft.hpp")
 
 
 def kernel_source_hash():
@@ -47,10 +49,9 @@ def kernel_source_hash():
 
     csrc = os.path.join(ROOT, "paper_2505_15204_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")) and f not in IMAGING_SOURCES_EXCLUDED:
-            h.update(f.encode())
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in IMAGING_KERNEL_SOURCES:
+        h.update(f.encode())
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
