@@ -70,23 +70,56 @@ def counter_traffic(tag, kernel, plan):
     return None
 
 
-def kernel_unit_bytes(spec):
+SPEED_OF_LIGHT = 299792458.0
+
+
+def column_extent(torch, d, spec, steps):
+    """Mean number of half-spectrum columns that carry data over the images of `steps` steps (step i
+    images time step i mod T, every channel): 1 + the largest |ku| = |rint(u k)| over the kept
+    visibilities of each (t, c) pair (not flagged, inside the grid), 0 when none is kept. Columns
+    beyond it are zero in the grid and therefore in the half spectrum."""
+    N = spec.grid_n
+    k = d["freq_hz"] * (N * spec.pixel_scale / SPEED_OF_LIGHT)              # cells per metre, [C]
+    per_t = {}
+    for i in range(steps):
+        t = i % spec.T
+        if t not in per_t:
+            iu = torch.round(d["uvw_m"][t, :, 0][None, :] * k[:, None])      # [C][B], ties to even
+            iv = torch.round(d["uvw_m"][t, :, 1][None, :] * k[:, None])
+            kept = (iu.abs() < N / 2) & (iv.abs() < N / 2) & (d["flags"][t] == 0)
+            ext = torch.where(kept, iu.abs() + 1, torch.zeros_like(iu)).amax(dim=1)
+            per_t[t] = float(ext.mean())
+    return sum(per_t[i % spec.T] for i in range(steps)) / steps
+
+
+def kernel_unit_bytes(spec, ext=None):
     """Algorithmic HBM bytes per unit of work of each kernel (unit, bytes).
 
-    grid_colfft: per image, write the half-spectrum intermediate N x N/2 complex64 (4 N^2 B) and
-                 read each visibility once (8 B) plus its placement record (8 B).
-    row_fft:     per image, read the intermediate (4 N^2 B) and write the FP32 image (4 N^2 B).
+    `ext` is the mean number of half-spectrum columns that carry data per image (column_extent);
+    None means all N/2 (paths that transform every column).
+    grid_colfft: per image, write the nonzero columns of the half-spectrum intermediate (N rows x
+                 ext columns of complex64, 8 N ext B; 4 N^2 B with every column) and read each
+                 visibility once (8 B) plus its placement record (8 B).
+    row_fft:     per image, read those columns (8 N ext B) and write the FP32 image (4 N^2 B).
     bin:         per (t,c) pair, read the flag (1 B) of each baseline and write at most one
                  placement record (8 B) per baseline (one per kept visibility in the half plane,
                  two for the few on the u = 0 column); u, v (16 B per baseline) are shared by the
                  C channels of a time step, so each pair is charged 16 B / C of them.
     """
     N, B, C = spec.grid_n, spec.B, spec.C
+    h = 8 * N * (N / 2 if ext is None else ext)
     return {
-        "grid_colfft": ("image", 4 * N * N + 16 * B),
-        "row_fft": ("image", 8 * N * N),
+        "grid_colfft": ("image", round(h + 16 * B)),
+        "row_fft": ("image", round(h + 4 * N * N)),
         "bin": ("pair", 9 * B + (16 * B) // C),
     }
+
+
+def path_bytes_per_image(spec, ext=None):
+    """The whole path per image: write and read the nonzero half-spectrum columns, write the image,
+    read the visibilities and placements and the per-pair binning bytes shared by the pols."""
+    N, B, P = spec.grid_n, spec.B, spec.P
+    return round(16 * N * (N / 2 if ext is None else ext) + 4 * N * N + 8 * B + B // P)
 
 
 # The last-level cache (AMD Infinity Cache, "MALL") of the MI355X: 256 MB in front of HBM.
@@ -322,19 +355,21 @@ def bench_phase2(ctx, torch, blink, synth, steps, warmup):
     n_img = steps * C * P
     value = n_img / (ms / 1e3)
     prof, _ = profiled(ctx, torch, step, 1)
-    kernels = kernel_table(prof, {"image": C * P, "pair": C}, kernel_unit_bytes(spec))
-    per_image = 12 * N * N + 8 * B + B // P
+    kernels = kernel_table(prof, {"image": C * P, "pair": C}, kernel_unit_bytes(spec, column_extent(torch, d, spec, 1)))
+    ext = column_extent(torch, d, spec, steps)
+    per_image = path_bytes_per_image(spec, ext)
     out = {"workload": "phase2-2048: 144 tiles (10296 cross baselines), 2 pols, 3072 x 10 kHz channels from 185 MHz, "
                        "20 x 1 ms time steps, 2048^2 FP32 grid, 0.75 arcmin pixels, uniform weighting, 10% flags; "
                        "one step = one time step = 6144 images in 4 calls of 768 channels",
            "images_per_step": C * P, "steps": steps, "images_per_s": round(value, 1),
            "ms_per_step": round(ms / steps, 3), "plan": ctx.get_plan(N, 1),
            "path_roofline": {"bytes_per_image_model": per_image,
+                             "column_extent": {"mean_columns": round(ext, 1), "of": N // 2},
                              "achieved_GB_s": round(value * per_image / 1e9, 1),
                              "frac_hbm": round(value * per_image / 1e9 / HBM_PEAK_GBS, 4)},
            "kernels": kernels}
     log(f"Phase II: {value:.0f} images/s ({ms / steps:.2f} ms per time step), "
-        f"{value * per_image / 1e9:.0f} GB/s on the 12 N^2 + 9 B model")
+        f"{value * per_image / 1e9:.0f} GB/s on the path model (mean column extent {ext:.0f} of {N // 2})")
     del d, images, ws, wsum, nout
     torch.cuda.empty_cache()
     return out
@@ -488,7 +523,8 @@ def main():
     log(f"kernel timing pass: {args.steps} steps with per-launch events")
     prof, prof_ms = profiled(ctx, torch, step, args.steps)
     units = {"image": n_images, "pair": args.steps * C}
-    ub = kernel_unit_bytes(spec)
+    ext = column_extent(torch, d, spec, args.steps)
+    ub = kernel_unit_bytes(spec, ext)
     kernels = kernel_table(prof, units, ub)
     dom = max((k for k in kernels if k in ub), key=lambda k: kernels[k]["total_ms"])
     roof = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["achieved_GB_s"], "peak": HBM_PEAK_GBS,
@@ -506,7 +542,8 @@ def main():
         ctx.set_plan(N, 0, plan["col_strip"], plan["row_block"], big, col_loop=plan["col_loop"])
         bprof, bms = profiled(ctx, torch, step, min(args.steps, 10))
         ctx.set_plan(N, 0, plan["col_strip"], plan["row_block"], plan["group"], col_loop=plan["col_loop"])
-        bk = kernel_table(bprof, {"image": min(args.steps, 10) * C * P, "pair": min(args.steps, 10) * C}, ub)
+        bk = kernel_table(bprof, {"image": min(args.steps, 10) * C * P, "pair": min(args.steps, 10) * C},
+                          kernel_unit_bytes(spec, column_extent(torch, d, spec, min(args.steps, 10))))
     else:
         bk, bms = {}, float("nan")
     roof["last_level_cache"] = {
@@ -520,8 +557,9 @@ def main():
     log(f"groups of {big} (half spectra beyond the cache): row kernel at "
         f"{bk.get('row_fft', {}).get('frac_hbm', 0):.3f} of HBM, column kernel at "
         f"{bk.get('grid_colfft', {}).get('frac_hbm', 0):.3f}")
-    per_image = 12 * N * N + 8 * B + B // P
+    per_image = path_bytes_per_image(spec, ext)
     path = {"bytes_per_image_model": per_image,
+            "column_extent": {"mean_columns": round(ext, 1), "of": N // 2},
             "achieved_GB_s": round(value * per_image / 1e9, 1),
             "frac_hbm": round(value * per_image / 1e9 / HBM_PEAK_GBS, 4),
             "kernel_timing_pass_ms": round(prof_ms, 3)}
@@ -546,7 +584,8 @@ def main():
                                           workspace=ws)
                 ms = timed(torch, fstep, fs, 2)
                 fprof, _ = profiled(ctx, torch, fstep, fs)
-                fk = kernel_table(fprof, {"image": fs * C * P, "pair": fs * C}, ub)
+                fk = kernel_table(fprof, {"image": fs * C * P, "pair": fs * C},
+                                  kernel_unit_bytes(spec, column_extent(torch, d, spec, fs)))
                 v = fs * C * P / (ms / 1e3)
                 forms["vcs-1024"][name] = {"images_per_s": round(v, 1), "vs_fp32": round(v / value, 4),
                                            "plan": ctx.get_plan(N, 0, prec),
@@ -563,7 +602,8 @@ def main():
                                            workspace=cws)
             ms = timed(torch, cstep, fs, 2)
             cprof, _ = profiled(ctx, torch, cstep, fs)
-            ck = kernel_table(cprof, {"image": fs * C * P, "pair": fs * C}, ub)
+            # the convolutional path transforms every column of the half spectrum
+            ck = kernel_table(cprof, {"image": fs * C * P, "pair": fs * C}, kernel_unit_bytes(spec))
             v = fs * C * P / (ms / 1e3)
             forms["vcs-1024"]["conv_w8_fp32"] = {"images_per_s": round(v, 1), "vs_fp32": round(v / value, 4),
                                                  "kernel": "exponential of semicircle, W = 8, beta = 18.4",
@@ -587,7 +627,8 @@ def main():
                                                 out=images, weight_sum=wsum, n_out=nout, workspace=xws)
             ms = timed(torch, xstep, fs, 2)
             xprof, _ = profiled(ctx, torch, xstep, fs)
-            xub = dict(ub, correct=("pair", P * B * 16 + 24 * B // C + P * spec.n_tiles * 8))
+            xub = dict(kernel_unit_bytes(spec, column_extent(torch, d, spec, fs)),
+                       correct=("pair", P * B * 16 + 24 * B // C + P * spec.n_tiles * 8))
             xk = kernel_table(xprof, {"image": fs * C * P, "pair": fs * C}, xub)
             v = fs * C * P / (ms / 1e3)
             forms["vcs-1024"]["corrected_fp32"] = {

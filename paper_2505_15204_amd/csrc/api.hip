@@ -150,7 +150,7 @@ struct Carve {
 };
 
 struct BinLayout {
-  size_t plc, off, kept, occ;
+  size_t plc, off, kept, occ, ext = 0;   // ext: column extent per pair (fused path)
 };
 
 BinLayout carve_bins(Carve& c, size_t Q, size_t P, size_t B, size_t nstrips) {
@@ -159,6 +159,7 @@ BinLayout carve_bins(Carve& c, size_t Q, size_t P, size_t B, size_t nstrips) {
   L.off = c.take(Q, (nstrips + 1) * sizeof(int));
   L.kept = c.take(Q, sizeof(int));
   L.occ = c.take(Q, P * sizeof(int));
+  L.ext = c.take(Q, sizeof(int));
   return L;
 }
 
@@ -666,6 +667,7 @@ static blink_status image_batch(blink_ctx ctx, const blink_cf32* vis, const uint
     ba.occ = (int*)(ws + L.bins.occ);
     ba.cell_idx = nullptr;
     ba.n_out = n_out;
+    ba.ext = (int*)(ws + L.bins.ext);
     hipError_t e;
     {
       KernelTimer kt(ctx, BLINK_KERNEL_BIN, s);
@@ -710,9 +712,11 @@ static blink_status image_batch(blink_ctx ctx, const blink_cf32* vis, const uint
     ca.occ = ba.occ;
     ca.dft_ops = ctx->dft_ops;
     ca.col_loop = plan.col_loop;
+    ca.ext = ba.ext;
     const int n_img = q * P;
     blink::RowArgs ra{};
     ra.H = ca.H;
+    ra.ext = ba.ext;
     ra.logn = logn;
     ra.P = P;
     ra.wmode = weighting == BLINK_WEIGHT_UNIFORM ? blink::kWeightUniform : blink::kWeightNatural;

@@ -14,6 +14,9 @@ constexpr int kLdsBytes = 160 * 1024;
 constexpr double kSpeedOfLight = 299792458.0;
 constexpr int kBinThreads = 1024;
 constexpr int kMaxStrips = 4096;
+// Fourth word of a raw buffer resource on gfx9-family chips (gfx950): 32-bit data format, no
+// swizzle, no index stride; with it a load at or past the resource's byte size returns zero.
+constexpr int kBufferRsrcWord3 = 0x00020000;
 
 __host__ __device__ constexpr int pow2_floor(int x) {
   int p = 1;
@@ -77,23 +80,25 @@ __device__ __forceinline__ int nearest_cell(double u, double v, double k, double
 struct BinShared {
   int cnt[kMaxStrips + 1];
   int wave[17];
-  int red[2];
+  int red[3];
 };
 
 // Cell indices and the counting sort of one visibility set's placements into column strips of
 // width 2^log_strip, keeping only columns ku < ku_limit. Writes the placement list plc (each
 // record {kv*N + ku, b | conj<<31}), the strip offsets off[0..ku_limit>>log_strip], the kept and
-// out-of-grid counts, and cell_idx[b] when non-null. One workgroup (a multiple of 64 threads,
-// at least 512 so that the strip count fits the scan).
+// out-of-grid counts, and cell_idx[b] when non-null. When ext_out is non-null it receives the
+// column extent: (index of the last strip holding a placement + 1) * 2^log_strip, 0 when no
+// placement is kept; every column at or beyond it is zero in the grid. One workgroup (a multiple
+// of 64 threads, at least 512 so that the strip count fits the scan).
 __device__ inline void bin_visibilities(const double* __restrict__ uvw, const uint8_t* __restrict__ fl, int B,
                                         double k, int logn, int log_strip, int ku_limit, int2* __restrict__ plc,
                                         int* __restrict__ off, int* kept_out, int* nout_out,
-                                        int32_t* __restrict__ cell_idx, BinShared& sh) {
+                                        int32_t* __restrict__ cell_idx, BinShared& sh, int* ext_out = nullptr) {
   const int N = 1 << logn, mask = N - 1;
   const int nstrips = ku_limit >> log_strip;
   const double half = (double)(N / 2);
   for (int i = threadIdx.x; i <= nstrips; i += blockDim.x) sh.cnt[i] = 0;
-  if (threadIdx.x < 2) sh.red[threadIdx.x] = 0;
+  if (threadIdx.x < 3) sh.red[threadIdx.x] = 0;
   __syncthreads();
   int kept = 0, outside = 0;
   for (int b = threadIdx.x; b < B; b += blockDim.x) {
@@ -116,6 +121,10 @@ __device__ inline void bin_visibilities(const double* __restrict__ uvw, const ui
   if (kept) atomicAdd(&sh.red[0], kept);
   if (outside) atomicAdd(&sh.red[1], outside);
   __syncthreads();
+  // the counts are read here before the scan's first barrier, after which it overwrites them
+  if (ext_out)
+    for (int i = threadIdx.x; i < nstrips; i += blockDim.x)
+      if (sh.cnt[i] > 0) atomicMax(&sh.red[2], i + 1);
   block_exclusive_scan(sh.cnt, nstrips, sh.wave);
   for (int i = threadIdx.x; i <= nstrips; i += blockDim.x) off[i] = sh.cnt[i];
   if (threadIdx.x == 0) {
@@ -123,6 +132,7 @@ __device__ inline void bin_visibilities(const double* __restrict__ uvw, const ui
     if (nout_out) *nout_out = sh.red[1];
   }
   __syncthreads();
+  if (ext_out && threadIdx.x == 0) *ext_out = sh.red[2] << log_strip;
   for (int b = threadIdx.x; b < B; b += blockDim.x) {
     if (fl && fl[b]) continue;
     int iu, iv;
@@ -400,22 +410,51 @@ __device__ __forceinline__ void grid_colfft_strips(const float2* __restrict__ V,
 // multiplies pixel (y, x) by corr[y] corr[x] (the convolutional path's grid correction).
 // Pixels are written with non-temporal stores: nothing in the path reads them again, and keeping
 // them out of the caches leaves the last-level cache to the half spectra that the launches of
-// the image group read and write.
-__device__ __forceinline__ float2 hermitian_pair(const float2* __restrict__ h1, const float2* __restrict__ h2, int e,
-                                                 int N) {
-  const int HALF = N / 2;
-  const int idx = (e < HALF) ? e : ((e == HALF) ? 0 : N - e);
-  const float2 a = h1[idx], b = h2[idx];
+// the image group read and write. H columns at or beyond `ext` hold no placement and the column
+// pass does not write them: they are read as zero, without a memory access where the rows of a
+// transform are uniform over the wavefront (buffer loads whose range ends at the extent), and
+// otherwise from a column the other lanes read too, masked to zero afterwards. Either way the
+// loads stay unconditional, so they are all in flight before the first wait.
+__device__ __forceinline__ float2 hermitian_combine(float2 a, float2 b, int e, int HALF) {
   if (e == 0) return make_float2(a.x, b.x);
   if (e == HALF) return make_float2(a.y, b.y);
   if (e < HALF) return make_float2(a.x - b.y, a.y + b.x);
   return make_float2(a.x + b.y, b.x - a.y);
 }
 
+__device__ __forceinline__ int hermitian_index(int e, int HALF) {
+  return (e < HALF) ? e : ((e == HALF) ? 0 : 2 * HALF - e);
+}
+
+__device__ __forceinline__ float2 masked(float2 a, unsigned keep) {
+  return make_float2(__uint_as_float(__float_as_uint(a.x) & keep), __uint_as_float(__float_as_uint(a.y) & keep));
+}
+
+__device__ __forceinline__ float2 hermitian_pair(const float2* __restrict__ h1, const float2* __restrict__ h2, int e,
+                                                 int N, int ext) {
+  const int HALF = N / 2;
+  const int idx = hermitian_index(e, HALF);
+  const bool live = idx < ext;
+  const int at = live ? idx : 0;
+  const unsigned keep = 0u - (unsigned)live;
+  return hermitian_combine(masked(h1[at], keep), masked(h2[at], keep), e, HALF);
+}
+
+// Buffer resource over the first `ext` columns of a stored half row (base and size uniform over
+// the wavefront); a load past the size returns zero without touching memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t half_row_rsrc(const float2* row, int ext) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(row), (short)0, ext * (int)sizeof(float2),
+                                           kBufferRsrcWord3);
+}
+
+__device__ __forceinline__ float2 half_row_load(__amdgpu_buffer_rsrc_t r, int idx) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, idx * (int)sizeof(float2), 0, 0));
+}
+
 template <int LOGN, int TPB, int PREC = kPrecFp32>
 __device__ __forceinline__ void row_task(const float2* __restrict__ H, int rowblk, float scale, float* __restrict__ out,
                                          const float2* __restrict__ tw, float2* sbuf, SplitCtx sp = {},
-                                         const float* __restrict__ corr = nullptr) {
+                                         const float* __restrict__ corr = nullptr, int ext = 1 << 30) {
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, T = P::T, NP = P::NP, HALF = N / 2;
   if constexpr (PREC != kPrecFp32 && LOGN >= 4) {
@@ -424,7 +463,7 @@ __device__ __forceinline__ void row_task(const float2* __restrict__ H, int rowbl
     const float2* hb = H + (size_t)(2 * rowblk * TPB) * HALF;
     float* ob = out + (size_t)(2 * rowblk * TPB) * N;
     auto load = [&](int c, int e) {
-      return hermitian_pair(hb + (size_t)(2 * c) * HALF, hb + (size_t)(2 * c + 1) * HALF, e, N);
+      return hermitian_pair(hb + (size_t)(2 * c) * HALF, hb + (size_t)(2 * c + 1) * HALF, e, N, ext);
     };
     if (corr) {
       fft_inverse_split<LOGN, PREC, false, false>(sbuf, TPB, tw, load, [&](int c, int e, float2 z) {
@@ -448,9 +487,22 @@ __device__ __forceinline__ void row_task(const float2* __restrict__ H, int rowbl
     const float2* h1 = H + (size_t)(2 * r) * HALF;
     const float2* h2 = h1 + HALF;
     float2 v[P::R];
-    if (active) {
+    if constexpr (T % 64 == 0) {
+      // a transform spans whole wavefronts: its two rows are the same for every lane of one
+      const int ru = __builtin_amdgcn_readfirstlane(r);
+      const float2* g1 = H + (size_t)(2 * ru) * HALF;
+      const __amdgpu_buffer_rsrc_t r1 = half_row_rsrc(g1, cmin(ext, HALF));
+      const __amdgpu_buffer_rsrc_t r2 = half_row_rsrc(g1 + HALF, cmin(ext, HALF));
+      if (active) {
 #pragma unroll
-      for (int m = 0; m < P::R; ++m) v[m] = hermitian_pair(h1, h2, lt + m * T, N);
+        for (int m = 0; m < P::R; ++m) {
+          const int e = lt + m * T, idx = hermitian_index(e, HALF);
+          v[m] = hermitian_combine(half_row_load(r1, idx), half_row_load(r2, idx), e, HALF);
+        }
+      }
+    } else if (active) {
+#pragma unroll
+      for (int m = 0; m < P::R; ++m) v[m] = hermitian_pair(h1, h2, lt + m * T, N, ext);
     }
     __syncthreads();   // the caller's twiddle table is visible
     float* o1 = out + (size_t)(2 * r) * N;

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BinArgs a) {
   bin_visibilities(a.uvw + (size_t)t * a.B * 3, a.flags ? a.flags + (size_t)tc * a.B : nullptr, a.B, k, a.logn,
                    a.log_strip, a.ku_limit, a.plc + (size_t)tcl * 2 * a.B, a.strip_off + (size_t)tcl * (nstrips + 1),
                    a.n_kept + tcl, a.n_out ? a.n_out + tc : nullptr, a.cell_idx ? a.cell_idx + (size_t)tc * a.B : nullptr,
-                   sh);
+                   sh, a.ext ? a.ext + tcl : nullptr);
   if (threadIdx.x < a.P) a.occ[(size_t)tcl * a.P + threadIdx.x] = 0;
 }
 

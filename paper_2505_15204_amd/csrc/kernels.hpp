@@ -71,12 +71,16 @@ __global__ __launch_bounds__(fft_block(S * FftPlan<LOGN>::T, PREC)) void k_grid_
   const int slot = blockIdx.x, img = a.img0 + slot;
   const int tcl = img / a.P;
   const int nstrips = (N / 2) / S;
+  // Strips at or beyond the column extent hold no placement: their columns of H are zero, and the
+  // row pass reads them as zero without loading them, so they are neither transformed nor stored.
+  const int live = a.ext ? a.ext[tcl] / S : nstrips;
+  if ((int)blockIdx.y >= live) return;   // uniform over the workgroup
   for (int i = threadIdx.x; i < TW; i += NT) stw[i] = twg[i];   // visible after the task's first barrier
   const int* so = a.strip_off + (size_t)tcl * (nstrips + 1);
   for (int i = threadIdx.x; i <= nstrips; i += NT) s_off[i] = so[i];   // visible after the task's first barrier
   grid_colfft_strips<LOGN, S, UNIFORM, PREC, NT, kColPrefetch>(
-      a.vis + (size_t)img * a.B, a.plc + (size_t)tcl * 2 * a.B, s_off, blockIdx.y, gridDim.y, nstrips,
-      a.B > 0 ? nstrips : 0, a.shift != 0,
+      a.vis + (size_t)img * a.B, a.plc + (size_t)tcl * 2 * a.B, s_off, blockIdx.y, gridDim.y, live,
+      a.B > 0 ? live : 0, a.shift != 0,
       a.H + (size_t)slot * N * (N / 2), a.occ + img, stw, sbuf, scnt, &s_tmp, SplitCtx{&s_max, a.dft_ops});
 }
 
@@ -189,8 +193,9 @@ __global__ __launch_bounds__(fft_block(TPB * FftPlan<LOGN>::T, PREC)) void k_row
   }
   const double W = image_weight(a, img);
   if (a.weight_sum && blockIdx.y == 0 && threadIdx.x == 0) a.weight_sum[img] = W;
+  const int ext = a.ext ? a.ext[img / a.P] : N / 2;
   row_task<LOGN, TPB, PREC>(a.H + (size_t)slot * N * (N / 2), blockIdx.y, inverse_weight(W),
-                            a.images + (size_t)slot * N * N, stw, sbuf, SplitCtx{&s_max, a.dft_ops}, a.corr);
+                            a.images + (size_t)slot * N * N, stw, sbuf, SplitCtx{&s_max, a.dft_ops}, a.corr, ext);
 }
 
 // ---------------------------------------------------------------- dispatch

@@ -37,6 +37,7 @@ struct BinArgs {
   int* occ;                 // [Q][P], zeroed here
   int32_t* cell_idx;        // [T][C][B] or null (global)
   int32_t* n_out;           // [T][C] or null (global)
+  int* ext;                 // [Q] or null: half-spectrum columns [0, ext) hold every placement (whole strips)
 };
 hipError_t launch_bin(const BinArgs& a, hipStream_t s);
 
@@ -64,6 +65,7 @@ struct ColArgs {
   const uint4* dft_ops;     // DFT operand table of the split forms
   int rec_stride;           // convolutional path: records per (t,c) pair (plc holds ConvRec)
   int col_loop;             // strips each column workgroup takes in turn (<= 1: one strip each)
+  const int* ext;           // [Q] or null: only strips below ext[pair] / S are gridded and stored
 };
 // `prec` selects the FFT form: BLINK_PREC_FP32 or a split matrix-core precision.
 hipError_t launch_grid_colfft(const ColArgs& a, int n_img, int strip, int prec, const float2* tw, hipStream_t s);
@@ -90,6 +92,7 @@ struct RowArgs {
   double* weight_sum;       // chunk base or null
   const uint4* dft_ops;     // DFT operand table of the split forms
   const float* corr;        // grid correction 1/c per pixel index [N], or null
+  const int* ext;           // [Q] or null: H columns at or beyond ext[pair] are read as zero
 };
 hipError_t launch_row_c2r(const RowArgs& a, int n_img, int tpb, int prec, const float2* tw, hipStream_t s);
 
