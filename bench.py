@@ -534,9 +534,10 @@ def main():
     # read by the row launch; when they fit the 256 MB last-level cache they are served from it, and
     # the byte counters (which sit above that cache) count those hits as HBM traffic. The same steps
     # with a group whose half spectra exceed the cache give the kernels' rates from DRAM.
-    h_group = plan["group"] * 4 * N * N
+    h_image = 8 * N * ext           # the half-spectrum columns one image writes and reads back (mean)
+    h_group = plan["group"] * h_image
     big = 0 if args.no_cache_probe else max(plan["group"], 1)
-    while big and big * 4 * N * N <= 1.5 * MALL_BYTES:
+    while big and big * h_image <= 1.5 * MALL_BYTES:
         big += max(plan["group"], 1)
     if big:
         ctx.set_plan(N, 0, plan["col_strip"], plan["row_block"], big, col_loop=plan["col_loop"])
@@ -547,11 +548,12 @@ def main():
     else:
         bk, bms = {}, float("nan")
     roof["last_level_cache"] = {
-        "note": f"a group's half spectra ({plan['group']} images x {4 * N * N >> 20} MiB = {h_group >> 20} MiB) fit "
-                f"the {MALL_BYTES // 10**6} MB Infinity Cache between the column and the row launch; the byte "
-                f"counters count its hits, so this fraction includes reads served from that cache",
+        "note": f"a group's half spectra ({plan['group']} images x {h_image / 2**20:.2f} MiB of nonzero columns = "
+                f"{h_group / 2**20:.0f} MiB) fit the {MALL_BYTES // 10**6} MB Infinity Cache between the column and "
+                f"the row launch; the byte counters count its hits, so this fraction includes reads served from "
+                f"that cache",
         "group_beyond_cache": big,
-        "half_spectra_MiB": (big * 4 * N * N) >> 20,
+        "half_spectra_MiB": round(big * h_image / 2**20),
         "frac_hbm": {k: bk[k]["frac_hbm"] for k in ("grid_colfft", "row_fft") if k in bk},
         "images_per_s": round(min(args.steps, 10) * C * P / (bms / 1e3), 1) if big else None}
     log(f"groups of {big} (half spectra beyond the cache): row kernel at "

@@ -925,7 +925,12 @@ blink_status blink_image_batch_conv(blink_ctx ctx, const blink_cf32* vis, const 
   const size_t n_tc = (size_t)T * C;
   if (n_tc == 0) return BLINK_OK;
   const auto& plan = ctx->plan[logn][BLINK_WEIGHT_NATURAL][precision];
-  const size_t want = plan.group > 0 ? (size_t)plan.group : kMaxGroupImages;
+  // The nearest-cell plan's group size, capped so that the group's half spectra (every column:
+  // the convolutional path does not skip any) stay within 192 MiB of the last-level cache.
+  const size_t h_bytes = (size_t(1) << (2 * logn - 1)) * sizeof(float2);
+  const size_t cache_group = ((size_t)192 << 20) / h_bytes > 0 ? ((size_t)192 << 20) / h_bytes : 1;
+  size_t want = plan.group > 0 ? (size_t)plan.group : kMaxGroupImages;
+  if (want > cache_group) want = cache_group;
   size_t Q = largest_fitting_chunk(n_tc, workspace_bytes, [&](size_t q) {
     return conv_layout(q, P, B, logn, kernel_width, q * P < want ? q * P : want).total;
   });
