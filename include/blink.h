@@ -311,11 +311,20 @@ blink_status blink_dedisperse(blink_ctx ctx, const float *images, int T, int C, 
 /* ---------------------------------------------------------------- uneven batches
  * Section 6.2.4 grids many fine channels and integration intervals in parallel on one GPU and
  * transforms all grids at once. blink_image_batch_desc does this for images that differ in grid
- * size and visibility count: every image is described by one blink_image_desc (device memory) and
- * the batch runs as two launches: a descriptor pass (checks, largest-grid-first order) and one
- * persistent fused kernel whose workgroups claim images from a queue and image each one alone
- * (binning, gridding + column FFT, row FFT) through a per-workgroup intermediate slot.
- * Workgroups never wait for each other. */
+ * size and visibility count: every image is described by one blink_image_desc (device memory).
+ * A descriptor pass checks the descriptors and orders the images largest grid first; then one of
+ * two forms (blink_set_desc_form) images them:
+ *   BLINK_DESC_PERSISTENT  one persistent fused kernel whose workgroups claim images from a queue
+ *                          and image each one alone (binning, gridding + column FFT, row FFT)
+ *                          through a per-workgroup intermediate slot;
+ *   BLINK_DESC_STAGED      one launch bins every image; then, per chunk of images of one grid size
+ *                          whose half spectra fit a 192 MiB buffer (sized for the last-level
+ *                          cache), a column launch and a row launch of blink_image_batch's fused
+ *                          column and row kernels for that size, reading each image's visibilities
+ *                          and output offset from its descriptor.
+ * In both, workgroups never wait for each other (the staged launches are ordered by the stream). */
+#define BLINK_DESC_PERSISTENT 0
+#define BLINK_DESC_STAGED 1
 typedef struct {
     int64_t vis_offset;    /* first visibility of the image in vis (blink_cf32 elements) */
     int64_t uvw_offset;    /* first baseline of the image in uvw_m (baselines: uvw_m + 3*uvw_offset) */
@@ -332,8 +341,9 @@ typedef struct {
 #define BLINK_DESC_BAD 1       /* a descriptor was invalid or out of bounds; that image was skipped */
 
 /* Workspace bytes for blink_image_batch_desc with n_img images of at most max_baselines
- * visibilities and grid side at most max_grid_n, run by `workgroups` persistent workgroups (each
- * owns one intermediate slot of max_grid_n^2/2 complex values). */
+ * visibilities and grid side at most max_grid_n, enough for either form: the persistent form run
+ * by `workgroups` workgroups (each owns one intermediate slot of max_grid_n^2/2 complex values)
+ * and the staged form (placements of every image, 16 B per baseline, and the chunk buffer). */
 blink_status blink_desc_workspace_size(int n_img, int max_baselines, int max_grid_n, int workgroups,
                                        size_t *bytes);
 
@@ -342,9 +352,11 @@ blink_status blink_desc_workspace_size(int n_img, int max_baselines, int max_gri
  * them on the device and an invalid one only sets BLINK_DESC_BAD (its image is left untouched).
  * weighting, precision (any BLINK_PREC_* form) and shift apply to the whole batch. Outputs: images at each image_offset; weight_sum
  * double [n_img] and n_out int32 [n_img] (either may be NULL); status int32 [1] (may be NULL)
- * receives the BLINK_DESC_* bits. Uses the context's descriptor plan (blink_set_desc_plan); the
- * number of workgroups is reduced to the slots the workspace holds. Capturable into a hipGraph
- * (no allocation, copy or memset is issued). */
+ * receives the BLINK_DESC_* bits. Uses the context's descriptor form and plan
+ * (blink_set_desc_form, blink_set_desc_plan); the persistent form reduces the number of
+ * workgroups to the slots the workspace holds, the staged form returns BLINK_ERR_SIZE when the
+ * workspace is smaller than its layout. Capturable into a hipGraph (no allocation, copy or
+ * memset is issued). */
 blink_status blink_image_batch_desc(blink_ctx ctx, const blink_image_desc *desc, int n_img,
                                     const blink_cf32 *vis, int64_t vis_len, const double *uvw_m,
                                     int64_t uvw_len, const uint8_t *flags, int64_t flags_len,
@@ -353,13 +365,19 @@ blink_status blink_image_batch_desc(blink_ctx ctx, const blink_image_desc *desc,
                                     double *weight_sum, int32_t *n_out, int32_t *status,
                                     void *workspace, size_t workspace_bytes, void *hip_stream);
 
-/* Descriptor-path plan: block_threads (512 or 1024; uniform weighting uses 512) and the number of
- * persistent workgroups (0 = as many as are resident on the device). */
+/* Persistent-form plan: block_threads (512 or 1024; uniform weighting uses 512) and the number of
+ * workgroups (0 = as many as are resident on the device). */
 blink_status blink_get_desc_plan(blink_ctx ctx, int *block_threads, int *workgroups);
 blink_status blink_set_desc_plan(blink_ctx ctx, int block_threads, int workgroups);
+/* Descriptor-path form: BLINK_DESC_STAGED (the default) or BLINK_DESC_PERSISTENT. The staged form
+ * takes each grid size's execution plan of blink_image_batch (strip width, strips per workgroup,
+ * row block); block_threads and workgroups apply to the persistent form. */
+blink_status blink_get_desc_form(blink_ctx ctx, int *form);
+blink_status blink_set_desc_form(blink_ctx ctx, int form);
 
-/* Autotuner of the descriptor plan: times block sizes and workgroup counts on the caller's batch
- * (same arguments as blink_image_batch_desc) and keeps the fastest. Synchronises. */
+/* Autotuner of the descriptor plan: times both forms (the staged one when the workspace holds it),
+ * block sizes and workgroup counts on the caller's batch (same arguments as
+ * blink_image_batch_desc) and keeps the fastest, form included. Synchronises. */
 blink_status blink_autotune_desc(blink_ctx ctx, const blink_image_desc *desc, int n_img,
                                  const blink_cf32 *vis, int64_t vis_len, const double *uvw_m,
                                  int64_t uvw_len, const uint8_t *flags, int64_t flags_len,

@@ -24,6 +24,7 @@ KERNELS = ("bin", "grid", "grid_colfft", "dense_colfft", "weights", "row_fft", "
            "conv_correction", "average", "correct", "correlate", "dedisperse")
 AVG_TIME, AVG_CHANNEL, AVG_POL = 1, 2, 4   # BLINK_KERNEL_* ids
 DESC_BAD = 1
+DESC_PERSISTENT, DESC_STAGED = 0, 1   # BLINK_DESC_PERSISTENT / BLINK_DESC_STAGED: forms of the uneven-batch path
 
 # blink_image_desc as a NumPy structured dtype (64 bytes, C layout)
 import numpy as _np  # noqa: E402
@@ -144,6 +145,10 @@ def lib() -> ctypes.CDLL:
     L.blink_get_desc_plan.argtypes = [P, P, P]
     L.blink_set_desc_plan.restype = i32
     L.blink_set_desc_plan.argtypes = [P, i32, i32]
+    L.blink_get_desc_form.restype = i32
+    L.blink_get_desc_form.argtypes = [P, P]
+    L.blink_set_desc_form.restype = i32
+    L.blink_set_desc_form.argtypes = [P, i32]
     L.blink_autotune_desc.restype = i32
     L.blink_autotune_desc.argtypes = desc_args + [P, P, P, P]
     L.blink_graph_create_desc.restype = i32
@@ -420,13 +425,16 @@ class Context:
         return images
 
     def get_desc_plan(self) -> dict:
-        b, w = ctypes.c_int(), ctypes.c_int()
+        b, w, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(lib().blink_get_desc_plan(self.handle, ctypes.byref(b), ctypes.byref(w)), self.handle,
                "blink_get_desc_plan")
-        return {"block_threads": b.value, "workgroups": w.value}
+        _check(lib().blink_get_desc_form(self.handle, ctypes.byref(f)), self.handle, "blink_get_desc_form")
+        return {"block_threads": b.value, "workgroups": w.value, "form": f.value}
 
-    def set_desc_plan(self, block_threads: int = 512, workgroups: int = 0):
+    def set_desc_plan(self, block_threads: int = 512, workgroups: int = 0, form=None):
         _check(lib().blink_set_desc_plan(self.handle, block_threads, workgroups), self.handle, "blink_set_desc_plan")
+        if form is not None:
+            _check(lib().blink_set_desc_form(self.handle, int(form)), self.handle, "blink_set_desc_form")
 
     @_on_stream
     def autotune_desc(self, desc, vis, uvw_m, flags, images, max_baselines: int, max_grid_n: int, weighting: int = 0,
@@ -436,7 +444,7 @@ class Context:
         b, w, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         st = lib().blink_autotune_desc(*args, self._stream(stream), ctypes.byref(b), ctypes.byref(w), ctypes.byref(ms))
         _check(st, self.handle, "blink_autotune_desc")
-        return {"block_threads": b.value, "workgroups": w.value}, ms.value
+        return self.get_desc_plan(), ms.value
 
     def graph_desc(self, desc, vis, uvw_m, flags, images, max_baselines: int, max_grid_n: int, weighting: int = 0,
                    precision: int = PREC_FP32, shift: bool = True, weight_sum=None, n_out=None, status=None,

@@ -37,7 +37,7 @@ struct blink_ctx_s {
     int col_strip = 0, row_tpb = 0, group = 0, col_loop = 1;
   } plan[13][2][kPrecForms];
   // descriptor-path plan (blink_set_desc_plan) and device facts
-  int desc_block = 512, desc_workgroups = 0;
+  int desc_block = 512, desc_workgroups = 0, desc_form = BLINK_DESC_STAGED;
   int cu_count = 0;
   // kernel timing (blink_profile_enable)
   bool profiling = false;
@@ -1079,6 +1079,45 @@ DescLayout desc_layout(size_t n_img, size_t max_b, size_t max_n, size_t slots) {
   return L;
 }
 
+// Staged form: per-image placements, strip offsets, counts and extents (by position in the
+// order), the chunk table and the chunk buffer, which holds as many of the largest images' half
+// spectra as fit 192 MiB of the last-level cache (at least one, at most the batch).
+struct StagedLayout {
+  size_t valid, order, counter, status, chunks, plc, strip_off, kept, occ, ext, H, total;
+  int max_chunks;
+  int64_t chunk_elems;
+  bool ok;
+};
+
+StagedLayout staged_layout(size_t n_img, size_t max_b, size_t max_n) {
+  StagedLayout L;
+  int max_logn = 0;
+  while ((size_t(1) << max_logn) < max_n) ++max_logn;
+  const int64_t h = (int64_t)max_n * (int64_t)(max_n / 2);
+  int64_t cap = ((int64_t)192 << 20) / (h * (int64_t)sizeof(float2));
+  if (cap > (int64_t)n_img) cap = (int64_t)n_img;   // a batch of few images needs no more
+  if (cap < 1) cap = 1;
+  L.chunk_elems = h * cap;
+  int64_t mc = 0;                   // the chunk slots reserved for every grid size up to the largest
+  for (int l = 3; l <= max_logn; ++l) mc += blink::staged_slots(l, L.chunk_elems, (int)n_img);
+  L.max_chunks = (int)(mc < (int64_t)1 << 30 ? mc : (int64_t)1 << 30);
+  Carve c;
+  L.valid = c.take(n_img, sizeof(int));
+  L.order = c.take(n_img, sizeof(int));
+  L.counter = c.take(1, sizeof(int));
+  L.status = c.take(1, sizeof(int));
+  L.chunks = c.take((size_t)L.max_chunks, sizeof(int4));
+  L.plc = c.take(n_img, 2 * max_b * sizeof(int2));
+  L.strip_off = c.take(n_img, (max_n / 2 + 1) * sizeof(int));
+  L.kept = c.take(n_img, sizeof(int));
+  L.occ = c.take(n_img, sizeof(int));
+  L.ext = c.take(n_img, sizeof(int));
+  L.H = c.take((size_t)L.chunk_elems, sizeof(float2));
+  L.total = c.off;
+  L.ok = c.ok;
+  return L;
+}
+
 struct DescCall {
   const blink_image_desc* desc;
   int n_img;
@@ -1119,26 +1158,8 @@ blink_status check_desc(blink_ctx ctx, const DescCall& c, int* max_logn) {
 
 int desc_block_for(blink_ctx ctx, int weighting) { return weighting ? 512 : ctx->desc_block; }
 
-blink_status run_desc(blink_ctx ctx, const DescCall& c, hipStream_t s) {
-  int max_logn = 0;
-  blink_status st = check_desc(ctx, c, &max_logn);
-  if (st != BLINK_OK || c.n_img == 0) return st;
-  const int block = desc_block_for(ctx, c.weighting);
-  const int per_cu = blink::persistent_blocks_per_cu(block, c.weighting != 0, c.precision);
-  if (per_cu <= 0) return fail(ctx, BLINK_ERR_ARG, "persistent kernel with %d threads is not available", block);
-  size_t wg = ctx->desc_workgroups > 0 ? (size_t)ctx->desc_workgroups : (size_t)per_cu * ctx->cu_count;
-  if (wg > (size_t)c.n_img) wg = (size_t)c.n_img;
-  while (wg > 1 && desc_layout(c.n_img, c.max_b, c.max_n, wg).total > c.ws_bytes) wg = wg / 2 > 1 ? wg / 2 : 1;
-  while (desc_layout(c.n_img, c.max_b, c.max_n, wg + 1).total <= c.ws_bytes && wg < (size_t)c.n_img &&
-         wg < (ctx->desc_workgroups > 0 ? (size_t)ctx->desc_workgroups : (size_t)per_cu * ctx->cu_count))
-    ++wg;
-  DescLayout L = desc_layout(c.n_img, c.max_b, c.max_n, wg);
-  if (!L.ok || L.total > c.ws_bytes)
-    return fail(ctx, BLINK_ERR_SIZE, "workspace of %zu bytes is smaller than the %zu bytes one slot needs", c.ws_bytes,
-                L.total);
-  DeviceGuard g(ctx->device);
-  if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
-  char* ws = (char*)c.ws;
+// The common descriptor-pass arguments of both forms.
+blink::DescArgs desc_args(blink_ctx ctx, const DescCall& c, int max_logn, int block) {
   blink::DescArgs a{};
   a.desc = c.desc;
   a.n_img = c.n_img;
@@ -1157,16 +1178,100 @@ blink_status run_desc(blink_ctx ctx, const DescCall& c, hipStream_t s) {
   a.images_len = c.images_len;
   a.weight_sum = c.weight_sum;
   a.n_out = c.n_out;
+  a.strip_stride = c.max_n / 2 + 1;
+  for (int l = 3; l <= 12; ++l) a.tw[l] = ctx->tw[l];
+  a.dft_ops = ctx->dft_ops;
+  return a;
+}
+
+// Staged form: the descriptor pass, one binning launch, then for every grid size from the largest
+// down and every chunk slot reserved for it, the chunk's column launch and row launch with the
+// batched path's plan for that size (strip width, strips per workgroup, row block).
+blink_status run_desc_staged(blink_ctx ctx, const DescCall& c, int max_logn, hipStream_t s) {
+  StagedLayout L = staged_layout(c.n_img, c.max_b, c.max_n);
+  if (!L.ok || L.total > c.ws_bytes)
+    return fail(ctx, BLINK_ERR_SIZE, "workspace of %zu bytes is smaller than the %zu bytes the staged form needs",
+                c.ws_bytes, L.total);
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
+  char* ws = (char*)c.ws;
+  blink::DescArgs a = desc_args(ctx, c, max_logn, desc_block_for(ctx, c.weighting));
   a.status = c.status ? c.status : (int32_t*)(ws + L.status);
   a.valid = (int*)(ws + L.valid);
   a.order = (int*)(ws + L.order);
   a.counter = (int*)(ws + L.counter);
   a.plc = (int2*)(ws + L.plc);
   a.strip_off = (int*)(ws + L.strip_off);
-  a.strip_stride = c.max_n / 2 + 1;
   a.H = (float2*)(ws + L.H);
-  for (int l = 3; l <= 12; ++l) a.tw[l] = ctx->tw[l];
-  a.dft_ops = ctx->dft_ops;
+  a.chunks = (int4*)(ws + L.chunks);
+  a.max_chunks = L.max_chunks;
+  a.chunk_elems = L.chunk_elems;
+  a.kept = (int*)(ws + L.kept);
+  a.occ = (int*)(ws + L.occ);
+  a.ext = (int*)(ws + L.ext);
+  for (int l = 3; l <= 12; ++l) {
+    int ls = 0;
+    while ((1 << (ls + 1)) <= ctx->plan[l][c.weighting][c.precision].col_strip) ++ls;
+    a.col_log_strip[l] = ls;
+  }
+  hipError_t e;
+  {
+    KernelTimer kt(ctx, BLINK_KERNEL_DESC_PREP, s);
+    e = blink::launch_desc_prep(a, s);
+  }
+  if (e == hipSuccess) {
+    KernelTimer kt(ctx, BLINK_KERNEL_BIN, s);
+    e = blink::launch_desc_bin(a, s);
+  }
+  int j = 0;
+  for (int l = max_logn; l >= 3 && e == hipSuccess; --l) {
+    const auto& plan = ctx->plan[l][c.weighting][c.precision];
+    const int cap = blink::staged_capacity(l, L.chunk_elems, c.n_img);
+    const int slots = blink::staged_slots(l, L.chunk_elems, c.n_img);
+    for (int m = 0; m < slots && e == hipSuccess; ++m, ++j) {
+      {
+        KernelTimer kt(ctx, BLINK_KERNEL_GRID_COLFFT, s);
+        e = blink::launch_chunk_colfft(a, j, l, plan.col_strip, plan.col_loop, cap, c.precision, s);
+      }
+      if (e == hipSuccess) {
+        KernelTimer kt(ctx, BLINK_KERNEL_ROW_FFT, s);
+        e = blink::launch_chunk_row(a, j, l, plan.row_tpb, cap, c.precision, s);
+      }
+    }
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "uneven-batch staged kernels");
+  return BLINK_OK;
+}
+
+blink_status run_desc(blink_ctx ctx, const DescCall& c, hipStream_t s) {
+  int max_logn = 0;
+  blink_status st = check_desc(ctx, c, &max_logn);
+  if (st != BLINK_OK || c.n_img == 0) return st;
+  if (ctx->desc_form == BLINK_DESC_STAGED) return run_desc_staged(ctx, c, max_logn, s);
+  const int block = desc_block_for(ctx, c.weighting);
+  const int per_cu = blink::persistent_blocks_per_cu(block, c.weighting != 0, c.precision);
+  if (per_cu <= 0) return fail(ctx, BLINK_ERR_ARG, "persistent kernel with %d threads is not available", block);
+  size_t wg = ctx->desc_workgroups > 0 ? (size_t)ctx->desc_workgroups : (size_t)per_cu * ctx->cu_count;
+  if (wg > (size_t)c.n_img) wg = (size_t)c.n_img;
+  while (wg > 1 && desc_layout(c.n_img, c.max_b, c.max_n, wg).total > c.ws_bytes) wg = wg / 2 > 1 ? wg / 2 : 1;
+  while (desc_layout(c.n_img, c.max_b, c.max_n, wg + 1).total <= c.ws_bytes && wg < (size_t)c.n_img &&
+         wg < (ctx->desc_workgroups > 0 ? (size_t)ctx->desc_workgroups : (size_t)per_cu * ctx->cu_count))
+    ++wg;
+  DescLayout L = desc_layout(c.n_img, c.max_b, c.max_n, wg);
+  if (!L.ok || L.total > c.ws_bytes)
+    return fail(ctx, BLINK_ERR_SIZE, "workspace of %zu bytes is smaller than the %zu bytes one slot needs", c.ws_bytes,
+                L.total);
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(ctx, g.err, "hipSetDevice");
+  char* ws = (char*)c.ws;
+  blink::DescArgs a = desc_args(ctx, c, max_logn, block);
+  a.status = c.status ? c.status : (int32_t*)(ws + L.status);
+  a.valid = (int*)(ws + L.valid);
+  a.order = (int*)(ws + L.order);
+  a.counter = (int*)(ws + L.counter);
+  a.plc = (int2*)(ws + L.plc);
+  a.strip_off = (int*)(ws + L.strip_off);
+  a.H = (float2*)(ws + L.H);
   hipError_t e;
   {
     KernelTimer kt(ctx, BLINK_KERNEL_DESC_PREP, s);
@@ -1195,8 +1300,9 @@ blink_status blink_desc_workspace_size(int n_img, int max_baselines, int max_gri
   if (log2_exact(max_grid_n) < 0) return BLINK_ERR_SIZE;
   DescLayout L = desc_layout((size_t)n_img, (size_t)max_baselines, (size_t)max_grid_n,
                              (size_t)(workgroups < n_img ? workgroups : (n_img > 0 ? n_img : 1)));
-  if (!L.ok) return BLINK_ERR_SIZE;
-  *bytes = L.total;
+  StagedLayout S = staged_layout((size_t)n_img, (size_t)max_baselines, (size_t)max_grid_n);
+  if (!L.ok || !S.ok) return BLINK_ERR_SIZE;
+  *bytes = L.total > S.total ? L.total : S.total;
   return BLINK_OK;
 }
 
@@ -1215,6 +1321,20 @@ blink_status blink_get_desc_plan(blink_ctx ctx, int* block_threads, int* workgro
   if (!ctx) return BLINK_ERR_ARG;
   if (block_threads) *block_threads = ctx->desc_block;
   if (workgroups) *workgroups = ctx->desc_workgroups;
+  return BLINK_OK;
+}
+
+blink_status blink_get_desc_form(blink_ctx ctx, int* form) {
+  if (!ctx || !form) return BLINK_ERR_ARG;
+  *form = ctx->desc_form;
+  return BLINK_OK;
+}
+
+blink_status blink_set_desc_form(blink_ctx ctx, int form) {
+  if (!ctx) return BLINK_ERR_ARG;
+  if (form != BLINK_DESC_PERSISTENT && form != BLINK_DESC_STAGED)
+    return fail(ctx, BLINK_ERR_ARG, "unknown descriptor-path form %d", form);
+  ctx->desc_form = form;
   return BLINK_OK;
 }
 
@@ -1238,7 +1358,7 @@ blink_status blink_autotune_desc(blink_ctx ctx, const blink_image_desc* desc, in
   int max_logn = 0;
   blink_status st = check_desc(ctx, c, &max_logn);
   if (st != BLINK_OK) return st;
-  const int sb = ctx->desc_block, sw = ctx->desc_workgroups;
+  const int sb = ctx->desc_block, sw = ctx->desc_workgroups, sf = ctx->desc_form;
   const bool was_profiling = ctx->profiling;
   ctx->profiling = false;
   DeviceGuard g(ctx->device);
@@ -1249,32 +1369,41 @@ blink_status blink_autotune_desc(blink_ctx ctx, const blink_image_desc* desc, in
     return hip_fail(ctx, hipErrorOutOfMemory, "hipEventCreate");
   }
   const int blocks[] = {512, 1024};
+  // the staged form is timed only when the workspace holds its layout
+  const bool staged_fits = n_img > 0 && staged_layout(n_img, max_baselines, max_grid_n).total <= workspace_bytes;
   double best = 1e300;
-  int bb = sb, bw = sw;
+  int bb = sb, bw = sw, bf = sf;
   blink_status result = BLINK_OK;
-  for (int bi = 0; bi < 2 && result == BLINK_OK; ++bi) {
-    if (weighting && blocks[bi] != 512) continue;
-    const int resident = blink::persistent_blocks_per_cu(blocks[bi], weighting != 0, precision) * ctx->cu_count;
-    const int counts[] = {0, resident / 2, resident / 4};
-    for (int wi = 0; wi < 3 && result == BLINK_OK; ++wi) {
-      if (wi > 0 && counts[wi] < 1) continue;
-      ctx->desc_block = blocks[bi];
-      ctx->desc_workgroups = counts[wi];
-      double t = 1e300;
-      for (int rep = 0; rep < 3 && result == BLINK_OK; ++rep) {
-        hipError_t he = hipEventRecord(e0, s);
-        result = run_desc(ctx, c, s);
-        if (he == hipSuccess) he = hipEventRecord(e1, s);
-        if (he == hipSuccess) he = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        if (he != hipSuccess && result == BLINK_OK) result = hip_fail(ctx, he, "autotune timing");
-        if (rep > 0 && ms < t) t = ms;
-      }
-      if (result == BLINK_OK && t < best) {
-        best = t;
-        bb = ctx->desc_block;
-        bw = ctx->desc_workgroups;
+  for (int form = BLINK_DESC_PERSISTENT; form <= BLINK_DESC_STAGED && result == BLINK_OK; ++form) {
+    if (form == BLINK_DESC_STAGED && !staged_fits) continue;
+    for (int bi = 0; bi < 2 && result == BLINK_OK; ++bi) {
+      if (weighting && blocks[bi] != 512) continue;
+      // the staged form takes the batched path's per-size plans: one timing, with block 512
+      if (form == BLINK_DESC_STAGED && blocks[bi] != 512) continue;
+      const int resident = blink::persistent_blocks_per_cu(blocks[bi], weighting != 0, precision) * ctx->cu_count;
+      const int counts[] = {0, resident / 2, resident / 4};
+      for (int wi = 0; wi < 3 && result == BLINK_OK; ++wi) {
+        if (wi > 0 && (counts[wi] < 1 || form == BLINK_DESC_STAGED)) continue;
+        ctx->desc_form = form;
+        ctx->desc_block = blocks[bi];
+        ctx->desc_workgroups = counts[wi];
+        double t = 1e300;
+        for (int rep = 0; rep < 3 && result == BLINK_OK; ++rep) {
+          hipError_t he = hipEventRecord(e0, s);
+          result = run_desc(ctx, c, s);
+          if (he == hipSuccess) he = hipEventRecord(e1, s);
+          if (he == hipSuccess) he = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+          if (he != hipSuccess && result == BLINK_OK) result = hip_fail(ctx, he, "autotune timing");
+          if (rep > 0 && ms < t) t = ms;
+        }
+        if (result == BLINK_OK && t < best) {
+          best = t;
+          bb = ctx->desc_block;
+          bw = ctx->desc_workgroups;
+          bf = ctx->desc_form;
+        }
       }
     }
   }
@@ -1284,10 +1413,12 @@ blink_status blink_autotune_desc(blink_ctx ctx, const blink_image_desc* desc, in
   if (result != BLINK_OK) {
     ctx->desc_block = sb;
     ctx->desc_workgroups = sw;
+    ctx->desc_form = sf;
     return result;
   }
   ctx->desc_block = bb;
   ctx->desc_workgroups = bw;
+  ctx->desc_form = bf;
   result = run_desc(ctx, c, s);
   if (block_threads) *block_threads = bb;
   if (workgroups) *workgroups = bw;

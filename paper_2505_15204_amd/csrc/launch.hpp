@@ -153,10 +153,17 @@ hipError_t launch_dedisperse(const float* in, int C, int logn, const int* delays
 // Averages of images [T][C][P][N][N] over the axes in `axes` (1 time, 2 channel, 4 pol).
 hipError_t launch_image_average(const float* in, int T, int C, int P, int logn, int axes, float* out, hipStream_t s);
 
+struct DescArgs;
+
 // The same three launchers for one precision form; FP32 is built in kernels.hip, each split
-// precision in its own object from split.hip.
+// precision in its own object from split.hip. chunk_colfft and chunk_row are the staged form of
+// the uneven-batch path: the fused column kernel and the row kernel of one chunk (images of one
+// grid size 2^logn, at most `slots` of them) with strip width `strip` and `tpb` row-pair transforms.
 template <int PREC>
 struct PrecLaunch {
+  static hipError_t chunk_colfft(const DescArgs& a, int chunk, int logn, int strip, int col_loop, int slots,
+                                 hipStream_t s);
+  static hipError_t chunk_row(const DescArgs& a, int chunk, int logn, int tpb, int slots, hipStream_t s);
   static hipError_t grid_colfft(const ColArgs& a, int n_img, int strip, const float2* tw, hipStream_t s);
   static hipError_t dense_colfft(const float2* grids, int n_img, int logn, int shift, float2* H, const float2* tw,
                                  const uint4* dft_ops, hipStream_t s);
@@ -194,11 +201,37 @@ struct DescArgs {
   float2* H;                       // [workgroups][max_n * max_n / 2]
   const float2* tw[13];            // twiddle tables per log2 N
   const uint4* dft_ops;            // DFT operand table of the split forms
+  // staged form (plc, strip_off and H above then hold per-image placements and offsets, indexed
+  // by position in `order`, and the chunk buffer)
+  int4* chunks;                    // [max_chunks] {log2 N, first position in order, images, 0}; null: persistent form
+  int max_chunks;
+  int64_t chunk_elems;             // float2 elements of the chunk buffer (a multiple of the largest image's)
+  int* kept;                       // [n_img] kept visibilities, by position
+  int* occ;                        // [n_img] occupied cells (uniform weighting), by position
+  int* ext;                        // [n_img] column extent, by position
+  int col_log_strip[13];           // per log2 N: log2 of the column kernel's strip width
 };
+// Staged form: the chunk table reserves, for each grid size 2^logn <= the batch's largest, the
+// chunk slots that n_img images of that size could fill (largest size first), so that the host
+// can launch each slot's kernels for its size without reading the table back.
+__host__ __device__ inline int staged_capacity(int logn, int64_t chunk_elems, int n_img) {
+  const int64_t c = chunk_elems >> (2 * logn - 1);
+  return (int)(c < (int64_t)n_img ? (c > 0 ? c : 1) : (n_img > 0 ? n_img : 1));
+}
+__host__ __device__ inline int staged_slots(int logn, int64_t chunk_elems, int n_img) {
+  const int cap = staged_capacity(logn, chunk_elems, n_img);
+  return n_img > 0 ? (n_img + cap - 1) / cap : 0;
+}
 hipError_t launch_desc_prep(const DescArgs& a, hipStream_t s);
 hipError_t launch_persistent(const DescArgs& a, int workgroups, int prec, hipStream_t s);
 // Resident workgroups of the persistent kernel per CU (0 if the configuration is not compiled).
 int persistent_blocks_per_cu(int block, bool uniform, int prec);
+// Staged form: binning of every image (one workgroup each, strips of the column width that
+// `a.block` threads give), then per chunk a column launch and a row launch over `workgroups`.
+hipError_t launch_desc_bin(const DescArgs& a, hipStream_t s);
+hipError_t launch_chunk_colfft(const DescArgs& a, int chunk, int logn, int strip, int col_loop, int slots, int prec,
+                               hipStream_t s);
+hipError_t launch_chunk_row(const DescArgs& a, int chunk, int logn, int tpb, int slots, int prec, hipStream_t s);
 
 // The persistent kernel of one precision form (FP32 in persistent.hip, split forms in split.hip).
 template <int PREC>

@@ -3,7 +3,8 @@
 //
 //   k_desc_prep      checks every descriptor against the caller's array lengths, orders the valid
 //                    images by decreasing grid size (so the longest jobs start first) and resets
-//                    the queue
+//                    the queue; for the staged form it also cuts the order into chunks
+//   k_desc_bin       staged form: bins every valid image (one workgroup per image)
 #include <hip/hip_runtime.h>
 
 #include "persistent.hpp"
@@ -47,14 +48,66 @@ __global__ __launch_bounds__(1024) void k_desc_prep(DescArgs a) {
     *a.status = s_bad ? BLINK_DESC_BAD : 0;
   }
   __syncthreads();
+  if (a.chunks) {
+    // Staged form: the images of one bucket (one grid size) go in chunks of as many as the chunk
+    // buffer holds, in that size's reserved range of the chunk table (staged_slots); the
+    // remaining slots of the range get no images.
+    __shared__ int s_first[10], s_count[10], s_cap[10], s_base[11];
+    if (tid == 0) {
+      int base = 0;
+      for (int b = 0; b < 10; ++b) {
+        const int logn = 12 - b;
+        s_first[b] = s_bucket[b];
+        s_count[b] = s_bucket[b + 1] - s_bucket[b];
+        s_cap[b] = staged_capacity(logn, a.chunk_elems, a.n_img);
+        s_base[b] = base;
+        if (logn <= a.max_logn) base += staged_slots(logn, a.chunk_elems, a.n_img);
+      }
+      s_base[10] = base;
+    }
+    __syncthreads();
+    for (int j = tid; j < a.max_chunks; j += blockDim.x) {
+      int4 e = make_int4(0, 0, 0, 0);
+      for (int b = 0; b < 10; ++b)
+        if (j >= s_base[b] && j < s_base[b + 1]) {
+          const int first = s_first[b] + (j - s_base[b]) * s_cap[b];
+          const int left = s_first[b] + s_count[b] - first;
+          e = make_int4(12 - b, first, left > 0 ? min(s_cap[b], left) : 0, 0);
+        }
+      a.chunks[j] = e;
+    }
+  }
   for (int i = tid; i < a.n_img; i += blockDim.x) {
     const int b = a.valid[i] ? 12 - (31 - __clz(a.desc[i].grid_n)) : 16;
     a.order[atomicAdd(&s_bucket[b], 1)] = i;
   }
 }
 
+// Staged form: workgroup q bins the image at position q of the order into strips of the column
+// width the chunk kernels use for its size, into its own placement list and offsets.
+__global__ __launch_bounds__(kBinThreads) void k_desc_bin(DescArgs a) {
+  __shared__ BinShared sh;
+  const int q = blockIdx.x;
+  const int img = a.order[q];
+  if (!a.valid[img]) return;                 // uniform over the workgroup
+  const blink_image_desc d = a.desc[img];
+  const int logn = 31 - __clz(d.grid_n);
+  const int log_s = a.col_log_strip[logn];
+  const double k = (d.freq_hz / kSpeedOfLight) * ((double)d.grid_n * d.pixel_scale);
+  bin_visibilities(a.uvw + 3 * d.uvw_offset, a.flags ? a.flags + d.flag_offset : nullptr, d.n_baselines, k, logn,
+                   log_s, d.grid_n / 2, a.plc + (size_t)q * 2 * a.max_b, a.strip_off + (size_t)q * a.strip_stride,
+                   a.kept + q, a.n_out ? a.n_out + img : nullptr, nullptr, sh, a.ext + q);
+  if (threadIdx.x == 0) a.occ[q] = 0;
+}
+
 hipError_t launch_desc_prep(const DescArgs& a, hipStream_t s) {
   k_desc_prep<<<1, 1024, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_desc_bin(const DescArgs& a, hipStream_t s) {
+  if (a.n_img <= 0) return hipSuccess;
+  k_desc_bin<<<a.n_img, kBinThreads, 0, s>>>(a);
   return hipGetLastError();
 }
 

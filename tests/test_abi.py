@@ -117,9 +117,14 @@ def test_single_workspace_query_matches_each_entry(L):
 
 def test_desc_workspace_and_validation(L):
     s = blink.desc_workspace_size(10, 100, 256, 4)
+    # enough for the persistent form's 4 slots and for the staged form (every image's placements,
+    # and a chunk buffer of at most the batch's half spectra)
     assert s >= 4 * 2 * 100 * 8 + 4 * 256 * 128 * 8
-    assert blink.desc_workspace_size(10, 100, 256, 8) > s
+    assert s >= 10 * 2 * 100 * 8 + 10 * 256 * 128 * 8
+    assert blink.desc_workspace_size(10, 100, 256, 8) >= s
     assert blink.desc_workspace_size(10, 100, 256, 64) == blink.desc_workspace_size(10, 100, 256, 10)
+    # many workgroups: the persistent slots (256 KiB each) outgrow the staged form's 192 MiB buffer
+    assert blink.desc_workspace_size(2000, 100, 256, 1000) > blink.desc_workspace_size(2000, 100, 256, 800)
     with pytest.raises(blink.BlinkError):
         blink.desc_workspace_size(10, 100, 300, 4)
     dummy = ctypes.c_void_p(0x1000)
@@ -133,6 +138,8 @@ def test_desc_workspace_and_validation(L):
     assert L.blink_image_batch_desc(*args(prec=4)) == blink.BLINK_ERR_ARG
     assert L.blink_image_batch_desc(*args()) == blink.BLINK_ERR_ARG
     assert L.blink_set_desc_plan(None, 512, 0) == blink.BLINK_ERR_ARG
+    assert L.blink_set_desc_form(None, blink.DESC_STAGED) == blink.BLINK_ERR_ARG
+    assert L.blink_get_desc_form(None, None) == blink.BLINK_ERR_ARG
     assert L.blink_graph_launch(None, None) == blink.BLINK_ERR_ARG
     assert L.blink_graph_destroy(None) == blink.BLINK_OK
 

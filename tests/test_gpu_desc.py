@@ -1,5 +1,7 @@
 """GPU parity of the uneven-batch path (blink_image_batch_desc: descriptor pass, per-image binning,
-persistent fused gridding + FFT with a work queue) and of its hipGraph capture, against the oracle."""
+then either the persistent fused gridding + FFT with a work queue or the staged launches per chunk
+of same-size images) and of its hipGraph capture, against the oracle. Every test runs in both
+forms."""
 import numpy as np
 import pytest
 
@@ -33,10 +35,12 @@ def torch():
     return _t
 
 
-@pytest.fixture(scope="module")
-def ctx(torch):
+@pytest.fixture(scope="module", params=[0, 1], ids=["persistent", "staged"])
+def ctx(torch, request):
     import paper_2505_15204_amd as blink
     c = blink.Context(0)
+    c.set_desc_plan(512, 0, form=request.param)
+    say(f"descriptor form {'staged' if request.param else 'persistent'}")
     yield c
     c.close()
 
