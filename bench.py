@@ -13,8 +13,8 @@ the FP64 CPU oracle timed on a bounded sample of the same workload on the host c
 other forms measured beside it on the same GPU: the split-precision matrix-core FFT forms on
 this workload and on the 4096^2 precision workload (images/s ratio to FP32), convolutional
 gridding (W = 8) on this workload, the Stokes I + band average of one time step's images, and
-the uneven batch (4096 images of 512^2 .. 2048^2 in one persistent launch, eager and as a
-hipGraph).
+the uneven batch (4096 images of 512^2 .. 2048^2 in one blink_image_batch_desc call, in the form
+and plan the descriptor autotuner picks, eager and as a hipGraph).
 """
 import argparse
 import json
@@ -375,9 +375,10 @@ def bench_phase2(ctx, torch, blink, synth, steps, warmup):
     return out
 
 
-def bench_uneven(ctx, torch, blink, synth, reps):
-    """One persistent launch over 4096 images of 512^2, 1024^2 and 2048^2 (70-300 MHz, 70-100% of
-    8128 baselines each), FP32 and split forms, eager and replayed from a hipGraph."""
+def bench_uneven(ctx, torch, blink, synth, reps, desc_form="auto"):
+    """One blink_image_batch_desc call over 4096 images of 512^2, 1024^2 and 2048^2 (70-300 MHz,
+    70-100% of 8128 baselines each), FP32 and split forms, eager and replayed from a hipGraph; the
+    descriptor autotuner picks the form (staged or persistent) and its plan for each."""
     import numpy as np
 
     lay = synth.uneven_layout()
@@ -390,16 +391,34 @@ def bench_uneven(ctx, torch, blink, synth, reps):
     n_img = lay["n_img"]
     ws = torch.empty(blink.desc_workspace_size(n_img, lay["max_b"], lay["max_n"], 1024), dtype=torch.uint8,
                      device=dev)
-    model = int(sum(12 * int(n) ** 2 + 9 * int(b) for n, b in zip(lay["grid_n"], lay["n_baselines"])))
+    # per image: the nonzero half-spectrum columns written and read back (16 N E), the image
+    # (4 N^2) and 9 B per baseline; E = 1 + the largest |ku| over the image's baselines (none is
+    # flagged in this batch)
+    ext = []
+    for i in range(n_img):
+        n, o, nb = int(lay["grid_n"][i]), int(lay["uvw_offset"][i]), int(lay["n_baselines"][i])
+        k = lay["freq_hz"][i] / SPEED_OF_LIGHT * n * lay["pixel_scale"][i]
+        u = np.rint(lay["uvw_ext"][o:o + nb, :2] * k)
+        keep = (np.abs(u) < n / 2).all(axis=1)
+        ext.append(int(np.abs(u[keep, 0]).max()) + 1 if keep.any() else 0)
+    model = int(sum(16 * int(n) * e + 4 * int(n) ** 2 + 9 * int(b)
+                    for n, e, b in zip(lay["grid_n"], ext, lay["n_baselines"])))
     sizes = {int(n): int((lay["grid_n"] == n).sum()) for n in sorted(set(lay["grid_n"].tolist()))}
     out = {"workload": "uneven: 4096 images, f = 70-300 MHz, N = 512 / 1024 / 2048 below 120 / 200 MHz / above, "
                        "pixel scale per channel so every baseline fits, 70-100% of 8128 baselines per image",
-           "images": n_img, "images_per_size": sizes, "bytes_model_total": model}
+           "images": n_img, "images_per_size": sizes, "bytes_model_total": model,
+           "column_extent_mean_fraction": round(float(np.mean([e / (n / 2) for e, n in zip(ext, lay["grid_n"])])), 3)}
     for name, prec in FORMS:
-        # the descriptor autotuner picks the mode (one launch, or one per size), block and workgroups
-        plan, tune_ms = ctx.autotune_desc(desc, vis, uvw, None, images, lay["max_b"], lay["max_n"], precision=prec,
-                                          workspace=ws)
-        log(f"uneven {name}: autotuned plan {plan} ({tune_ms:.2f} ms)")
+        if desc_form == "auto":
+            # the descriptor autotuner picks the form (staged or persistent) and the persistent form's block
+            # and workgroups
+            plan, tune_ms = ctx.autotune_desc(desc, vis, uvw, None, images, lay["max_b"], lay["max_n"],
+                                              precision=prec, workspace=ws)
+            log(f"uneven {name}: autotuned plan {plan} ({tune_ms:.2f} ms)")
+        else:
+            ctx.set_desc_plan(1024 if desc_form == "persistent" and prec == 0 else 512, 0,
+                              form=blink.DESC_STAGED if desc_form == "staged" else blink.DESC_PERSISTENT)
+            plan = ctx.get_desc_plan()
 
         def run(i, prec=prec):
             ctx.blink_image_batch_desc(desc, vis, uvw, None, images, lay["max_b"], lay["max_n"], precision=prec,
@@ -435,6 +454,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the split-precision and uneven-batch measurements beside the headline")
     ap.add_argument("--form-steps", type=int, default=20, help="steps per split-precision form measurement")
+    ap.add_argument("--desc-form", choices=("auto", "staged", "persistent"), default="auto",
+                    help="form of the uneven batch: auto runs the descriptor autotuner per precision (default); "
+                         "staged or persistent fix the form with its default plan (for profiles)")
     ap.add_argument("--no-cache-probe", action="store_true",
                     help="skip the pass with image groups whose half spectra exceed the last-level cache (profiles "
                          "of the headline kernels use it so that every traced launch has the headline plan)")
@@ -659,7 +681,7 @@ def main():
         if "precision" in want:
             forms["precision-4096"], precision_samples = bench_precision_workload(ctx, torch, blink, synth, 3, 1)
         if "uneven" in want:
-            forms["uneven"] = bench_uneven(ctx, torch, blink, synth, 3)
+            forms["uneven"] = bench_uneven(ctx, torch, blink, synth, 3, args.desc_form)
         if "phase2" in want:
             forms["phase2-2048"] = bench_phase2(ctx, torch, blink, synth, 2, 1)
 
