@@ -12,9 +12,12 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libblink.so")
-# (source, extra defines): split.hip is built once per split precision (1 = FP16, 2 = BF16).
+# (source, extra defines): split.hip is built once per split precision (1 = FP16, 2 = BF16),
+# staged.hip once per precision form (0 = FP32).
 UNITS = [("kernels.hip", []), ("persistent.hip", []), ("api.hip", []), ("correlate.hip", []),
-         ("split.hip", ["-DBLINK_SPLIT_PREC=1"]), ("split.hip", ["-DBLINK_SPLIT_PREC=2"])]
+         ("split.hip", ["-DBLINK_SPLIT_PREC=1"]), ("split.hip", ["-DBLINK_SPLIT_PREC=2"]),
+         ("staged.hip", ["-DBLINK_STAGED_PREC=0"]), ("staged.hip", ["-DBLINK_STAGED_PREC=1"]),
+         ("staged.hip", ["-DBLINK_STAGED_PREC=2"])]
 SOURCES = sorted({os.path.join(CSRC, f) for f, _ in UNITS})
 
 HIPCC_FLAGS = [

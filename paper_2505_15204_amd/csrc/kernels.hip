@@ -420,20 +420,20 @@ hipError_t launch_dense_colfft(const float2* grids, int n_img, int logn, int shi
 hipError_t launch_chunk_colfft(const DescArgs& a, int chunk, int logn, int strip, int col_loop, int slots, int prec,
                                hipStream_t s) {
   switch (prec) {
-    case BLINK_PREC_FP32: return PrecLaunch<BLINK_PREC_FP32>::chunk_colfft(a, chunk, logn, strip, col_loop, slots, s);
+    case BLINK_PREC_FP32: return StagedLaunch<BLINK_PREC_FP32>::colfft(a, chunk, logn, strip, col_loop, slots, s);
     case BLINK_PREC_SPLIT_F16:
-      return PrecLaunch<BLINK_PREC_SPLIT_F16>::chunk_colfft(a, chunk, logn, strip, col_loop, slots, s);
+      return StagedLaunch<BLINK_PREC_SPLIT_F16>::colfft(a, chunk, logn, strip, col_loop, slots, s);
     case BLINK_PREC_SPLIT_BF16:
-      return PrecLaunch<BLINK_PREC_SPLIT_BF16>::chunk_colfft(a, chunk, logn, strip, col_loop, slots, s);
+      return StagedLaunch<BLINK_PREC_SPLIT_BF16>::colfft(a, chunk, logn, strip, col_loop, slots, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_chunk_row(const DescArgs& a, int chunk, int logn, int tpb, int slots, int prec, hipStream_t s) {
   switch (prec) {
-    case BLINK_PREC_FP32: return PrecLaunch<BLINK_PREC_FP32>::chunk_row(a, chunk, logn, tpb, slots, s);
-    case BLINK_PREC_SPLIT_F16: return PrecLaunch<BLINK_PREC_SPLIT_F16>::chunk_row(a, chunk, logn, tpb, slots, s);
-    case BLINK_PREC_SPLIT_BF16: return PrecLaunch<BLINK_PREC_SPLIT_BF16>::chunk_row(a, chunk, logn, tpb, slots, s);
+    case BLINK_PREC_FP32: return StagedLaunch<BLINK_PREC_FP32>::row(a, chunk, logn, tpb, slots, s);
+    case BLINK_PREC_SPLIT_F16: return StagedLaunch<BLINK_PREC_SPLIT_F16>::row(a, chunk, logn, tpb, slots, s);
+    case BLINK_PREC_SPLIT_BF16: return StagedLaunch<BLINK_PREC_SPLIT_BF16>::row(a, chunk, logn, tpb, slots, s);
     default: return hipErrorInvalidValue;
   }
 }

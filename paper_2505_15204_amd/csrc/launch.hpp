@@ -155,15 +155,22 @@ hipError_t launch_image_average(const float* in, int T, int C, int P, int logn, 
 
 struct DescArgs;
 
+// The staged form of the uneven-batch path (staged.hip, one object per precision): the fused
+// column kernel and the row kernel of one chunk (images of one grid size 2^logn, at most `slots`
+// of them) with strip width `strip` and `tpb` row-pair transforms.
+template <int PREC>
+struct StagedLaunch {
+  static hipError_t colfft(const DescArgs& a, int chunk, int logn, int strip, int col_loop, int slots, hipStream_t s);
+  static hipError_t row(const DescArgs& a, int chunk, int logn, int tpb, int slots, hipStream_t s);
+};
+extern template struct StagedLaunch<BLINK_PREC_FP32>;
+extern template struct StagedLaunch<BLINK_PREC_SPLIT_F16>;
+extern template struct StagedLaunch<BLINK_PREC_SPLIT_BF16>;
+
 // The same three launchers for one precision form; FP32 is built in kernels.hip, each split
-// precision in its own object from split.hip. chunk_colfft and chunk_row are the staged form of
-// the uneven-batch path: the fused column kernel and the row kernel of one chunk (images of one
-// grid size 2^logn, at most `slots` of them) with strip width `strip` and `tpb` row-pair transforms.
+// precision in its own object from split.hip.
 template <int PREC>
 struct PrecLaunch {
-  static hipError_t chunk_colfft(const DescArgs& a, int chunk, int logn, int strip, int col_loop, int slots,
-                                 hipStream_t s);
-  static hipError_t chunk_row(const DescArgs& a, int chunk, int logn, int tpb, int slots, hipStream_t s);
   static hipError_t grid_colfft(const ColArgs& a, int n_img, int strip, const float2* tw, hipStream_t s);
   static hipError_t dense_colfft(const float2* grids, int n_img, int logn, int shift, float2* H, const float2* tw,
                                  const uint4* dft_ops, hipStream_t s);
