@@ -318,7 +318,7 @@ blink_status blink_dedisperse(blink_ctx ctx, const float *images, int T, int C, 
  *                          and image each one alone (binning, gridding + column FFT, row FFT)
  *                          through a per-workgroup intermediate slot;
  *   BLINK_DESC_STAGED      one launch bins every image; then, per chunk of images of one grid size
- *                          whose half spectra fit a 192 MiB buffer (sized for the last-level
+ *                          whose half spectra fit a 256 MiB buffer (sized for the last-level
  *                          cache), a column launch and a row launch of blink_image_batch's fused
  *                          column and row kernels for that size, reading each image's visibilities
  *                          and output offset from its descriptor.

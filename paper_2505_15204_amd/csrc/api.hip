@@ -1081,7 +1081,10 @@ DescLayout desc_layout(size_t n_img, size_t max_b, size_t max_n, size_t slots) {
 
 // Staged form: per-image placements, strip offsets, counts and extents (by position in the
 // order), the chunk table and the chunk buffer, which holds as many of the largest images' half
-// spectra as fit 192 MiB of the last-level cache (at least one, at most the batch).
+// spectra as fit 256 MiB (at least one, at most the batch). An image touches only the columns
+// below its extent, so a chunk's working set is that fraction of the buffer (about 220 MiB with
+// the uneven benchmark's extents, which the 256 MB last-level cache holds between the chunk's
+// two launches; 128, 192, 320, 384 and 512 MiB were slower on it).
 struct StagedLayout {
   size_t valid, order, counter, status, chunks, plc, strip_off, kept, occ, ext, H, total;
   int max_chunks;
@@ -1094,7 +1097,7 @@ StagedLayout staged_layout(size_t n_img, size_t max_b, size_t max_n) {
   int max_logn = 0;
   while ((size_t(1) << max_logn) < max_n) ++max_logn;
   const int64_t h = (int64_t)max_n * (int64_t)(max_n / 2);
-  int64_t cap = ((int64_t)192 << 20) / (h * (int64_t)sizeof(float2));
+  int64_t cap = ((int64_t)256 << 20) / (h * (int64_t)sizeof(float2));
   if (cap > (int64_t)n_img) cap = (int64_t)n_img;   // a batch of few images needs no more
   if (cap < 1) cap = 1;
   L.chunk_elems = h * cap;

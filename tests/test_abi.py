@@ -123,8 +123,8 @@ def test_desc_workspace_and_validation(L):
     assert s >= 10 * 2 * 100 * 8 + 10 * 256 * 128 * 8
     assert blink.desc_workspace_size(10, 100, 256, 8) >= s
     assert blink.desc_workspace_size(10, 100, 256, 64) == blink.desc_workspace_size(10, 100, 256, 10)
-    # many workgroups: the persistent slots (256 KiB each) outgrow the staged form's 192 MiB buffer
-    assert blink.desc_workspace_size(2000, 100, 256, 1000) > blink.desc_workspace_size(2000, 100, 256, 800)
+    # many workgroups: the persistent slots (256 KiB each) outgrow the staged form's 256 MiB buffer
+    assert blink.desc_workspace_size(2000, 100, 256, 2000) > blink.desc_workspace_size(2000, 100, 256, 1500)
     with pytest.raises(blink.BlinkError):
         blink.desc_workspace_size(10, 100, 300, 4)
     dummy = ctypes.c_void_p(0x1000)
