@@ -487,7 +487,42 @@ __device__ __forceinline__ void row_task(const float2* __restrict__ H, int rowbl
     const float2* h1 = H + (size_t)(2 * r) * HALF;
     const float2* h2 = h1 + HALF;
     float2 v[P::R];
-    if constexpr (T % 64 == 0) {
+    if constexpr (T == 64) {
+      // One wavefront per transform (N = 1024). Lane lt loads only its columns below N/2
+      // (e = lt + 64 m, m < R/2) and takes the values of the columns above, Z[N - e], from lane
+      // 64 - lt, which loaded column N - e's half-row entries as its own: one cross-lane read per
+      // float (ds_bpermute, no memory access) instead of loading every entry twice.
+      const int ru = __builtin_amdgcn_readfirstlane(r);
+      const float2* g1 = H + (size_t)(2 * ru) * HALF;
+      const __amdgpu_buffer_rsrc_t r1 = half_row_rsrc(g1, cmin(ext, HALF));
+      const __amdgpu_buffer_rsrc_t r2 = half_row_rsrc(g1 + HALF, cmin(ext, HALF));
+      constexpr int HR = P::R / 2;
+      float2 zm[HR];                         // Z at N - e of this lane's columns e
+      float2 a0 = make_float2(0.f, 0.f), b0 = a0;
+#pragma unroll
+      for (int m = 0; m < HR; ++m) {
+        const int e = lt + m * T;
+        const float2 a = half_row_load(r1, e), b = half_row_load(r2, e);
+        v[m] = hermitian_combine(a, b, e, HALF);
+        zm[m] = make_float2(a.x + b.y, b.x - a.y);
+        if (m == 0) {
+          a0 = a;
+          b0 = b;
+        }
+      }
+      const int src = ((T - lt) & (T - 1)) << 2;
+#pragma unroll
+      for (int m = HR; m < P::R; ++m) {
+        const float2 z = zm[P::R - 1 - m];
+        v[m] = make_float2(__int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(z.x))),
+                           __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(z.y))));
+      }
+      if (lt == 0) {                         // columns N/2 and N - 64 m are this lane's own
+        v[HR] = make_float2(a0.y, b0.y);
+#pragma unroll
+        for (int m = HR + 1; m < P::R; ++m) v[m] = zm[P::R - m];
+      }
+    } else if constexpr (T % 64 == 0) {
       // a transform spans whole wavefronts: its two rows are the same for every lane of one
       const int ru = __builtin_amdgcn_readfirstlane(r);
       const float2* g1 = H + (size_t)(2 * ru) * HALF;
