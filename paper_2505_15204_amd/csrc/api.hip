@@ -214,6 +214,7 @@ ConvLayout conv_layout(size_t Q, int P, int B, int logn, int width, size_t h_ima
   L.bins.off = c.take(Q, (nstrips + 1) * sizeof(int));
   L.bins.kept = c.take(Q, sizeof(int));
   L.bins.occ = c.take(Q, (size_t)P * sizeof(int));
+  L.bins.ext = c.take(Q, sizeof(int));
   L.corr = c.take(N, sizeof(float));
   L.H = c.take(h_images, N * (N / 2) * sizeof(float2));
   L.total = c.off;
@@ -982,6 +983,7 @@ blink_status blink_image_batch_conv(blink_ctx ctx, const blink_cf32* vis, const 
     ba.occ = (int*)(ws + L.bins.occ);
     ba.cell_idx = nullptr;
     ba.n_out = n_out;
+    ba.ext = (int*)(ws + L.bins.ext);
     {
       KernelTimer kt(ctx, BLINK_KERNEL_BIN, s);
       e = blink::launch_bin_conv(ba, cp, L.rec_stride, s);
@@ -1001,9 +1003,11 @@ blink_status blink_image_batch_conv(blink_ctx ctx, const blink_cf32* vis, const 
     ca.occ = ba.occ;
     ca.dft_ops = ctx->dft_ops;
     ca.rec_stride = L.rec_stride;
+    ca.ext = ba.ext;
     const int n_img = q * P;
     blink::RowArgs ra{};
     ra.H = ca.H;
+    ra.ext = ba.ext;
     ra.logn = logn;
     ra.P = P;
     ra.wmode = blink::kWeightNatural;

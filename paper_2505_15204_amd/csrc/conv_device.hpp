@@ -77,12 +77,13 @@ __device__ __forceinline__ void for_each_conv_strip(int j0, int n, int N, int lo
 // rec holds at most 2 B (ceil(W / 2^log_strip) + 2) records; off[0..nstrips] gets the offsets.
 __device__ inline void bin_visibilities_conv(const double* __restrict__ uvw, const uint8_t* __restrict__ fl, int B,
                                              double k, int logn, int log_strip, ConvSpec cs, ConvRec* __restrict__ rec,
-                                             int* __restrict__ off, int* kept_out, int* nout_out, BinShared& sh) {
+                                             int* __restrict__ off, int* kept_out, int* nout_out, BinShared& sh,
+                                             int* ext_out = nullptr) {
   const int N = 1 << logn;
   const int nstrips = (N / 2) >> log_strip;
   const double half = (double)(N / 2), h = 0.5 * cs.width;
   for (int i = threadIdx.x; i <= nstrips; i += blockDim.x) sh.cnt[i] = 0;
-  if (threadIdx.x < 2) sh.red[threadIdx.x] = 0;
+  if (threadIdx.x < 3) sh.red[threadIdx.x] = 0;
   __syncthreads();
   int kept = 0, outside = 0;
   // pass 1: counts per strip
@@ -107,6 +108,10 @@ __device__ inline void bin_visibilities_conv(const double* __restrict__ uvw, con
   if (kept) atomicAdd(&sh.red[0], kept);
   if (outside) atomicAdd(&sh.red[1], outside);
   __syncthreads();
+  // column extent: the end of the last strip any tap reaches (read before the scan's first barrier)
+  if (ext_out)
+    for (int i = threadIdx.x; i < nstrips; i += blockDim.x)
+      if (sh.cnt[i] > 0) atomicMax(&sh.red[2], i + 1);
   block_exclusive_scan(sh.cnt, nstrips, sh.wave);
   for (int i = threadIdx.x; i <= nstrips; i += blockDim.x) off[i] = sh.cnt[i];
   if (threadIdx.x == 0) {
@@ -114,6 +119,7 @@ __device__ inline void bin_visibilities_conv(const double* __restrict__ uvw, con
     if (nout_out) *nout_out = sh.red[1];
   }
   __syncthreads();
+  if (ext_out && threadIdx.x == 0) *ext_out = sh.red[2] << log_strip;
   // pass 2: records
   for (int b = threadIdx.x; b < B; b += blockDim.x) {
     if (fl && fl[b]) continue;

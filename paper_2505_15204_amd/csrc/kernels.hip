@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_conv(BinArgs a, ConvSpec cs
   bin_visibilities_conv(a.uvw + (size_t)t * a.B * 3, a.flags ? a.flags + (size_t)tc * a.B : nullptr, a.B, k, a.logn,
                         a.log_strip, cs, reinterpret_cast<ConvRec*>(a.plc) + (size_t)tcl * rec_stride,
                         a.strip_off + (size_t)tcl * (nstrips + 1), a.n_kept + tcl, a.n_out ? a.n_out + tc : nullptr,
-                        sh);
+                        sh, a.ext ? a.ext + tcl : nullptr);
 }
 
 int conv_records_per_pair(int B, int width, int min_strip) {

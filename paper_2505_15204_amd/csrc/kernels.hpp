@@ -97,6 +97,8 @@ __global__ __launch_bounds__(fft_block(S * FftPlan<LOGN>::T, PREC)) void k_grid_
   const int slot = blockIdx.x, img = a.img0 + slot, strip = blockIdx.y;
   const int tcl = img / a.P;
   const int nstrips = (N / 2) / S;
+  // strips past the column extent receive no tap; the row pass reads their columns as zero
+  if (a.ext && strip >= a.ext[tcl] / S) return;   // uniform over the workgroup
   for (int i = threadIdx.x; i < TW; i += NT) stw[i] = twg[i];   // visible after the task's first barrier
   const int* so = a.strip_off + (size_t)tcl * (nstrips + 1);
   const ConvRec* rec = reinterpret_cast<const ConvRec*>(a.plc) + (size_t)tcl * a.rec_stride;
