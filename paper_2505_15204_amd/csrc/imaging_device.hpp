@@ -451,22 +451,95 @@ __device__ __forceinline__ float2 half_row_load(__amdgpu_buffer_rsrc_t r, int id
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, idx * (int)sizeof(float2), 0, 0));
 }
 
+// The first stage's inputs of the row-pair transform of rows 2r, 2r + 1 held by this thread:
+// v[m] = Z[lt + T m], Z the Hermitian-extended pair (see row_task). Threads with active == false
+// load nothing (the T = 64 form takes every lane of the wavefront, which is one transform).
+template <int LOGN>
+__device__ __forceinline__ void load_row_pair(const float2* __restrict__ H, int r, int lt, bool active, int ext,
+                                              float2 (&v)[FftPlan<LOGN>::R]) {
+  using P = FftPlan<LOGN>;
+  constexpr int N = P::N, T = P::T, HALF = N / 2;
+  const float2* h1 = H + (size_t)(2 * r) * HALF;
+  const float2* h2 = h1 + HALF;
+  if constexpr (T == 64) {
+    // One wavefront per transform (N = 1024). Lane lt loads only its columns below N/2
+    // (e = lt + 64 m, m < R/2) and takes the values of the columns above, Z[N - e], from lane
+    // 64 - lt, which loaded column N - e's half-row entries as its own: one cross-lane read per
+    // float (ds_bpermute, no memory access) instead of loading every entry twice.
+    const int ru = __builtin_amdgcn_readfirstlane(r);
+    const float2* g1 = H + (size_t)(2 * ru) * HALF;
+    const __amdgpu_buffer_rsrc_t r1 = half_row_rsrc(g1, cmin(ext, HALF));
+    const __amdgpu_buffer_rsrc_t r2 = half_row_rsrc(g1 + HALF, cmin(ext, HALF));
+    constexpr int HR = P::R / 2;
+    float2 zm[HR];                         // Z at N - e of this lane's columns e
+    float2 a0 = make_float2(0.f, 0.f), b0 = a0;
+#pragma unroll
+    for (int m = 0; m < HR; ++m) {
+      const int e = lt + m * T;
+      const float2 a = half_row_load(r1, e), b = half_row_load(r2, e);
+      v[m] = hermitian_combine(a, b, e, HALF);
+      zm[m] = make_float2(a.x + b.y, b.x - a.y);
+      if (m == 0) {
+        a0 = a;
+        b0 = b;
+      }
+    }
+    const int src = ((T - lt) & (T - 1)) << 2;
+#pragma unroll
+    for (int m = HR; m < P::R; ++m) {
+      const float2 z = zm[P::R - 1 - m];
+      v[m] = make_float2(__int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(z.x))),
+                         __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(z.y))));
+    }
+    if (lt == 0) {                         // columns N/2 and N - 64 m are this lane's own
+      v[HR] = make_float2(a0.y, b0.y);
+#pragma unroll
+      for (int m = HR + 1; m < P::R; ++m) v[m] = zm[P::R - m];
+    }
+  } else if constexpr (T % 64 == 0) {
+    // a transform spans whole wavefronts: its two rows are the same for every lane of one
+    const int ru = __builtin_amdgcn_readfirstlane(r);
+    const float2* g1 = H + (size_t)(2 * ru) * HALF;
+    const __amdgpu_buffer_rsrc_t r1 = half_row_rsrc(g1, cmin(ext, HALF));
+    const __amdgpu_buffer_rsrc_t r2 = half_row_rsrc(g1 + HALF, cmin(ext, HALF));
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < P::R; ++m) {
+        const int e = lt + m * T, idx = hermitian_index(e, HALF);
+        v[m] = hermitian_combine(half_row_load(r1, idx), half_row_load(r2, idx), e, HALF);
+      }
+    }
+  } else if (active) {
+#pragma unroll
+    for (int m = 0; m < P::R; ++m) v[m] = hermitian_pair(h1, h2, lt + m * T, N, ext);
+  }
+}
+
 template <int LOGN, int TPB, int PREC = kPrecFp32>
 __device__ __forceinline__ void row_task(const float2* __restrict__ H, int rowblk, float scale, float* __restrict__ out,
                                          const float2* __restrict__ tw, float2* sbuf, SplitCtx sp = {},
                                          const float* __restrict__ corr = nullptr, int ext = 1 << 30) {
   using P = FftPlan<LOGN>;
-  constexpr int N = P::N, T = P::T, NP = P::NP, HALF = N / 2;
+  constexpr int N = P::N, T = P::T, NP = P::NP;
   if constexpr (PREC != kPrecFp32 && LOGN >= 4) {
-    if (threadIdx.x == 0) *sp.s_max = 0u;
-    __syncthreads();   // the caller's twiddle table is visible
-    const float2* hb = H + (size_t)(2 * rowblk * TPB) * HALF;
+    // Z of every transform is loaded as in the FP32 form (one transform per T threads) and staged
+    // into the row buffer, from which the matrix-core stages read their operands.
+    {
+      const int j = (int)threadIdx.x / T, lt = (int)threadIdx.x % T;
+      const bool active = j < TPB;
+      float2 v[P::R];
+      load_row_pair<LOGN>(H, rowblk * TPB + (active ? j : 0), lt, active, ext, v);
+      if (threadIdx.x == 0) *sp.s_max = 0u;
+      if (active) {
+#pragma unroll
+        for (int m = 0; m < P::R; ++m) sbuf[j * NP + pad_index(lt + m * T)] = v[m];
+      }
+    }
+    __syncthreads();   // the staged rows and the caller's twiddle table are visible
     float* ob = out + (size_t)(2 * rowblk * TPB) * N;
-    auto load = [&](int c, int e) {
-      return hermitian_pair(hb + (size_t)(2 * c) * HALF, hb + (size_t)(2 * c + 1) * HALF, e, N, ext);
-    };
+    auto load = [](int, int) { return make_float2(0.f, 0.f); };   // unused: the inputs are in sbuf
     if (corr) {
-      fft_inverse_split<LOGN, PREC, false, false>(sbuf, TPB, tw, load, [&](int c, int e, float2 z) {
+      fft_inverse_split<LOGN, PREC, false, true>(sbuf, TPB, tw, load, [&](int c, int e, float2 z) {
         const int y1 = 2 * (rowblk * TPB + c);
         float* o1 = ob + (size_t)(2 * c) * N;
         const float cx = corr[e] * scale;
@@ -474,7 +547,7 @@ __device__ __forceinline__ void row_task(const float2* __restrict__ H, int rowbl
         __builtin_nontemporal_store(z.y * cx * corr[y1 + 1], &o1[N + e]);
       }, sp);
     } else {
-      fft_inverse_split<LOGN, PREC, false, false>(sbuf, TPB, tw, load, [&](int c, int e, float2 z) {
+      fft_inverse_split<LOGN, PREC, false, true>(sbuf, TPB, tw, load, [&](int c, int e, float2 z) {
         float* o1 = ob + (size_t)(2 * c) * N;
         __builtin_nontemporal_store(z.x * scale, &o1[e]);
         __builtin_nontemporal_store(z.y * scale, &o1[N + e]);
@@ -484,61 +557,8 @@ __device__ __forceinline__ void row_task(const float2* __restrict__ H, int rowbl
     const int j = (int)threadIdx.x / T, lt = (int)threadIdx.x % T;
     const bool active = j < TPB;
     const int r = rowblk * TPB + (active ? j : 0);
-    const float2* h1 = H + (size_t)(2 * r) * HALF;
-    const float2* h2 = h1 + HALF;
     float2 v[P::R];
-    if constexpr (T == 64) {
-      // One wavefront per transform (N = 1024). Lane lt loads only its columns below N/2
-      // (e = lt + 64 m, m < R/2) and takes the values of the columns above, Z[N - e], from lane
-      // 64 - lt, which loaded column N - e's half-row entries as its own: one cross-lane read per
-      // float (ds_bpermute, no memory access) instead of loading every entry twice.
-      const int ru = __builtin_amdgcn_readfirstlane(r);
-      const float2* g1 = H + (size_t)(2 * ru) * HALF;
-      const __amdgpu_buffer_rsrc_t r1 = half_row_rsrc(g1, cmin(ext, HALF));
-      const __amdgpu_buffer_rsrc_t r2 = half_row_rsrc(g1 + HALF, cmin(ext, HALF));
-      constexpr int HR = P::R / 2;
-      float2 zm[HR];                         // Z at N - e of this lane's columns e
-      float2 a0 = make_float2(0.f, 0.f), b0 = a0;
-#pragma unroll
-      for (int m = 0; m < HR; ++m) {
-        const int e = lt + m * T;
-        const float2 a = half_row_load(r1, e), b = half_row_load(r2, e);
-        v[m] = hermitian_combine(a, b, e, HALF);
-        zm[m] = make_float2(a.x + b.y, b.x - a.y);
-        if (m == 0) {
-          a0 = a;
-          b0 = b;
-        }
-      }
-      const int src = ((T - lt) & (T - 1)) << 2;
-#pragma unroll
-      for (int m = HR; m < P::R; ++m) {
-        const float2 z = zm[P::R - 1 - m];
-        v[m] = make_float2(__int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(z.x))),
-                           __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(z.y))));
-      }
-      if (lt == 0) {                         // columns N/2 and N - 64 m are this lane's own
-        v[HR] = make_float2(a0.y, b0.y);
-#pragma unroll
-        for (int m = HR + 1; m < P::R; ++m) v[m] = zm[P::R - m];
-      }
-    } else if constexpr (T % 64 == 0) {
-      // a transform spans whole wavefronts: its two rows are the same for every lane of one
-      const int ru = __builtin_amdgcn_readfirstlane(r);
-      const float2* g1 = H + (size_t)(2 * ru) * HALF;
-      const __amdgpu_buffer_rsrc_t r1 = half_row_rsrc(g1, cmin(ext, HALF));
-      const __amdgpu_buffer_rsrc_t r2 = half_row_rsrc(g1 + HALF, cmin(ext, HALF));
-      if (active) {
-#pragma unroll
-        for (int m = 0; m < P::R; ++m) {
-          const int e = lt + m * T, idx = hermitian_index(e, HALF);
-          v[m] = hermitian_combine(half_row_load(r1, idx), half_row_load(r2, idx), e, HALF);
-        }
-      }
-    } else if (active) {
-#pragma unroll
-      for (int m = 0; m < P::R; ++m) v[m] = hermitian_pair(h1, h2, lt + m * T, N, ext);
-    }
+    load_row_pair<LOGN>(H, r, lt, active, ext, v);
     __syncthreads();   // the caller's twiddle table is visible
     float* o1 = out + (size_t)(2 * r) * N;
     float* o2 = o1 + N;
