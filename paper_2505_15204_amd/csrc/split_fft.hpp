@@ -219,6 +219,22 @@ __device__ __forceinline__ float block_max_abs(float m, unsigned* s_max) {
   return __uint_as_float(*s_max);
 }
 
+// Largest |re| or |im| over the wave (no LDS word, no barrier).
+__device__ __forceinline__ float wave_max_abs(float m) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  return m;
+}
+
+// Orders the LDS accesses of one wave across its lanes: the accesses before it are performed
+// before those after it. A wave's LDS instructions are executed in issue order, so this only has
+// to keep the compiler from moving accesses across it; it emits no barrier instruction.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Power of two that brings a maximum magnitude mx into [32, 64).
 __device__ __forceinline__ int f16_scale_exponent(float mx) {
   if (!(mx > 0.f) || !isfinite(mx)) return 0;
@@ -235,6 +251,12 @@ __device__ __forceinline__ int f16_scale_exponent(float mx) {
 // block size is a multiple of 64 and at least ntrans * N / 16. `tw` is the twiddle table of N in
 // the stage-ordered twiddle layout (visible to the block on entry); sp.s_max as for block_max_abs (FP16 only)
 // and sp.ops the DFT operand table.
+//
+// Up to N = 1024 (N / 16 <= 64 butterflies per stage) every butterfly and every thread of the
+// FP32 stage of transform c lies in wave 64 c / (N / 16): each wave owns whole transforms, so the
+// stages exchange data through LDS within the wave only and are ordered by wave_lds_order instead
+// of workgroup barriers, and the FP16 scale is taken per wave (every transform of a wave shares
+// one power of two). Larger N spread a transform over several waves and use workgroup barriers.
 template <int LOGN, int PREC, bool ToLds, bool FromBuf, class Load, class Sink>
 __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const float2* __restrict__ tw, Load load,
                                                   Sink sink, SplitCtx sp) {
@@ -245,6 +267,12 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
   const DftOperands<PREC> F = dft16_operands<PREC>(sp.ops);
   const int lane = threadIdx.x & 63, n = lane & 31, g = lane >> 5, w = threadIdx.x >> 6;
   const int total = ntrans * NB;
+  constexpr bool WAVE_LOCAL = NB <= 64;
+  // orders the stages: within the wave, or over the workgroup
+  auto stage_sync = [] {
+    if constexpr (WAVE_LOCAL) wave_lds_order();
+    else __syncthreads();
+  };
 
   // The butterfly of batch h of this lane, and whether it exists. A lane without one gets
   // butterfly 0 (which always exists), so its loads need no branch (their values are discarded):
@@ -313,7 +341,13 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int i = 0; i < 8; ++i) m = fmaxf(m, fmaxf(fabsf(x[h][i].x), fabsf(x[h][i].y)));
-    const int e = f16_scale_exponent(block_max_abs(m, sp.s_max));   // also: every load of buf is done
+    int e;
+    if constexpr (WAVE_LOCAL) {
+      e = f16_scale_exponent(wave_max_abs(m));
+      wave_lds_order();                  // every load of buf is done before the in-place stores
+    } else {
+      e = f16_scale_exponent(block_max_abs(m, sp.s_max));   // also: every load of buf is done
+    }
     const float s = ldexpf(1.f, e);
     u = ldexpf(1.f, -e);
 #pragma unroll
@@ -321,7 +355,7 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
 #pragma unroll
       for (int i = 0; i < 8; ++i) x[h][i] = cscale(x[h][i], s);
   } else {
-    __syncthreads();                     // every load of buf is done before the in-place stores
+    stage_sync();                        // every load of buf is done before the in-place stores
   }
   using One = std::integral_constant<int, 1>;
   constexpr bool ONE_STAGE = (P::NST == 1);
@@ -334,7 +368,7 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
     if constexpr (ToLds) __syncthreads();
     return;
   } else {
-    __syncthreads();
+    stage_sync();
     // ---- later stages
     auto mfma_stage = [&](auto ns_tag, auto last_tag) {
       constexpr int NS = decltype(ns_tag)::value;
@@ -350,7 +384,7 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
           x[h][i] = cmul(v, stage_twiddle<NS>(tw, k, q));
         }
       }
-      __syncthreads();
+      stage_sync();
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const f32x16 r = dft16_mfma<PREC>(x[h], F);
@@ -367,7 +401,7 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
         stage_load_lds<N, 16, T, RAD>(v, buf + c * NP, lt);
         stage_compute<N, 16, T, NS, RAD>(v, lt, tw);
       }
-      if constexpr (ToLds) __syncthreads();
+      if constexpr (ToLds) stage_sync();
       if (active) {
         constexpr int Q = 16 / RAD;
 #pragma unroll
@@ -394,7 +428,7 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
       }
     } else {
       mfma_stage(S16{}, B0{});
-      __syncthreads();
+      stage_sync();
       using S256 = std::integral_constant<int, 256>;
       if constexpr (P::R2 == 16) {
         mfma_stage(S256{}, B1{});
