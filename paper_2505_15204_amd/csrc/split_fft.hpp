@@ -16,8 +16,9 @@
 // of 16, stay in FP32 on the vector ALUs. The reduced-precision study is left open by the paper
 // (Section 10, future work); this is one design for it.
 //
-// FP16 range: the inputs of a task (the columns of a strip, or the row pairs of a row block) are
-// scaled by one power of two so that their largest real or imaginary part lies in [32, 64). A
+// FP16 range: the inputs of a task (the columns of a strip, or the row pairs of a row block; up
+// to N = 1024 those of one wave, which holds whole transforms) are scaled by one power of two so
+// that their largest real or imaginary part lies in [32, 64). A
 // radix-16 stage with unit-modulus twiddles grows that bound by at most 16 sqrt(2) = 2^4.5, so
 // the inputs of the third radix-16 stage stay below 2^15 and no 16-bit operand overflows; the
 // outputs are multiplied back by the exact inverse power of two. BF16 has the FP32 exponent
@@ -226,15 +227,6 @@ __device__ __forceinline__ float wave_max_abs(float m) {
   return m;
 }
 
-// Orders the LDS accesses of one wave across its lanes: the accesses before it are performed
-// before those after it. A wave's LDS instructions are executed in issue order, so this only has
-// to keep the compiler from moving accesses across it; it emits no barrier instruction.
-__device__ __forceinline__ void wave_lds_order() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Power of two that brings a maximum magnitude mx into [32, 64).
 __device__ __forceinline__ int f16_scale_exponent(float mx) {
   if (!(mx > 0.f) || !isfinite(mx)) return 0;
@@ -254,9 +246,10 @@ __device__ __forceinline__ int f16_scale_exponent(float mx) {
 //
 // Up to N = 1024 (N / 16 <= 64 butterflies per stage) every butterfly and every thread of the
 // FP32 stage of transform c lies in wave 64 c / (N / 16): each wave owns whole transforms, so the
-// stages exchange data through LDS within the wave only and are ordered by wave_lds_order instead
-// of workgroup barriers, and the FP16 scale is taken per wave (every transform of a wave shares
-// one power of two). Larger N spread a transform over several waves and use workgroup barriers.
+// stages exchange data through LDS within the wave only and are ordered by stage_sync's
+// wavefront-scope fences instead of workgroup barriers, and the FP16 scale is taken per wave
+// (every transform of a wave shares one power of two). Larger N spread a transform over several
+// waves and use workgroup barriers.
 template <int LOGN, int PREC, bool ToLds, bool FromBuf, class Load, class Sink>
 __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const float2* __restrict__ tw, Load load,
                                                   Sink sink, SplitCtx sp) {
@@ -267,12 +260,7 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
   const DftOperands<PREC> F = dft16_operands<PREC>(sp.ops);
   const int lane = threadIdx.x & 63, n = lane & 31, g = lane >> 5, w = threadIdx.x >> 6;
   const int total = ntrans * NB;
-  constexpr bool WAVE_LOCAL = NB <= 64;
-  // orders the stages: within the wave, or over the workgroup
-  auto stage_sync = [] {
-    if constexpr (WAVE_LOCAL) wave_lds_order();
-    else __syncthreads();
-  };
+  constexpr bool WAVE_LOCAL = NB <= 64;   // T == NB: stage_sync<T> orders within the wave
 
   // The butterfly of batch h of this lane, and whether it exists. A lane without one gets
   // butterfly 0 (which always exists), so its loads need no branch (their values are discarded):
@@ -344,7 +332,7 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
     int e;
     if constexpr (WAVE_LOCAL) {
       e = f16_scale_exponent(wave_max_abs(m));
-      wave_lds_order();                  // every load of buf is done before the in-place stores
+      stage_sync<T>();                   // every load of buf is done before the in-place stores
     } else {
       e = f16_scale_exponent(block_max_abs(m, sp.s_max));   // also: every load of buf is done
     }
@@ -355,7 +343,7 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
 #pragma unroll
       for (int i = 0; i < 8; ++i) x[h][i] = cscale(x[h][i], s);
   } else {
-    stage_sync();                        // every load of buf is done before the in-place stores
+    stage_sync<T>();                        // every load of buf is done before the in-place stores
   }
   using One = std::integral_constant<int, 1>;
   constexpr bool ONE_STAGE = (P::NST == 1);
@@ -368,7 +356,7 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
     if constexpr (ToLds) __syncthreads();
     return;
   } else {
-    stage_sync();
+    stage_sync<T>();
     // ---- later stages
     auto mfma_stage = [&](auto ns_tag, auto last_tag) {
       constexpr int NS = decltype(ns_tag)::value;
@@ -384,7 +372,7 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
           x[h][i] = cmul(v, stage_twiddle<NS>(tw, k, q));
         }
       }
-      stage_sync();
+      stage_sync<T>();
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const f32x16 r = dft16_mfma<PREC>(x[h], F);
@@ -401,7 +389,7 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
         stage_load_lds<N, 16, T, RAD>(v, buf + c * NP, lt);
         stage_compute<N, 16, T, NS, RAD>(v, lt, tw);
       }
-      if constexpr (ToLds) stage_sync();
+      if constexpr (ToLds) stage_sync<T>();
       if (active) {
         constexpr int Q = 16 / RAD;
 #pragma unroll
@@ -428,7 +416,7 @@ __device__ __forceinline__ void fft_inverse_split(float2* buf, int ntrans, const
       }
     } else {
       mfma_stage(S16{}, B0{});
-      stage_sync();
+      stage_sync<T>();
       using S256 = std::integral_constant<int, 256>;
       if constexpr (P::R2 == 16) {
         mfma_stage(S256{}, B1{});
