@@ -206,12 +206,11 @@ struct ConvLayout {
 ConvLayout conv_layout(size_t Q, int P, int B, int logn, int width, size_t h_images) {
   const size_t N = size_t(1) << logn;
   const int S = blink::conv_strip_width(logn);
-  const size_t nstrips = (N / 2) / (size_t)S;
   ConvLayout L;
-  L.rec_stride = blink::conv_records_per_pair(B, width, S);
+  L.rec_stride = blink::conv_records_per_pair(B, width, S, logn);
   Carve c;
   L.bins.plc = c.take(Q, (size_t)L.rec_stride * 16);
-  L.bins.off = c.take(Q, (nstrips + 1) * sizeof(int));
+  L.bins.off = c.take(Q, ((size_t)blink::conv_bins_per_pair(logn, S) + 1) * sizeof(int));
   L.bins.kept = c.take(Q, sizeof(int));
   L.bins.occ = c.take(Q, (size_t)P * sizeof(int));
   L.bins.ext = c.take(Q, sizeof(int));

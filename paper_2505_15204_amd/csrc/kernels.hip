@@ -102,15 +102,22 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_conv(BinArgs a, ConvSpec cs
   const int N = 1 << a.logn;
   const int nstrips = (N / 2) >> a.log_strip;
   const double k = (a.freq[c] / kSpeedOfLight) * ((double)N * a.pixel_scale);
+  const int log_band = conv_log_band(a.logn), nb = N >> log_band;
   bin_visibilities_conv(a.uvw + (size_t)t * a.B * 3, a.flags ? a.flags + (size_t)tc * a.B : nullptr, a.B, k, a.logn,
-                        a.log_strip, cs, reinterpret_cast<ConvRec*>(a.plc) + (size_t)tcl * rec_stride,
-                        a.strip_off + (size_t)tcl * (nstrips + 1), a.n_kept + tcl, a.n_out ? a.n_out + tc : nullptr,
-                        sh, a.ext ? a.ext + tcl : nullptr);
+                        a.log_strip, log_band, cs, reinterpret_cast<ConvRec*>(a.plc) + (size_t)tcl * rec_stride,
+                        a.strip_off + (size_t)tcl * (nstrips * nb + 1), a.n_kept + tcl,
+                        a.n_out ? a.n_out + tc : nullptr, sh, a.ext ? a.ext + tcl : nullptr);
 }
 
-int conv_records_per_pair(int B, int width, int min_strip) {
-  return 2 * B * ((width + min_strip - 1) / min_strip + 2);
+// A placement's W < N/2 tap columns reach at most ceil(W / S) + 1 strips and its W <= 16 tap rows
+// at most two 16-row bands; with bands every bin holds at most three padding records.
+int conv_records_per_pair(int B, int width, int min_strip, int logn) {
+  const bool banded = conv_log_band(logn) < logn;
+  return 2 * B * ((width + min_strip - 1) / min_strip + 2) * (banded ? 2 : 1) +
+         (banded ? 3 * conv_bins_per_pair(logn, min_strip) : 0);
 }
+
+int conv_bins_per_pair(int logn, int strip) { return ((1 << logn) / 2 / strip) * ((1 << logn) >> conv_log_band(logn)); }
 
 hipError_t launch_bin_conv(const BinArgs& a, ConvParams cp, int rec_stride, hipStream_t s) {
   if (a.Q <= 0) return hipSuccess;

@@ -91,8 +91,10 @@ __global__ __launch_bounds__(fft_block(S * FftPlan<LOGN>::T, PREC)) void k_grid_
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, NP = P::NP;
   constexpr int NT = fft_block(S * FftPlan<LOGN>::T, PREC), TW = tw_size(LOGN);
+  constexpr int NB = N >> conv_log_band(LOGN);   // row bands per column
   __shared__ float2 sbuf[S * NP];
   __shared__ float2 stw[TW];
+  __shared__ int s_boff[NB + 1];
   __shared__ unsigned s_max;
   const int slot = blockIdx.x, img = a.img0 + slot, strip = blockIdx.y;
   const int tcl = img / a.P;
@@ -100,10 +102,10 @@ __global__ __launch_bounds__(fft_block(S * FftPlan<LOGN>::T, PREC)) void k_grid_
   // strips past the column extent receive no tap; the row pass reads their columns as zero
   if (a.ext && strip >= a.ext[tcl] / S) return;   // uniform over the workgroup
   for (int i = threadIdx.x; i < TW; i += NT) stw[i] = twg[i];   // visible after the task's first barrier
-  const int* so = a.strip_off + (size_t)tcl * (nstrips + 1);
+  const int* so = a.strip_off + (size_t)tcl * (nstrips * NB + 1) + (size_t)strip * NB;
   const ConvRec* rec = reinterpret_cast<const ConvRec*>(a.plc) + (size_t)tcl * a.rec_stride;
-  grid_colfft_conv_task<LOGN, S, PREC, NT>(a.vis + (size_t)img * a.B, rec, so[strip], so[strip + 1], strip,
-                                           a.shift != 0, cs, a.H + (size_t)slot * N * (N / 2), stw, sbuf,
+  grid_colfft_conv_task<LOGN, S, PREC, NT>(a.vis + (size_t)img * a.B, rec, so, s_boff, strip, a.shift != 0,
+                                           cs, a.H + (size_t)slot * N * (N / 2), stw, sbuf,
                                            SplitCtx{&s_max, a.dft_ops});
 }
 

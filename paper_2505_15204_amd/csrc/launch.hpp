@@ -103,7 +103,9 @@ struct ConvParams {
   double beta;
 };
 // Records per (t,c) pair the convolutional binning may write for strips of width >= min_strip.
-int conv_records_per_pair(int B, int width, int min_strip);
+int conv_records_per_pair(int B, int width, int min_strip, int logn);
+// (column strips) x (row bands) of one (t,c) pair's convolutional binning (its offsets hold one more).
+int conv_bins_per_pair(int logn, int strip);
 hipError_t launch_bin_conv(const BinArgs& a, ConvParams cp, int rec_stride, hipStream_t s);
 // Fused convolutional gridding + column FFT (strip width: the largest compiled for natural weighting).
 hipError_t launch_grid_colfft_conv(const ColArgs& a, int n_img, ConvParams cp, int prec, const float2* tw,
