@@ -122,6 +122,66 @@ def path_bytes_per_image(spec, ext=None):
     return round(16 * N * (N / 2 if ext is None else ext) + 4 * N * N + 8 * B + B // P)
 
 
+def conv_unit_bytes(torch, d, spec, width, steps, strip=16, band=16):
+    """Algorithmic bytes of the convolutional path (kernel support `width` cells), per unit.
+
+    Counted from the workload's geometry over the (t, c) pairs of `steps` steps, with the keep
+    rule and tap rule of the binning: a kept visibility's two placements reach the columns
+    ceil(+-x - W/2) .. + n_u - 1 and the rows likewise (n = min(W, ceil(W/2 - d0)) taps).
+    bin:         per pair, the flags (1 B per baseline), the shared u, v (16 B per baseline over C
+                 pairs), one 16-byte record per (placement, column strip of `strip` columns, row
+                 band of `band` rows) it reaches, and the (strips x bands + 1) 4-byte offsets;
+    grid_colfft: per image, write the half-spectrum columns up to the last tap column (8 N ext B)
+                 and read one record (16 B) and one visibility (8 B) per record;
+    row_fft:     per image, read those columns and write the image (8 N ext + 4 N^2 B).
+    Also returns the mean column extent."""
+    N, B, C, W = spec.grid_n, spec.B, spec.C, width
+    h = W / 2.0
+    half = N // 2
+    nstrips, nbands = half // strip, N // band
+    recs, exts = [], []
+    for i in range(steps):
+        t = i % spec.T
+        k = d["freq_hz"] * (N * spec.pixel_scale / SPEED_OF_LIGHT)                 # [C]
+        x = d["uvw_m"][t, :, 0][None, :] * k[:, None]                               # [C][B] FP64
+        y = d["uvw_m"][t, :, 1][None, :] * k[:, None]
+        kept = (torch.round(x).abs() < half) & (torch.round(y).abs() < half) & (d["flags"][t] == 0)
+        n_rec = torch.zeros(C, dtype=torch.float64, device=x.device)
+        last = torch.zeros(C, dtype=torch.float64, device=x.device)
+        for sgn in (1.0, -1.0):
+            xs, ys = sgn * x, sgn * y
+            ju0 = torch.ceil(xs - h)
+            ju0 = torch.where(ju0 - xs > -h, ju0, ju0 + 1)
+            jv0 = torch.ceil(ys - h)
+            jv0 = torch.where(jv0 - ys > -h, jv0, jv0 + 1)
+            nu = torch.clamp(torch.ceil(h - (ju0 - xs)), max=W)
+            nv = torch.clamp(torch.ceil(h - (jv0 - ys)), max=W)
+            ju0, jv0, nu, nv = ju0.long(), jv0.long(), nu.long(), nv.long()
+            strips = torch.zeros_like(ju0)
+            prev = torch.full_like(ju0, -2)
+            for j in range(W):
+                col = (ju0 + j) % N
+                s_j = torch.where(col < half, col // strip, torch.where(col == half, torch.zeros_like(col), -1))
+                s_j = torch.where(j < nu, s_j, torch.full_like(s_j, -1))
+                strips += ((s_j >= 0) & (s_j != prev)).long()
+                prev = s_j
+                in_half = (j < nu) & (col < half)        # the Nyquist column is packed into column 0
+                last = torch.maximum(last, torch.where(kept & in_half, col + 1, torch.zeros_like(col)).amax(dim=1).double())
+            b0 = (jv0 % N) // band
+            b1 = ((jv0 + nv - 1) % N) // band
+            bands = torch.where(nv > 0, 1 + (b1 != b0).long(), torch.zeros_like(nv))
+            n_rec += torch.where(kept, strips * bands, torch.zeros_like(strips)).sum(dim=1).double()
+        recs.append(n_rec.mean().item())
+        exts.append(last.mean().item())
+    R, ext = sum(recs) / len(recs), sum(exts) / len(exts)
+    hb = 8 * N * ext
+    return {
+        "grid_colfft": ("image", round(hb + 24 * R)),        # each image reads all of its pair's records
+        "row_fft": ("image", round(hb + 4 * N * N)),
+        "bin": ("pair", round(B + (16 * B) // C + 16 * R + 4 * (nstrips * nbands + 1))),
+    }, ext
+
+
 # The last-level cache (AMD Infinity Cache, "MALL") of the MI355X: 256 MB in front of HBM.
 MALL_BYTES = 256 * 10**6
 
@@ -626,11 +686,13 @@ def main():
                                            workspace=cws)
             ms = timed(torch, cstep, fs, 2)
             cprof, _ = profiled(ctx, torch, cstep, fs)
-            # the convolutional path transforms every column of the half spectrum
-            ck = kernel_table(cprof, {"image": fs * C * P, "pair": fs * C}, kernel_unit_bytes(spec))
+            # byte model from the workload's records and its column extent (the last tap column)
+            cbytes, cext = conv_unit_bytes(torch, d, spec, 8, fs)
+            ck = kernel_table(cprof, {"image": fs * C * P, "pair": fs * C}, cbytes)
             v = fs * C * P / (ms / 1e3)
             forms["vcs-1024"]["conv_w8_fp32"] = {"images_per_s": round(v, 1), "vs_fp32": round(v / value, 4),
                                                  "kernel": "exponential of semicircle, W = 8, beta = 18.4",
+                                                 "column_extent": {"mean_columns": round(cext, 1), "of": N // 2},
                                                  "kernels": {k: ck[k] for k in ("bin", "grid_colfft", "row_fft") if k in ck}}
             log(f"conv W=8: {v:.0f} images/s ({v / value:.3f} x nearest-cell FP32)")
             del cws
