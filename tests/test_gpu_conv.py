@@ -61,7 +61,9 @@ CASES = [
     ("small-64-w4", synth.Spec("small-64", 11, 30, 1, 2, np.array([140.0e6, 171.25e6]), 64, 4.5e-4, 3, 0.15), 4, 9.2),
     ("small-32-w6", synth.Spec("small-32", 12, 24, 2, 1, np.array([150.0e6]), 32, 9e-4, 3, 0.1), 6, 13.8),
     ("small-64-w1-beta0", synth.Spec("small-64", 13, 30, 1, 1, np.array([155.5e6]), 64, 4.5e-4, 3, 0.1), 1, 0.0),
+    ("mid-128-w5", synth.Spec("mid-128", 14, 40, 1, 2, np.array([140.0e6, 160.0e6]), 128, 3.0e-4, 3, 0.1), 5, 11.5),
     ("tiny-256-w8", synth.spec_tiny(), 8, 18.4),
+    ("mid-512-w8", synth.Spec("mid-512", 15, 60, 1, 1, np.array([170.0e6]), 512, 4.0e-4, 3, 0.1), 8, 18.4),
     ("vcs-1024-1x2x2-w8", synth.spec_vcs(T=1, C=2, P=2), 8, 18.4),
     ("vcs-1024-1x1x1-w16", synth.spec_vcs(T=1, C=1, P=1), 16, 36.8),
     ("phase2-2048-1x1x2-w7", synth.Spec("phase2-2048", 3, 144, 1, 2, np.array([185.005e6]), 2048, 0.75 * synth.ARCMIN,
