@@ -181,20 +181,13 @@ __global__ __launch_bounds__(fft_block(TPB * FftPlan<LOGN>::T, PREC)) void k_row
                                                                                       const float2* __restrict__ twg) {
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, NP = P::NP;
-  constexpr int NT = fft_block(TPB * FftPlan<LOGN>::T, PREC), TW = tw_size(LOGN);
-  // The FP32 form reads its twiddles from the global table (cached in L1): without a copy in LDS
-  // a workgroup of TPB <= 4 transforms leaves room for four workgroups per compute unit. The
-  // split forms keep the table in LDS.
-  constexpr bool TW_LDS = PREC != kPrecFp32;
+  // Every form reads its twiddles from the global table (cached in L1): without a copy in LDS a
+  // workgroup of a few transforms leaves room for many workgroups per compute unit (the split
+  // forms, with their LDS copy, took 3.9 ms per 1536 images at 1024^2; 3.7 ms without).
   __shared__ float2 sbuf[TPB * NP];
-  __shared__ float2 stw_lds[TW_LDS ? TW : 1];
   __shared__ unsigned s_max;
   const int slot = blockIdx.x, img = a.img0 + slot;
   const float2* stw = twg;
-  if constexpr (TW_LDS) {
-    for (int i = threadIdx.x; i < TW; i += NT) stw_lds[i] = twg[i];   // visible after row_task's barrier
-    stw = stw_lds;
-  }
   const double W = image_weight(a, img);
   if (a.weight_sum && blockIdx.y == 0 && threadIdx.x == 0) a.weight_sum[img] = W;
   const int ext = a.ext ? a.ext[img / a.P] : N / 2;

@@ -49,10 +49,7 @@ __global__ __launch_bounds__(fft_block(TPB * FftPlan<LOGN>::T, PREC)) void k_chu
                                                                                         const float2* __restrict__ twg) {
   using P = FftPlan<LOGN>;
   constexpr int N = P::N, NP = P::NP;
-  constexpr int NT = fft_block(TPB * FftPlan<LOGN>::T, PREC), TW = tw_size(LOGN);
-  constexpr bool TW_LDS = PREC != kPrecFp32;   // as in k_row_c2r
-  __shared__ float2 sbuf[TPB * NP];
-  __shared__ float2 stw_lds[TW_LDS ? TW : 1];
+  __shared__ float2 sbuf[TPB * NP];        // twiddles from the global table, as in k_row_c2r
   __shared__ unsigned s_max;
   const int4 c = a.chunks[chunk];
   const int slot = blockIdx.x;
@@ -60,10 +57,6 @@ __global__ __launch_bounds__(fft_block(TPB * FftPlan<LOGN>::T, PREC)) void k_chu
   const int q = c.y + slot;
   const int img = a.order[q];
   const float2* stw = twg;
-  if constexpr (TW_LDS) {
-    for (int i = threadIdx.x; i < TW; i += NT) stw_lds[i] = twg[i];   // visible after row_task's barrier
-    stw = stw_lds;
-  }
   const double W = a.weighting ? (double)a.occ[q] : 2.0 * (double)a.kept[q];
   if (a.weight_sum && blockIdx.y == 0 && threadIdx.x == 0) a.weight_sum[img] = W;
   row_task<LOGN, TPB, PREC>(a.H + (size_t)slot * N * (N / 2), blockIdx.y, inverse_weight(W),
