@@ -317,19 +317,24 @@ __device__ __forceinline__ void scatter_strip_conv_waves(const ConvRec* __restri
 // in registers. A band whose groups all lie in the wave's range is added to the LDS strip with a
 // plain read-add-write when the wave leaves it; the first and the last band of the range can
 // also hold groups of other waves, so their tiles stay in registers until the loop is over and
-// are then added by one wave after another, with a workgroup barrier between turns (LDS float
-// atomics, the alternative, cost several times a plain access and serialise where waves meet on
-// a busy band). The (-1)^(ku + kv) modulation is a sign per cell, applied there. s_boff (LDS)
-// holds the strip's NB + 1 band offsets into rec. Every thread of the workgroup calls this.
+// are then added in turns with a workgroup barrier between turns: the waves whose ranges reach a
+// band add their tiles of it in the order of their ranges (a wave's last band, when it differs
+// from its first, begins inside its range, so the wave is that band's first contributor), and
+// there are as many turns as the most waves that share one band (LDS float atomics, the
+// alternative, cost several times a plain access and serialise where waves meet on a busy band).
+// The (-1)^(ku + kv) modulation is a sign per cell, applied there. s_boff (LDS) holds the strip's
+// NB + 1 band offsets into rec and, at s_boff[NB + 1], the turn count (zero on entry, visible).
+// Every thread of the workgroup calls this.
 constexpr int kConvBatch = 8;                  // groups whose records are requested together
 
 template <int NB>
 __device__ __forceinline__ void set_conv_bands(const int* __restrict__ so, int* s_boff) {
   for (int i = threadIdx.x; i <= NB; i += blockDim.x) s_boff[i] = so[i];
+  if (threadIdx.x == 0) s_boff[NB + 1] = 0;   // the tile turns of spread_strip_conv_mfma
 }
 
 template <int LOGN, int S, int NT>
-__device__ __forceinline__ void spread_strip_conv_mfma(const ConvRec* __restrict__ rec, const int* s_boff,
+__device__ __forceinline__ void spread_strip_conv_mfma(const ConvRec* __restrict__ rec, int* s_boff,
                                                        const float2* __restrict__ V, int strip, bool modulate,
                                                        ConvSpec cs, float2* sbuf) {
   typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -433,12 +438,28 @@ __device__ __forceinline__ void spread_strip_conv_mfma(const ConvRec* __restrict
       }
     }
   }
-  // the first and the last band's tiles (acc holds the last), one wave at a time
-  for (int w = 0; w < NW; ++w) {
-    __syncthreads();
-    if (wave == w && active) {
-      if (first != last) flush(first, acc_first);
-      flush(last, acc);
+  // The first and the last band's tiles (acc holds the last). The turn of the first band's tile is
+  // the number of earlier waves whose ranges reach that band (ranges are in wave order).
+  int turn = 0;
+  if (active) {
+    const int gs = (s_boff[first] - base) >> 2;      // the band's first group
+    for (int v = 0; v < wave; ++v) {
+      const int a0 = (int)(((long long)ngroups * v) / NW), a1 = (int)(((long long)ngroups * (v + 1)) / NW);
+      if (a0 < a1 && a1 > gs) ++turn;
+    }
+    if (lane == 0) atomicMax(&s_boff[NB + 1], turn + 1);
+  }
+  __syncthreads();
+  const int turns = s_boff[NB + 1];
+  for (int t = 0; t < turns; ++t) {
+    if (t > 0) __syncthreads();
+    if (active) {
+      if (first != last) {
+        if (t == turn) flush(first, acc_first);
+        if (t == 0) flush(last, acc);
+      } else if (t == turn) {
+        flush(last, acc);
+      }
     }
   }
 }
@@ -447,7 +468,7 @@ __device__ __forceinline__ void spread_strip_conv_mfma(const ConvRec* __restrict
 // One strip of S half-spectrum columns of one image: zero the LDS strip, spread the strip's
 // records, transform the columns and store the strip into Hi (column 0 keeps the packed Nyquist
 // column). NT is the workgroup size. so (global) holds the strip's NB + 1 band
-// offsets into rec (NB = 1: one band); s_boff is NB + 1 ints of LDS.
+// offsets into rec (NB = 1: one band); s_boff is NB + 2 ints of LDS.
 template <int LOGN, int S, int PREC, int NT>
 __device__ __forceinline__ void grid_colfft_conv_task(const float2* __restrict__ V, const ConvRec* __restrict__ rec,
                                                       const int* __restrict__ so, int* s_boff, int strip, bool shift,

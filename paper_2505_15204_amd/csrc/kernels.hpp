@@ -94,7 +94,7 @@ __global__ __launch_bounds__(fft_block(S * FftPlan<LOGN>::T, PREC)) void k_grid_
   constexpr int NB = N >> conv_log_band(LOGN);   // row bands per column
   __shared__ float2 sbuf[S * NP];
   __shared__ float2 stw[TW];
-  __shared__ int s_boff[NB + 1];
+  __shared__ int s_boff[NB + 2];
   __shared__ unsigned s_max;
   const int slot = blockIdx.x, img = a.img0 + slot, strip = blockIdx.y;
   const int tcl = img / a.P;
