@@ -303,8 +303,8 @@ __device__ __forceinline__ void scatter_strip_conv_waves(const ConvRec* __restri
   }
 }
 
-// Matrix-core spreading of one strip (S = 16 CT columns) from records binned by row band of 16
-// rows. The cells of band beta (rows 16 beta .. 16 beta + 15) receive the sum over the band's
+// Matrix-core spreading of one strip (S a multiple of 16 columns) from records binned by row
+// band of 16 rows. The cells of band beta (rows 16 beta .. 16 beta + 15) receive the sum over the band's
 // records r of wv_r(kv) * V_r wu_r(ku): the product of a 16 x R matrix of row weights and an
 // R x S matrix of column-weighted visibilities, evaluated four records at a time with
 // v_mfma_f32_16x16x4_f32 (FP32 products and sums) for the real and the imaginary parts. Lane
