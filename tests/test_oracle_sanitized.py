@@ -1,6 +1,6 @@
 """CPU test: the oracle built with AddressSanitizer and UndefinedBehaviorSanitizer runs every pin
 cleanly (no out-of-bounds access, use after free, signed overflow, misaligned access, ... in the
-C code the GPU path is judged against).
+C code the GPU path is compared with).
 
 The instrumented library is loaded into a child Python process with the ASan runtime preloaded
 (a sanitized shared object cannot be loaded into an uninstrumented interpreter otherwise);
