@@ -925,8 +925,9 @@ blink_status blink_image_batch_conv(blink_ctx ctx, const blink_cf32* vis, const 
   const size_t n_tc = (size_t)T * C;
   if (n_tc == 0) return BLINK_OK;
   const auto& plan = ctx->plan[logn][BLINK_WEIGHT_NATURAL][precision];
-  // The nearest-cell plan's group size, capped so that the group's half spectra (every column:
-  // the convolutional path does not skip any) stay within 192 MiB of the last-level cache.
+  // The nearest-cell plan's group size, capped at 192 MiB of full half spectra (48 images at
+  // 1024^2: faster for this path than the nearest-cell plan's 64, whose column kernel per image
+  // is shorter).
   const size_t h_bytes = (size_t(1) << (2 * logn - 1)) * sizeof(float2);
   const size_t cache_group = ((size_t)192 << 20) / h_bytes > 0 ? ((size_t)192 << 20) / h_bytes : 1;
   size_t want = plan.group > 0 ? (size_t)plan.group : kMaxGroupImages;
