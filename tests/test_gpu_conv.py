@@ -177,3 +177,34 @@ def test_conv_beats_nearest_cell_against_direct_transform(torch, ctx):
     e_near = np.abs(centre(near - direct)).max() / np.abs(direct).max()
     say(f"  centre max error: conv {e_conv:.2e}, nearest {e_near:.2e}")
     assert e_conv <= 1e-5 and e_near > 1e-2
+
+
+@pytest.mark.parametrize("N,width", [(1024, 8), (256, 16)])
+def test_conv_busy_band_shared_by_many_waves(torch, ctx, N, width):
+    """Every visibility on a few rows around v = 0 (and its mirror) puts almost all records of the
+    strips into one or two row bands, so a band's records span most waves of the column workgroup
+    and its tile is added over many ordered turns. Compared with the oracle as the other cases."""
+    spec = synth.Spec(f"busy-{N}", 16, 60, 1, 2, np.array([150.0e6]), N, 3.0e-4, 3, 0.0)
+    base = synth.make_problem(spec)
+    rng = np.random.default_rng(1606)
+    k = (spec.freq_hz[0] / synth.C_LIGHT) * (N * spec.pixel_scale)
+    uvw = base.uvw_m.copy()
+    uvw[:, :, 0] = rng.uniform(-0.45 * N, 0.45 * N, size=uvw.shape[:2]) / k
+    uvw[:, :, 1] = rng.uniform(-1.5, 1.5, size=uvw.shape[:2]) / k
+    prob = synth.Problem(spec, uvw, base.freq_hz, base.flags, base.vis)
+    ref = oracle.image_batch_conv(prob.vis, prob.flags, prob.uvw_m, prob.freq_hz, N, spec.pixel_scale, width,
+                                  2.3 * width)
+    say(f"conv busy band N={N} W={width}: {spec.B} baselines on |v k| < 1.5")
+    vis, flags, uvw_d, freq = to_device(torch, prob)
+    res = ctx.blink_image_batch_conv(vis, flags, uvw_d, freq, N, spec.pixel_scale, width, 2.3 * width)
+    torch.cuda.synchronize()
+    assert np.array_equal(res["weight_sum"].cpu().numpy(), ref["weight_sum"])
+    img = res["images"].cpu().numpy()
+    assert np.isfinite(img).all()
+    c = oracle.conv_correction(N, width, 2.3 * width, True)
+    back = np.outer(c, c) / c.max() ** 2
+    for idx in np.ndindex(spec.T, spec.C, spec.P):
+        ec = rel_l2(centre(img[idx]), centre(ref["images"][idx]))
+        ef = rel_l2(img[idx] * back, ref["images"][idx] * back)
+        say(f"  {idx}: centre rel_l2={ec:.3e} full (corrected back) rel_l2={ef:.3e}")
+        assert ec <= CENTRE_TOL and ef <= FULL_TOL, (idx, ec, ef)
