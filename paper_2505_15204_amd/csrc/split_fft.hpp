@@ -220,11 +220,20 @@ __device__ __forceinline__ float block_max_abs(float m, unsigned* s_max) {
   return __uint_as_float(*s_max);
 }
 
-// Largest |re| or |im| over the wave (no LDS word, no barrier).
+// Largest |re| or |im| over the wave (no LDS word, no barrier): m >= 0, so its bits order as an
+// unsigned integer. A DPP reduction leaves the row maxima in lanes 15, 31, 47, 63 (row_shr 1, 2,
+// 4 and 8, the last two on the upper banks), then row_bcast 15 and 31 fold the rows into lane 63,
+// which is read back as a scalar. Lanes whose DPP source is masked keep their own value.
 __device__ __forceinline__ float wave_max_abs(float m) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-  return m;
+  int v = __float_as_int(m);
+  auto step = [](int x, int y) { return (int)max((unsigned)x, (unsigned)y); };
+  v = step(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+  v = step(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+  v = step(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xe, false));   // row_shr:4
+  v = step(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xf, 0xc, false));   // row_shr:8
+  v = step(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+  v = step(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+  return __int_as_float(__builtin_amdgcn_readlane(v, 63));
 }
 
 // Power of two that brings a maximum magnitude mx into [32, 64).
